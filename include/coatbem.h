@@ -1,0 +1,206 @@
+/*
+ * libcoatbem -- boundary element method for the frictionless normal contact
+ * of a rigid indenter with an elastic layer (h, E1, nu1) bonded to an
+ * elastic half-space (E2, nu2), non-adhesive and adhesive, on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Li, Pohrt, Lyashenko, Popov, "Boundary Element Method for
+ * non-adhesive and adhesive contacts of a coated elastic half-space",
+ * arXiv:1807.01885.  Section, equation and figure numbers below refer to it.
+ *
+ * Conventions shared by every entry point
+ *   - Grid (Sec. 2, Fig. 2): an L x L square of N x N cells, Delta = L/N.
+ *     Arrays are N*N, row-major, element (i, j) at i*N + j, row i = y,
+ *     column j = x; the centre of cell (i, j) is ((j-N/2)Delta, (i-N/2)Delta).
+ *   - Pressure p > 0 is compressive (sigma_zz = -p at z = 0, condition (c));
+ *     u is the surface displacement into the body; f >= 0 is the indenter
+ *     profile; d is the rigid approach (positive into the body); the gap is
+ *     g = f - d + u; the total force is F = Delta^2 * sum(p).
+ *   - Element type of every caller array (p, u, f, state) is the plan's
+ *     precision: double for CB_FP64, float for CB_FP32.  Masks are uint8,
+ *     1 = in contact.
+ *   - Every array pointer is a DEVICE pointer on the plan's device unless
+ *     the name says _host.  The caller owns every array; the library never
+ *     frees or retains caller memory beyond the call.  The library owns the
+ *     plan, its tables and its workspace.
+ *   - Work is enqueued on the plan's stream.  cb_apply_K is asynchronous.
+ *     The solve and sweep calls synchronise the stream before they fill
+ *     their host result structs and return.
+ *   - Errors are returned as negative status codes, never thrown across
+ *     the ABI; cb_last_error() gives text for the calling thread.  A plan
+ *     is not thread-safe; distinct plans are.
+ */
+#ifndef COATBEM_H
+#define COATBEM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cb_plan_s* cb_plan;
+
+enum {
+  CB_OK = 0,
+  CB_E_INVALID = -1,     /* bad argument (range, null pointer, size) */
+  CB_E_NOMEM = -2,       /* device or host allocation failed */
+  CB_E_DEVICE = -3,      /* a HIP call failed */
+  CB_E_NOCONV = -4,      /* iteration limit reached before the tolerance */
+  CB_E_NONFINITE = -5,   /* NaN/Inf met in the input or during iteration */
+  CB_E_STATE = -6,       /* plan in an unusable state */
+  CB_E_UNSUPPORTED = -7  /* combination not provided */
+};
+
+enum { CB_FP64 = 0, CB_FP32 = 1 };
+enum { CB_DC_BZ = 0, CB_DC_ZERO = 1 };
+
+/* Plan options; a NULL pointer selects every default. */
+typedef struct {
+  int precision;   /* CB_FP64 (default) or CB_FP32: FP32 convolution and
+                      FP32 fields with FP64 reductions and scalars */
+  int dc_mode;     /* CB_DC_BZ (default): the k = 0 value of the transfer
+                      function makes the frequency sum equal its integral
+                      over the Brillouin zone [-pi/Delta, pi/Delta]^2;
+                      CB_DC_ZERO: no DC component (Eq. 11 taken literally) */
+  void* stream;    /* hipStream_t to enqueue on; NULL = the null stream */
+  int autotune;    /* 1: time the available FFT launch shapes once for this
+                      (N, precision) and keep the fastest (cached in
+                      tune_cache if set); 0 (default): built-in choice */
+  const char* tune_cache; /* path of the autotune cache file, or NULL */
+} cb_plan_opts;
+
+/* Solve options; a NULL pointer selects every default. */
+typedef struct {
+  double tol;        /* relative residual target; <= 0: 1e-10 (FP64), 1e-6 (FP32) */
+  int max_iter;      /* conjugate-gradient iteration limit per solve; <= 0: 20000 */
+  int chunk;         /* iterations run on the device between host checks of
+                        the convergence flag; <= 0: 16 */
+  int init;          /* 0: cold start; 1: the caller's p_io is the initial guess */
+  double attach_tol; /* adhesive: a cell outside the contact attaches when
+                        its gap is below -attach_tol (length); < 0: 1e-12 L
+                        (FP64), 1e-6 L (FP32) */
+  int max_rounds;    /* adhesive detach/attach rounds per step; <= 0: 10000 */
+} cb_solve_opts;
+
+/* Per-solve (or per-step) outcome, filled on the host. */
+typedef struct {
+  int status;        /* CB_OK or a CB_E_* code for this solve / step */
+  int iters;         /* conjugate-gradient iterations (all rounds) */
+  int rounds;        /* adhesive detach/attach rounds (0 if non-adhesive) */
+  double resid;      /* final relative residual on the contact set */
+  double F;          /* total force Delta^2 sum p */
+  double d;          /* rigid approach (the one found, for force control) */
+  double area;       /* contact area Delta^2 |S| */
+  double U_el;       /* elastic energy 1/2 Delta^2 sum p u */
+  double U_ad;       /* adhesion energy -dgamma * area */
+  double ms;         /* wall time of the call on the host, milliseconds */
+} cb_result;
+
+/* Read-only plan facts. */
+typedef struct {
+  int N, M;          /* grid and padded FFT size, M = 2N */
+  int precision, dc_mode;
+  double L, dx, h, E1, nu1, E2, nu2, dgamma;
+  double E1s, E2s;   /* reduced moduli E/(1-nu^2), Eq. 4 */
+  double sigma_c;    /* Eq. 12 critical stress (0 when dgamma = 0) */
+  double k00;        /* self-influence: displacement of a cell per unit
+                        pressure on itself */
+  double dc;         /* the k = 0 transfer value used */
+  int validity_warning; /* 1 when dgamma > 0 and h < 5 Delta: Eq. 12 assumes
+                        Delta << h (Sec. 2 after Eq. 12) */
+  size_t workspace_bytes;
+} cb_plan_info;
+
+/*
+ * cb_plan_create -- build the operator u = K p for one grid and material.
+ *   Eq. 9-11 (Sec. 2): the transfer function is evaluated in FP64 from the
+ *   normalised form of Eq. 9-10 at k = sqrt(kx^2 + ky^2) on the 2N-padded
+ *   frequency grid, with the DC value of opts->dc_mode; sigma_c from Eq. 12.
+ *   N: power of two, 16 <= N <= 2048.  L > 0, h >= 0, E1, E2 > 0,
+ *   0 <= nu < 0.5, dgamma >= 0 (0: non-adhesive).
+ *   On success *out owns device tables and workspace (see cb_plan_info);
+ *   on failure *out is NULL and a CB_E_* code is returned.
+ */
+int cb_plan_create(cb_plan* out, int N, double L, double h, double E1,
+                   double nu1, double E2, double nu2, double dgamma,
+                   const cb_plan_opts* opts);
+
+/* Release a plan and everything it owns.  NULL is accepted (no-op). */
+int cb_plan_destroy(cb_plan plan);
+
+/* Copy the plan facts into *info (host). */
+int cb_plan_get_info(cb_plan plan, cb_plan_info* info);
+
+/* Copy the FP64 transfer table T[a][b] = K^(Delta_k sqrt(a^2 + b^2)),
+ * a, b in [0, N] ((N+1)^2 doubles, host memory, a row-major), DC at [0][0],
+ * WITHOUT the 1/M^2 inverse-FFT factor the device copy carries. */
+int cb_plan_get_table(cb_plan plan, double* table_host);
+
+/*
+ * cb_transfer_table -- the same FP64 table as cb_plan_get_table, computed on
+ * the host without a device or a plan (Eq. 9-11 and the DC rule of
+ * dc_mode).  Arguments as cb_plan_create; table_host: (N+1)^2 doubles.
+ * k00_host (nullable): the self-influence sum(T)/M^2 over the full grid.
+ */
+int cb_transfer_table(int N, double L, double h, double E1, double nu1,
+                      double E2, double nu2, int dc_mode, double* table_host,
+                      double* k00_host);
+
+/* Change the stream later calls are enqueued on (hipStream_t). */
+int cb_plan_set_stream(cb_plan plan, void* stream);
+
+/*
+ * cb_apply_K -- u = K p, Eq. 1 evaluated as Eq. 11 on the zero-padded
+ *   (2N)^2 grid: real 2-D FFT of p, multiply by the transfer table,
+ *   inverse FFT, keep the N x N patch.  p, u: device N*N of the plan type;
+ *   u must not alias p.  Asynchronous on the plan stream.
+ */
+int cb_apply_K(cb_plan plan, const void* p, void* u);
+
+/*
+ * cb_solve_indent -- non-adhesive (dgamma = 0) or adhesive (dgamma > 0)
+ *   contact at prescribed rigid approach d.
+ *   Non-adhesive: the complementarity problem p >= 0, g >= 0, p g = 0 by
+ *   constrained conjugate gradients (Sec. 2 after Eq. 11).  Adhesive: start
+ *   from the geometric overlap {f <= d}, solve on the contact set, detach
+ *   boundary cells whose tension exceeds sigma_c (Eq. 12), attach
+ *   penetrating cells, repeat until nothing changes (Sec. 2, last
+ *   paragraph).
+ *   f: profile; p_io: output pressure (input guess when opts->init = 1);
+ *   mask_io: optional (NULL) output contact set.  res: host, required.
+ */
+int cb_solve_indent(cb_plan plan, const void* f, double d, void* p_io,
+                    unsigned char* mask_io, const cb_solve_opts* opts,
+                    cb_result* res);
+
+/*
+ * cb_solve_force -- non-adhesive contact at prescribed total force F > 0;
+ *   res->d returns the approach found.  Adhesive plans: CB_E_UNSUPPORTED.
+ */
+int cb_solve_force(cb_plan plan, const void* f, double F, void* p_io,
+                   unsigned char* mask_io, const cb_solve_opts* opts,
+                   cb_result* res);
+
+/*
+ * cb_sweep -- quasi-static displacement-controlled adhesive approach and
+ *   pull-off (Sec. 2, last paragraph): for each d_steps_host[k] attach
+ *   penetrating cells, then {solve on the contact set; detach boundary
+ *   cells with p < -sigma_c} until no change.  The state (p_state,
+ *   mask_state) is carried between steps and left in the caller's arrays,
+ *   so a sweep can be resumed by calling again with the same state.
+ *   Zero both for a fresh start.  per_step_host: nsteps results.
+ */
+int cb_sweep(cb_plan plan, const void* f, const double* d_steps_host,
+             int nsteps, void* p_state, unsigned char* mask_state,
+             const cb_solve_opts* opts, cb_result* per_step_host);
+
+/* Status text; cb_last_error: last error message of this thread. */
+const char* cb_status_string(int status);
+const char* cb_last_error(void);
+int cb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COATBEM_H */

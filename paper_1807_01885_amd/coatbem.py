@@ -1,0 +1,247 @@
+"""Thin ctypes binding of libcoatbem (argument marshalling only).
+
+The names mirror the C-ABI in include/coatbem.h.  Arrays are torch tensors
+on the GPU (device memory and streams come from PyTorch); every step of
+the computation runs in the library's HIP kernels.  If the built library
+is missing this module raises at import: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcoatbem.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python -m paper_1807_01885_amd.build` "
+        "(libcoatbem has no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+CB_OK = 0
+CB_E_INVALID = -1
+CB_E_NOMEM = -2
+CB_E_DEVICE = -3
+CB_E_NOCONV = -4
+CB_E_NONFINITE = -5
+CB_E_STATE = -6
+CB_E_UNSUPPORTED = -7
+CB_FP64 = 0
+CB_FP32 = 1
+CB_DC_BZ = 0
+CB_DC_ZERO = 1
+
+
+class cb_plan_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("dc_mode", ctypes.c_int),
+                ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int),
+                ("tune_cache", ctypes.c_char_p)]
+
+
+class cb_solve_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("chunk", ctypes.c_int), ("init", ctypes.c_int),
+                ("attach_tol", ctypes.c_double), ("max_rounds", ctypes.c_int)]
+
+
+class cb_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int),
+                ("rounds", ctypes.c_int), ("resid", ctypes.c_double),
+                ("F", ctypes.c_double), ("d", ctypes.c_double),
+                ("area", ctypes.c_double), ("U_el", ctypes.c_double),
+                ("U_ad", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class cb_plan_info(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("M", ctypes.c_int),
+                ("precision", ctypes.c_int), ("dc_mode", ctypes.c_int),
+                ("L", ctypes.c_double), ("dx", ctypes.c_double),
+                ("h", ctypes.c_double), ("E1", ctypes.c_double),
+                ("nu1", ctypes.c_double), ("E2", ctypes.c_double),
+                ("nu2", ctypes.c_double), ("dgamma", ctypes.c_double),
+                ("E1s", ctypes.c_double), ("E2s", ctypes.c_double),
+                ("sigma_c", ctypes.c_double), ("k00", ctypes.c_double),
+                ("dc", ctypes.c_double), ("validity_warning", ctypes.c_int),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_d = ctypes.c_double
+_i = ctypes.c_int
+_SIGS = {
+    "cb_plan_create": (_i, [ctypes.POINTER(_vp), _i, _d, _d, _d, _d, _d, _d, _d,
+                            ctypes.POINTER(cb_plan_opts)]),
+    "cb_plan_destroy": (_i, [_vp]),
+    "cb_plan_get_info": (_i, [_vp, ctypes.POINTER(cb_plan_info)]),
+    "cb_plan_get_table": (_i, [_vp, ctypes.POINTER(_d)]),
+    "cb_plan_set_stream": (_i, [_vp, _vp]),
+    "cb_transfer_table": (_i, [_i, _d, _d, _d, _d, _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+    "cb_apply_K": (_i, [_vp, _vp, _vp]),
+    "cb_solve_indent": (_i, [_vp, _vp, _d, _vp, _vp, ctypes.POINTER(cb_solve_opts),
+                             ctypes.POINTER(cb_result)]),
+    "cb_solve_force": (_i, [_vp, _vp, _d, _vp, _vp, ctypes.POINTER(cb_solve_opts),
+                            ctypes.POINTER(cb_result)]),
+    "cb_sweep": (_i, [_vp, _vp, ctypes.POINTER(_d), _i, _vp, _vp,
+                      ctypes.POINTER(cb_solve_opts), ctypes.POINTER(cb_result)]),
+    "cb_status_string": (ctypes.c_char_p, [_i]),
+    "cb_last_error": (ctypes.c_char_p, []),
+    "cb_version": (_i, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class CoatbemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libcoatbem status {status} ({_lib.cb_status_string(status).decode()}): {msg}")
+        self.status = status
+
+
+def _check(rc):
+    if rc != CB_OK:
+        raise CoatbemError(rc, _lib.cb_last_error().decode())
+    return rc
+
+
+def cb_version():
+    return _lib.cb_version()
+
+
+def cb_status_string(status):
+    return _lib.cb_status_string(status).decode()
+
+
+@dataclass
+class Plan:
+    handle: ctypes.c_void_p
+    N: int
+    dtype: torch.dtype
+    device: torch.device
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.cb_plan_destroy(self.handle)
+            self.handle = None
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def cb_plan_create(N, L, h, E1, nu1, E2, nu2, dgamma=0.0, precision="fp64",
+                   dc_mode="bz", stream=None, autotune=0):
+    opts = cb_plan_opts(CB_FP64 if precision == "fp64" else CB_FP32,
+                        CB_DC_BZ if dc_mode == "bz" else CB_DC_ZERO,
+                        _stream_ptr(stream), int(autotune), None)
+    h_ = ctypes.c_void_p()
+    _check(_lib.cb_plan_create(ctypes.byref(h_), int(N), float(L), float(h),
+                               float(E1), float(nu1), float(E2), float(nu2),
+                               float(dgamma), ctypes.byref(opts)))
+    return Plan(h_, int(N), torch.float64 if precision == "fp64" else torch.float32,
+                torch.device("cuda", torch.cuda.current_device()))
+
+
+def cb_plan_destroy(plan: Plan):
+    if plan.handle:
+        _check(_lib.cb_plan_destroy(plan.handle))
+        plan.handle = None
+
+
+def cb_plan_get_info(plan: Plan):
+    info = cb_plan_info()
+    _check(_lib.cb_plan_get_info(plan.handle, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def cb_plan_get_table(plan: Plan):
+    import numpy as np
+    out = np.empty((plan.N + 1, plan.N + 1), dtype=np.float64)
+    _check(_lib.cb_plan_get_table(plan.handle, out.ctypes.data_as(ctypes.POINTER(_d))))
+    return out
+
+
+def cb_transfer_table(N, L, h, E1, nu1, E2, nu2, dc_mode="bz"):
+    """Host-computed FP64 table ((N+1)^2) and the self-influence k00."""
+    import numpy as np
+    out = np.empty((N + 1, N + 1), dtype=np.float64)
+    k00 = ctypes.c_double()
+    _check(_lib.cb_transfer_table(int(N), float(L), float(h), float(E1), float(nu1), float(E2),
+                                  float(nu2), CB_DC_BZ if dc_mode == "bz" else CB_DC_ZERO,
+                                  out.ctypes.data_as(ctypes.POINTER(_d)), ctypes.byref(k00)))
+    return out, k00.value
+
+
+def cb_plan_set_stream(plan: Plan, stream=None):
+    _check(_lib.cb_plan_set_stream(plan.handle, _stream_ptr(stream)))
+
+
+def _arr(plan: Plan, x, name, dtype=None):
+    dtype = dtype or plan.dtype
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if x.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if x.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {x.dtype}")
+    if tuple(x.shape) != (plan.N, plan.N) or not x.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {plan.N}x{plan.N} tensor")
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def _opts(tol=0.0, max_iter=0, chunk=0, init=0, attach_tol=-1.0, max_rounds=0):
+    return cb_solve_opts(float(tol), int(max_iter), int(chunk), int(init),
+                         float(attach_tol), int(max_rounds))
+
+
+def cb_apply_K(plan: Plan, p, u):
+    _check(_lib.cb_apply_K(plan.handle, _arr(plan, p, "p"), _arr(plan, u, "u")))
+    return u
+
+
+def cb_solve_indent(plan: Plan, f, d, p, mask=None, raise_on_error=True, **opts):
+    res = cb_result()
+    m = _arr(plan, mask, "mask", torch.uint8) if mask is not None else None
+    rc = _lib.cb_solve_indent(plan.handle, _arr(plan, f, "f"), float(d), _arr(plan, p, "p"),
+                              m, ctypes.byref(_opts(**opts)), ctypes.byref(res))
+    if raise_on_error:
+        _check(rc)
+    return res.as_dict()
+
+
+def cb_solve_force(plan: Plan, f, F, p, mask=None, raise_on_error=True, **opts):
+    res = cb_result()
+    m = _arr(plan, mask, "mask", torch.uint8) if mask is not None else None
+    rc = _lib.cb_solve_force(plan.handle, _arr(plan, f, "f"), float(F), _arr(plan, p, "p"),
+                             m, ctypes.byref(_opts(**opts)), ctypes.byref(res))
+    if raise_on_error:
+        _check(rc)
+    return res.as_dict()
+
+
+def cb_sweep(plan: Plan, f, d_steps, p_state, mask_state, raise_on_error=True, **opts):
+    n = len(d_steps)
+    steps = (ctypes.c_double * n)(*[float(x) for x in d_steps])
+    out = (cb_result * max(n, 1))()
+    rc = _lib.cb_sweep(plan.handle, _arr(plan, f, "f"), steps, n, _arr(plan, p_state, "p_state"),
+                       _arr(plan, mask_state, "mask_state", torch.uint8),
+                       ctypes.byref(_opts(**opts)), out)
+    if raise_on_error:
+        _check(rc)
+    return [out[i].as_dict() for i in range(n)]

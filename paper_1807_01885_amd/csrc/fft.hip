@@ -1,0 +1,354 @@
+// u = K p on the 2N-zero-padded grid (Eq. 1 evaluated as Eq. 11):
+//
+//   K1  rows, forward real FFT of length M = 2N of each of the N rows
+//       (only the first N inputs non-zero), as a length-N complex FFT of
+//       the packed pairs (x[2n] + i x[2n+1]) followed by the standard
+//       even/odd split; writes the N+1 half-spectrum values of every row.
+//   K2  columns, for each of the N+1 half-spectrum columns: forward complex
+//       FFT of length M (first N inputs non-zero), multiply by the real
+//       transfer table K^(|k|)/M^2, inverse FFT of length M, keep the first
+//       N outputs.  The multiply sits between the last forward pass and the
+//       first inverse pass, both register-resident.
+//   K3  rows, inverse real FFT (Hermitian half spectrum -> first N of M
+//       real outputs).
+//
+// Intermediate layout ("row tiles"): S[rb][kx][rr], rb = row / RB,
+// rr = row % RB, kx in [0, N], complex.  K1/K3 read and write whole tiles
+// (contiguous), K2 reads RB-element segments of a column.
+#include "fft_core.h"
+#include "internal.h"
+
+namespace cb {
+
+constexpr int PS = 4;  // LDS padding shift
+
+// ---------------------------------------------------------------------------
+// K1: forward row transform
+// ---------------------------------------------------------------------------
+template <typename T, int LOG2N, int RB, int NT1, int G>
+__global__ void __launch_bounds__(G * RB * NT1)
+k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restrict__ tw_g) {
+  using C = cx<T>;
+  constexpr int N = 1 << LOG2N, M = 2 * N, L = N, NC = N + 1;
+  constexpr int ROWS = G * RB, NTH = ROWS * NT1, E = L / NT1;
+  constexpr int LP = padded<PS>(L);
+  using TW = Tw<T, M>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tws = reinterpret_cast<C*>(smem_raw);
+  C* buf = tws + TW::NLO + TW::NHI;
+
+  const int tid = threadIdx.x;
+  TW::stage(tws, tw_g, tid, NTH);
+  const TW tw{tws, tws + TW::NLO};
+  const int lrow = tid / NT1, t = tid % NT1;
+  const int row0 = blockIdx.x * ROWS;
+  C* line = buf + lrow * LP;
+  __syncthreads();
+
+  // first pass (Ls = 1): packed inputs z[n], n < N/2, from global
+  {
+    constexpr int R = pick_radix(L, E, 1);
+    constexpr int NB = L / (R * NT1);
+    const C* z = reinterpret_cast<const C*>(p + (size_t)(row0 + lrow) * N);
+    C a[NB][R];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const int j = t + b * NT1;
+#pragma unroll
+      for (int i = 0; i < R; i++) a[b][i] = (i < R / 2) ? z[j + i * (L / R)] : C{T(0), T(0)};
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const int j = t + b * NT1;
+      dft<T, R, 1>(a[b]);
+#pragma unroll
+      for (int i = 0; i < R; i++) line[padi<PS>(out_index<R, 1>(j, i))] = a[b][i];
+    }
+    __syncthreads();
+    MidPasses<T, L, M, NT1, 1, PS, R, L>::run(line, t, tw);
+  }
+
+  // split into the half spectrum of the length-M real transform:
+  // X[k] = (Z[k] + conj Z[N-k])/2 - i/2 W^k (Z[k] - conj Z[N-k]),
+  // W = exp(-2 pi i / M), k in [0, N]; items in tile order (k major, rr minor)
+  constexpr int ITEMS = G * NC * RB;
+  C* out = S + (size_t)blockIdx.x * ITEMS;
+  for (int q = tid; q < ITEMS; q += NTH) {
+    const int g = q / (NC * RB);
+    const int qq = q - g * (NC * RB);
+    const int k = qq / RB;
+    const int rr = qq - k * RB;
+    const C* ln = buf + (g * RB + rr) * LP;
+    const C zk = ln[padi<PS>(k & (N - 1))];
+    const C zn = cconj(ln[padi<PS>((N - k) & (N - 1))]);
+    const C e = cscale(cadd(zk, zn), T(0.5));
+    const C o = cscale(csub(zk, zn), T(0.5));  // times -i below
+    const C w = tw.get(k);
+    const C wo = cmul(w, mul_mi<1>(o));
+    out[q] = cadd(e, wo);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K2: column transform, transfer multiply, inverse column transform
+// ---------------------------------------------------------------------------
+template <typename T, int LOG2N, int RB, int NT2, int CB>
+__global__ void __launch_bounds__(CB * NT2)
+k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict__ tw_g) {
+  using C = cx<T>;
+  constexpr int N = 1 << LOG2N, M = 2 * N, L = M, NC = N + 1;
+  constexpr int NTH = CB * NT2, E = L / NT2;
+  constexpr int LP = padded<PS>(L);
+  constexpr int NBLK = (NC + CB - 1) / CB;
+  using TW = Tw<T, M>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tws = reinterpret_cast<C*>(smem_raw);
+  C* buf = tws + TW::NLO + TW::NHI;
+
+  const int tid = threadIdx.x;
+  TW::stage(tws, tw_g, tid, NTH);
+  const TW tw{tws, tws + TW::NLO};
+  const int lc = tid / NT2, t = tid % NT2;
+  const int kx = xcd_block(blockIdx.x, NBLK) * CB + lc;
+  const bool active = kx < NC;
+  C* line = buf + lc * LP;
+  __syncthreads();
+
+  constexpr int R0 = pick_radix(L, E, 1);
+  constexpr int RL = last_radix(L, E);
+  // forward first pass, inputs rows n < N from the tiles (upper half zero)
+  {
+    constexpr int NB = L / (R0 * NT2);
+    C a[NB][R0];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const int j = t + b * NT2;
+#pragma unroll
+      for (int i = 0; i < R0; i++) {
+        const int n = j + i * (L / R0);
+        a[b][i] = (i < R0 / 2 && active)
+                      ? S[(size_t)(n / RB) * (NC * RB) + kx * RB + (n % RB)]
+                      : C{T(0), T(0)};
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const int j = t + b * NT2;
+      dft<T, R0, 1>(a[b]);
+#pragma unroll
+      for (int i = 0; i < R0; i++) line[padi<PS>(out_index<R0, 1>(j, i))] = a[b][i];
+    }
+    __syncthreads();
+  }
+  MidPasses<T, L, M, NT2, 1, PS, R0, L / RL>::run(line, t, tw);
+  // last forward pass (stride L/RL) -> multiply -> first inverse pass, in registers
+  {
+    constexpr int NB = L / (RL * NT2);
+    C a[NB][RL];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const int j = t + b * NT2;
+#pragma unroll
+      for (int i = 0; i < RL; i++) a[b][i] = line[padi<PS>(j + i * (L / RL))];
+    }
+    __syncthreads();
+    const T* trow = Tq + (size_t)(active ? kx : 0) * NC;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const int j = t + b * NT2;
+      butterfly<T, L, M, RL, L / RL, 1>(a[b], j, tw);
+#pragma unroll
+      for (int i = 0; i < RL; i++) {
+        const int ky = j + i * (L / RL);
+        const int kq = ky <= N ? ky : M - ky;
+        a[b][i] = cscale(a[b][i], trow[kq]);
+      }
+      dft<T, RL, -1>(a[b]);
+#pragma unroll
+      for (int i = 0; i < RL; i++) line[padi<PS>(out_index<RL, 1>(j, i))] = a[b][i];
+    }
+    __syncthreads();
+  }
+  // inverse passes: the first (radix RL, stride 1) is done; the greedy
+  // schedule continues from stride RL
+  constexpr int RIL = last_radix_from(L, E, RL);
+  MidPasses<T, L, M, NT2, -1, PS, RL, L / RIL>::run(line, t, tw);
+  {
+    constexpr int NB = L / (RIL * NT2);
+    C a[NB][RIL];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const int j = t + b * NT2;
+#pragma unroll
+      for (int i = 0; i < RIL; i++) a[b][i] = line[padi<PS>(j + i * (L / RIL))];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const int j = t + b * NT2;
+      butterfly<T, L, M, RIL, L / RIL, -1>(a[b], j, tw);
+      if (active) {
+#pragma unroll
+        for (int i = 0; i < RIL / 2; i++) {
+          const int n = j + i * (L / RIL);  // < N
+          S[(size_t)(n / RB) * (NC * RB) + kx * RB + (n % RB)] = a[b][i];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K3: inverse row transform (half spectrum -> first N real outputs)
+// ---------------------------------------------------------------------------
+template <typename T, int LOG2N, int RB, int NT1, int G>
+__global__ void __launch_bounds__(G * RB * NT1)
+k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restrict__ tw_g) {
+  using C = cx<T>;
+  constexpr int N = 1 << LOG2N, M = 2 * N, L = N, NC = N + 1;
+  constexpr int ROWS = G * RB, NTH = ROWS * NT1, E = L / NT1;
+  constexpr int LP = padded<PS>(L + 1);
+  using TW = Tw<T, M>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* tws = reinterpret_cast<C*>(smem_raw);
+  C* buf = tws + TW::NLO + TW::NHI;
+
+  const int tid = threadIdx.x;
+  TW::stage(tws, tw_g, tid, NTH);
+  const TW tw{tws, tws + TW::NLO};
+  constexpr int ITEMS = G * NC * RB;
+  const C* in = S + (size_t)blockIdx.x * ITEMS;
+  for (int q = tid; q < ITEMS; q += NTH) {
+    const int g = q / (NC * RB);
+    const int qq = q - g * (NC * RB);
+    const int k = qq / RB;
+    const int rr = qq - k * RB;
+    buf[(g * RB + rr) * LP + padi<PS>(k)] = in[q];
+  }
+  __syncthreads();
+  // Z[k] = (X[k] + conj X[N-k]) + i W^-k (X[k] - conj X[N-k]), pairs (k, N-k)
+  constexpr int PAIRS = N / 2 + 1;
+  for (int q = tid; q < ROWS * PAIRS; q += NTH) {
+    const int lr = q / PAIRS;
+    const int k = q - lr * PAIRS;
+    C* ln = buf + lr * LP;
+    const C xk = ln[padi<PS>(k)];
+    const C xn = ln[padi<PS>(N - k)];
+    {
+      const C s = cadd(xk, cconj(xn));
+      const C dd = csub(xk, cconj(xn));
+      const C w = cconj(tw.get(k));
+      ln[padi<PS>(k)] = cadd(s, mul_mi<-1>(cmul(w, dd)));
+    }
+    if (k != 0 && k != N / 2) {
+      const C s = cadd(xn, cconj(xk));
+      const C dd = csub(xn, cconj(xk));
+      const C w = cconj(tw.get(N - k));
+      ln[padi<PS>(N - k)] = cadd(s, mul_mi<-1>(cmul(w, dd)));
+    }
+  }
+  __syncthreads();
+  const int lrow = tid / NT1, t = tid % NT1;
+  C* line = buf + lrow * LP;
+  constexpr int RL = last_radix(L, E);
+  MidPasses<T, L, M, NT1, -1, PS, 1, L / RL>::run(line, t, tw);
+  {
+    constexpr int NB = L / (RL * NT1);
+    C* zo = reinterpret_cast<C*>(u + (size_t)(blockIdx.x * ROWS + lrow) * N);
+    C a[NB][RL];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const int j = t + b * NT1;
+#pragma unroll
+      for (int i = 0; i < RL; i++) a[b][i] = line[padi<PS>(j + i * (L / RL))];
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+      const int j = t + b * NT1;
+      butterfly<T, L, M, RL, L / RL, -1>(a[b], j, tw);
+#pragma unroll
+      for (int i = 0; i < RL / 2; i++) zo[j + i * (L / RL)] = a[b][i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch shapes and dispatch
+// ---------------------------------------------------------------------------
+template <int LOG2N> struct Shape {
+  static constexpr int N = 1 << LOG2N, M = 2 * N;
+  static constexpr int E1 = N < 16 ? N : 16;
+  static constexpr int NT1 = N / E1;
+  static constexpr int E2 = 16;
+  static constexpr int NT2 = M / E2;
+  static constexpr int CB = NT2 >= 64 ? 1 : 64 / NT2;
+};
+
+template <typename T> constexpr int row_tile() { return sizeof(T) == 4 ? 4 : 2; }
+
+template <typename T, int LOG2N>
+static size_t lds_rows(int G) {
+  constexpr int N = 1 << LOG2N, M = 2 * N;
+  using TW = Tw<T, M>;
+  return sizeof(cx<T>) * (TW::NLO + TW::NHI + (size_t)G * row_tile<T>() * padded<PS>(N + 1));
+}
+template <typename T, int LOG2N>
+static size_t lds_cols(int CB) {
+  constexpr int N = 1 << LOG2N, M = 2 * N;
+  using TW = Tw<T, M>;
+  return sizeof(cx<T>) * (TW::NLO + TW::NHI + (size_t)CB * padded<PS>(M));
+}
+
+template <typename T, int LOG2N>
+static hipError_t apply_impl(const T* p, T* u, cx<T>* S, const T* Tq, const cx<T>* tw,
+                             hipStream_t st) {
+  using SH = Shape<LOG2N>;
+  constexpr int N = SH::N, RB = row_tile<T>();
+  constexpr int G0 = (SH::NT1 * RB >= 64) ? 1 : 64 / (SH::NT1 * RB);
+  constexpr int G = G0 > N / RB ? N / RB : G0;
+  constexpr int NC = N + 1;
+  const size_t lr = lds_rows<T, LOG2N>(G), lc = lds_cols<T, LOG2N>(SH::CB);
+  auto k1 = k_rows_fwd<T, LOG2N, RB, SH::NT1, G>;
+  auto k2 = k_cols<T, LOG2N, RB, SH::NT2, SH::CB>;
+  auto k3 = k_rows_inv<T, LOG2N, RB, SH::NT1, G>;
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
+    hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
+    hipFuncSetAttribute((const void*)k3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
+    attr = true;
+  }
+  const int nb_rows = N / (RB * G);
+  const int nb_cols = (NC + SH::CB - 1) / SH::CB;
+  hipLaunchKernelGGL(k1, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw);
+  hipLaunchKernelGGL(k2, dim3(nb_cols), dim3(SH::CB * SH::NT2), lc, st, S, Tq, tw);
+  hipLaunchKernelGGL(k3, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t apply_dispatch(int log2n, const T* p, T* u, cx<T>* S, const T* Tq,
+                                 const cx<T>* tw, hipStream_t st) {
+  switch (log2n) {
+    case 4: return apply_impl<T, 4>(p, u, S, Tq, tw, st);
+    case 5: return apply_impl<T, 5>(p, u, S, Tq, tw, st);
+    case 6: return apply_impl<T, 6>(p, u, S, Tq, tw, st);
+    case 7: return apply_impl<T, 7>(p, u, S, Tq, tw, st);
+    case 8: return apply_impl<T, 8>(p, u, S, Tq, tw, st);
+    case 9: return apply_impl<T, 9>(p, u, S, Tq, tw, st);
+    case 10: return apply_impl<T, 10>(p, u, S, Tq, tw, st);
+    case 11: return apply_impl<T, 11>(p, u, S, Tq, tw, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st) {
+  if (P->precision == 0)
+    return apply_dispatch<double>(P->log2n, (const double*)p, (double*)u, (cx<double>*)P->d_S,
+                                  (const double*)P->d_table, (const cx<double>*)P->d_tw, st);
+  return apply_dispatch<float>(P->log2n, (const float*)p, (float*)u, (cx<float>*)P->d_S,
+                               (const float*)P->d_table, (const cx<float>*)P->d_tw, st);
+}
+
+size_t intermediate_elems(int N) { return (size_t)N * (N + 1); }
+
+}  // namespace cb

@@ -1,0 +1,194 @@
+// Device building blocks for the zero-padded real 2-D FFT convolution.
+//
+// Stockham autosort passes over lines held in LDS, radix 2..16 butterflies
+// in registers, twiddles from a two-level table (64-entry fine table times
+// a coarse table) so that every twiddle is one complex product of two
+// correctly rounded values.  All sizes are compile-time constants.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace cb {
+
+template <typename T> struct cx_of;
+template <> struct cx_of<float> { using type = float2; };
+template <> struct cx_of<double> { using type = double2; };
+template <typename T> using cx = typename cx_of<T>::type;
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename C> __device__ __forceinline__ C cconj(C a) { return C{a.x, -a.y}; }
+template <typename C, typename S> __device__ __forceinline__ C cscale(C a, S s) { return C{a.x * s, a.y * s}; }
+// a * (-i) for the forward direction (DIR = +1), a * (+i) for the inverse.
+template <int DIR, typename C> __device__ __forceinline__ C mul_mi(C a) {
+  if constexpr (DIR > 0) return C{a.y, -a.x};
+  else return C{-a.y, a.x};
+}
+
+// exp(-DIR * 2 pi i m / 16) for m in [1, 8), as exact-to-rounding constants.
+template <typename T, int DIR>
+__device__ __forceinline__ cx<T> root16(int m) {
+  constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;
+  constexpr double c2 = 0.70710678118654752440;
+  double c = 1.0, s = 0.0;
+  switch (m) {
+    case 1: c = c1; s = s1; break;
+    case 2: c = c2; s = c2; break;
+    case 3: c = s1; s = c1; break;
+    case 4: c = 0.0; s = 1.0; break;
+    case 5: c = -s1; s = c1; break;
+    case 6: c = -c2; s = c2; break;
+    case 7: c = -c1; s = s1; break;
+    default: break;
+  }
+  return cx<T>{T(c), T(DIR > 0 ? -s : s)};
+}
+
+__host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+
+template <int R>
+__host__ __device__ constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) { r = (r << 1) | (i & 1); i >>= 1; }
+  return r;
+}
+
+// In-register DFT of length R (power of two, <= 16), natural order in and
+// out.  DIR = +1: sum a_n exp(-2 pi i n k / R); DIR = -1: exp(+...).
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void dft(cx<T>* a) {
+  using C = cx<T>;
+#pragma unroll
+  for (int i = 0; i < R; i++) {
+    const int j = bitrev<R>(i);
+    if (j > i) { C t = a[i]; a[i] = a[j]; a[j] = t; }
+  }
+#pragma unroll
+  for (int len = 2; len <= R; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < R; i += len) {
+#pragma unroll
+      for (int k = 0; k < len / 2; k++) {
+        C v = a[i + k + len / 2];
+        const int m = k * (16 / len);
+        if (m == 4) v = mul_mi<DIR>(v);
+        else if (m != 0) v = cmul(v, root16<T, DIR>(m));
+        const C u = a[i + k];
+        a[i + k] = cadd(u, v);
+        a[i + k + len / 2] = csub(u, v);
+      }
+    }
+  }
+}
+
+// Two-level twiddle table for a transform length LT (power of two):
+// w(e) = exp(-2 pi i e / LT) = hi[e >> 6] * lo[e & 63] (LT > 64), lo[e] else.
+template <typename T, int LT>
+struct Tw {
+  static constexpr int NLO = LT < 64 ? LT : 64;
+  static constexpr int NHI = LT <= 64 ? 1 : LT / 64;
+  const cx<T>* lo;
+  const cx<T>* hi;
+  __device__ __forceinline__ cx<T> get(int e) const {
+    if constexpr (LT <= 64) return lo[e];
+    else return cmul(hi[e >> 6], lo[e & 63]);
+  }
+  // cooperative copy of the global tables (lo then hi) into LDS
+  __device__ __forceinline__ static void stage(cx<T>* dst, const cx<T>* __restrict__ src, int tid, int nthreads) {
+    for (int i = tid; i < NLO + NHI; i += nthreads) dst[i] = src[i];
+  }
+};
+
+// LDS padding: one extra slot every 2^PS elements.
+template <int PS>
+__device__ __forceinline__ int padi(int i) { return i + (i >> PS); }
+template <int PS>
+__host__ __device__ constexpr int padded(int n) { return n + (n >> PS) + 1; }
+
+// Radix used by the pass at stride Ls for a length-L line with E elements
+// per thread.
+__host__ __device__ constexpr int pick_radix(int L, int E, int Ls) {
+  int r = E < 16 ? E : 16;
+  return (L / Ls) < r ? (L / Ls) : r;
+}
+// Radix of the last pass of the greedy schedule that starts at stride Ls0.
+__host__ __device__ constexpr int last_radix_from(int L, int E, int Ls0) {
+  int Ls = Ls0, r = 1;
+  while (Ls < L) { r = pick_radix(L, E, Ls); Ls *= r; }
+  return r;
+}
+__host__ __device__ constexpr int last_radix(int L, int E) { return last_radix_from(L, E, 1); }
+
+// Twiddle then DFT of one butterfly of a Stockham pass (stride Ls, radix R,
+// twiddle-table length LT, line length L; j = butterfly index).
+template <typename T, int L, int LT, int R, int Ls, int DIR>
+__device__ __forceinline__ void butterfly(cx<T>* a, int j, const Tw<T, LT>& tw) {
+  if constexpr (Ls > 1) {
+    const int k = j & (Ls - 1);
+    constexpr int scale = LT / (Ls * R);
+#pragma unroll
+    for (int i = 1; i < R; i++) {
+      cx<T> w = tw.get(i * k * scale);
+      if constexpr (DIR < 0) w.y = -w.y;
+      a[i] = cmul(a[i], w);
+    }
+  }
+  dft<T, R, DIR>(a);
+}
+
+template <int R, int Ls>
+__device__ __forceinline__ int out_index(int j, int i) {
+  const int k = j & (Ls - 1);
+  return (j - k) * R + k + i * Ls;
+}
+
+// One Stockham pass LDS -> LDS for the line at `buf` (NT threads, t).
+template <typename T, int L, int LT, int R, int Ls, int NT, int DIR, int PS>
+__device__ __forceinline__ void lds_pass(cx<T>* buf, int t, const Tw<T, LT>& tw) {
+  constexpr int NB = L / (R * NT);
+  cx<T> a[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    const int j = t + b * NT;
+#pragma unroll
+    for (int i = 0; i < R; i++) a[b][i] = buf[padi<PS>(j + i * (L / R))];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    const int j = t + b * NT;
+    butterfly<T, L, LT, R, Ls, DIR>(a[b], j, tw);
+#pragma unroll
+    for (int i = 0; i < R; i++) buf[padi<PS>(out_index<R, Ls>(j, i))] = a[b][i];
+  }
+  __syncthreads();
+}
+
+// All passes with stride Ls < LsEnd, LDS -> LDS.
+template <typename T, int L, int LT, int NT, int DIR, int PS, int Ls, int LsEnd>
+struct MidPasses {
+  __device__ __forceinline__ static void run(cx<T>* buf, int t, const Tw<T, LT>& tw) {
+    if constexpr (Ls < LsEnd) {
+      constexpr int R = pick_radix(L, L / NT, Ls);
+      lds_pass<T, L, LT, R, Ls, NT, DIR, PS>(buf, t, tw);
+      MidPasses<T, L, LT, NT, DIR, PS, Ls * R, LsEnd>::run(buf, t, tw);
+    }
+  }
+};
+
+// XCD-aware block index: blocks are dealt round-robin to the 8 XCDs, so
+// block b runs on XCD b % 8; hand each XCD a contiguous range of logical
+// blocks so that neighbours sharing cache lines share an L2.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+  const int per = (nblocks + 7) >> 3;
+  const int xcd = b & 7;
+  const int idx = b >> 3;
+  // number of XCDs that receive `per` blocks vs `per - 1`
+  const int full = nblocks - (per - 1) * 8;  // XCDs [0, full) get `per`
+  int start = xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1);
+  return start + idx;
+}
+
+}  // namespace cb

@@ -1,0 +1,99 @@
+"""GPU parity of cb_apply_K (u = K p, Eq. 11 on the 2N-padded grid) against
+the FP64 oracle, element by element.
+
+Tolerances: FP64 1e-12 relative to max|u| (rounding of ~log2(M) FFT
+stages); FP32 (FP32 FFT with FP64-derived tables) 3e-6 relative to
+max|u|, derived from eps32 * (log2 M passes + twiddle rounding).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.operator import Operator
+from oracle.transfer import Material
+
+pytestmark = pytest.mark.gpu
+
+LAYER = Material(0.1, 10.0, 0.3, 1.0, 0.3)
+TOL = {"fp64": 1e-12, "fp32": 3e-6}
+DT = {"fp64": torch.float64, "fp32": torch.float32}
+
+
+def _run(lib, N, L, mat, p, prec):
+    plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, 0.0, prec)
+    pt = torch.tensor(p, dtype=DT[prec], device="cuda")
+    u = torch.empty_like(pt)
+    lib.cb_apply_K(plan, pt, u)
+    torch.cuda.synchronize()
+    return plan, u.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("N", [16, 32, 64, 128, 256, 512, 1024, 2048])
+def test_apply_random(lib, N, prec):
+    print(f"apply random N={N} {prec}", flush=True)
+    rng = np.random.default_rng(N + (0 if prec == "fp64" else 7))
+    p = rng.standard_normal((N, N))
+    op = Operator(N, 1.0, LAYER)
+    ref = op.apply(p)
+    _, u = _run(lib, N, 1.0, LAYER, p, prec)
+    err = np.abs(u - ref).max() / np.abs(ref).max()
+    assert err < TOL[prec], f"N={N} {prec} err={err:.3e}"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("mat", [Material(0.02, 0.1, 0.25, 1.0, 0.45),
+                                 Material(0.0, 2.0, 0.3, 2.0, 0.3),
+                                 Material(5.0, 0.05, 0.45, 1.0, 0.2)])
+def test_apply_materials_and_ragged_support(lib, mat, prec):
+    """Pressure on an off-centre rectangle touching the grid edges."""
+    N, L = 256, 2.0
+    rng = np.random.default_rng(3)
+    p = np.zeros((N, N))
+    p[0:77, 131:N] = rng.uniform(0, 1, (77, N - 131))
+    op = Operator(N, L, mat)
+    ref = op.apply(p)
+    _, u = _run(lib, N, L, mat, p, prec)
+    assert np.abs(u - ref).max() / np.abs(ref).max() < TOL[prec]
+
+
+def test_apply_zero_and_determinism(lib):
+    N = 128
+    plan = lib.cb_plan_create(N, 1.0, 0.1, 10.0, 0.3, 1.0, 0.3, 0.0, "fp64")
+    z = torch.zeros(N, N, dtype=torch.float64, device="cuda")
+    u = torch.full_like(z, 7.0)
+    lib.cb_apply_K(plan, z, u)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(u).item() == 0
+    p = torch.rand(N, N, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(1))
+    u1 = torch.empty_like(p)
+    u2 = torch.empty_like(p)
+    lib.cb_apply_K(plan, p, u1)
+    lib.cb_apply_K(plan, p, u2)
+    torch.cuda.synchronize()
+    assert torch.equal(u1, u2)
+
+
+def test_apply_on_side_stream(lib):
+    N = 64
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan = lib.cb_plan_create(N, 1.0, 0.1, 10.0, 0.3, 1.0, 0.3, 0.0, "fp64")
+        p = torch.ones(N, N, dtype=torch.float64, device="cuda")
+        u = torch.empty_like(p)
+        lib.cb_apply_K(plan, p, u)
+    s.synchronize()
+    ref = Operator(N, 1.0, LAYER).apply(np.ones((N, N)))
+    assert np.abs(u.cpu().numpy() - ref).max() / ref.max() < 1e-12
+
+
+def test_plan_table_matches_oracle(lib):
+    N, L = 128, 1.0
+    plan = lib.cb_plan_create(N, L, 0.1, 10.0, 0.3, 1.0, 0.3, 1e-3, "fp32")
+    T = lib.cb_plan_get_table(plan)
+    from oracle.transfer import transfer_table, critical_stress
+    ref = transfer_table(N, L, LAYER)[: N + 1, : N + 1]
+    np.testing.assert_allclose(T, ref, rtol=1e-11)
+    info = lib.cb_plan_get_info(plan)
+    assert info["sigma_c"] == pytest.approx(critical_stress(LAYER, 1e-3, L / N), rel=1e-14)
+    assert info["M"] == 2 * N and info["precision"] == 1

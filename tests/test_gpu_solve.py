@@ -1,0 +1,154 @@
+"""GPU parity of the contact solves against the FP64 oracle.
+
+Metrics (both sides on the same seeded inputs):
+  pressure relative L2 error, total-force relative error, contact-set
+  agreement 1 - |S_gpu ^ S_ora| / |S_gpu u S_ora|.
+Bars: FP64 path 1e-8 / 1e-10 / identical sets (the LCP solution is unique
+and both sides converge to 1e-10); FP32 path (FP32 fields and FFT, FP64
+reductions) 1e-4 / 1e-5 / >= 0.999.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.operator import Operator
+from oracle.solvers import adhesive_solve, solve_pk, sweep
+from oracle.transfer import Material, critical_stress
+from paper_1807_01885_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DT = {"fp64": torch.float64, "fp32": torch.float32}
+
+
+def agreement(a, b):
+    a = a.astype(bool)
+    b = b.astype(bool)
+    u = (a | b).sum()
+    return 1.0 if u == 0 else 1.0 - (a ^ b).sum() / u
+
+
+def _plan(lib, c, prec, dgamma=0.0):
+    return lib.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, dgamma, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_config1_indent(lib, prec):
+    print(f"config1 {prec}", flush=True)
+    c = inputs.paraboloid_c1()
+    op = Operator(c.N, c.L, Material(c.h, c.E1, c.nu1, c.E2, c.nu2))
+    ref = solve_pk(op, c.f, c.target, tol=1e-10)
+    plan = _plan(lib, c, prec)
+    f = torch.tensor(c.f, dtype=DT[prec], device="cuda")
+    p = torch.zeros_like(f)
+    mask = torch.zeros(c.N, c.N, dtype=torch.uint8, device="cuda")
+    res = lib.cb_solve_indent(plan, f, c.target, p, mask, tol=1e-10 if prec == "fp64" else 1e-6)
+    pg = p.double().cpu().numpy()
+    e_p = np.linalg.norm(pg - ref.p) / np.linalg.norm(ref.p)
+    e_F = abs(res["F"] - ref.F) / ref.F
+    agr = agreement(mask.cpu().numpy(), ref.p > 0)
+    print(f"  iters gpu {res['iters']} oracle {ref.iters} e_p {e_p:.2e} e_F {e_F:.2e} agree {agr}")
+    if prec == "fp64":
+        assert res["resid"] <= 1e-10
+        assert e_p < 1e-8 and e_F < 1e-10 and agr == 1.0
+    else:
+        assert e_p < 1e-4 and e_F < 1e-5 and agr >= 0.999
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", ["paraboloid", "flat", "cone"])
+def test_indent_and_force_N256(lib, prec, shape):
+    print(f"indent/force N=256 {shape} {prec}", flush=True)
+    N, L = 256, 1.0
+    mat = Material(0.05, 0.2, 0.3, 1.0, 0.35)
+    f = {"paraboloid": inputs.paraboloid(N, L, 1.0), "flat": inputs.flat_punch(N, L, 0.2),
+         "cone": inputs.cone(N, L, 0.1)}[shape]
+    d = {"paraboloid": 4e-3, "flat": 1e-3, "cone": 8e-3}[shape]
+    op = Operator(N, L, mat)
+    ref = solve_pk(op, f, d, tol=1e-10)
+    plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, 0.0, prec)
+    ft = torch.tensor(f, dtype=DT[prec], device="cuda")
+    p = torch.zeros_like(ft)
+    tol = 1e-10 if prec == "fp64" else 1e-6
+    res = lib.cb_solve_indent(plan, ft, d, p, tol=tol)
+    e_p = np.linalg.norm(p.double().cpu().numpy() - ref.p) / np.linalg.norm(ref.p)
+    print(f"  indent iters {res['iters']} (oracle {ref.iters}) e_p {e_p:.2e}")
+    assert e_p < (1e-8 if prec == "fp64" else 1e-4)
+    # force control at the oracle's force: recovers d and p
+    p2 = torch.zeros_like(ft)
+    res2 = lib.cb_solve_force(plan, ft, ref.F, p2, tol=tol)
+    e_p2 = np.linalg.norm(p2.double().cpu().numpy() - ref.p) / np.linalg.norm(ref.p)
+    print(f"  force iters {res2['iters']} d {res2['d']:.6e} vs {d:.6e} e_p {e_p2:.2e}")
+    assert abs(res2["F"] - ref.F) / ref.F < (1e-12 if prec == "fp64" else 1e-6)
+    assert e_p2 < (1e-7 if prec == "fp64" else 1e-4)
+    assert res2["d"] == pytest.approx(d, rel=1e-7 if prec == "fp64" else 1e-4)
+
+
+def test_adhesive_single_solve_fp64(lib):
+    print("adhesive single", flush=True)
+    N, L = 64, 1.0
+    mat = Material(0.1, 1.0, 0.3, 1.0, 0.3)
+    f = inputs.paraboloid(N, L, 1.0)
+    d, dg = 3e-3, 2e-4
+    op = Operator(N, L, mat)
+    sc = critical_stress(mat, dg, L / N)
+    st, rounds, u, conv = adhesive_solve(op, f, d, sc, 1e-12 * L, tol=1e-10)
+    plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, dg, "fp64")
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
+    p = torch.zeros_like(ft)
+    mask = torch.zeros(N, N, dtype=torch.uint8, device="cuda")
+    res = lib.cb_solve_indent(plan, ft, d, p, mask, tol=1e-10)
+    assert np.array_equal(mask.cpu().numpy().astype(bool), st.S)
+    e_p = np.linalg.norm(p.cpu().numpy() - st.p) / np.linalg.norm(st.p)
+    print(f"  rounds gpu {res['rounds']} oracle {rounds} e_p {e_p:.2e}")
+    assert e_p < 1e-8 and res["rounds"] == rounds
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adhesive_sweep_short(lib, prec):
+    print(f"sweep {prec}", flush=True)
+    N, L, R = 64, 1.0, 1.0
+    mat = Material(0.05, 1.0, 0.3, 5.0, 0.3)
+    f = inputs.paraboloid(N, L, R)
+    dg = 3e-4
+    steps = list(np.linspace(0, 0.01, 6)[1:]) + list(np.linspace(0.01, -0.01, 9)[1:])
+    op = Operator(N, L, mat)
+    sc = critical_stress(mat, dg, L / N)
+    out, st = sweep(op, f, steps, sc, 1e-12 * L, dg, tol=1e-10)
+    plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, dg, prec)
+    ft = torch.tensor(f, dtype=DT[prec], device="cuda")
+    p = torch.zeros_like(ft)
+    mask = torch.zeros(N, N, dtype=torch.uint8, device="cuda")
+    res = lib.cb_sweep(plan, ft, steps, p, mask, tol=1e-10 if prec == "fp64" else 1e-6)
+    Fspan = max(abs(o["F"]) for o in out)
+    for o, r in zip(out, res):
+        print(f"  d={o['d']:+.4e} F {r['F']:+.6e} vs {o['F']:+.6e} A {r['area']:.5f} vs {o['area']:.5f}")
+        if prec == "fp64":
+            assert r["area"] == pytest.approx(o["area"], abs=1e-15)
+            assert abs(r["F"] - o["F"]) <= 1e-8 * Fspan
+        else:
+            assert abs(r["area"] - o["area"]) <= 0.01 * max(o["area"], 1e-12) + 2 * (L / N) ** 2
+            assert abs(r["F"] - o["F"]) <= 1e-3 * Fspan
+    if prec == "fp64":
+        assert np.array_equal(mask.cpu().numpy().astype(bool), st.S)
+
+
+def test_error_paths(lib):
+    c = inputs.paraboloid_c1()
+    plan = _plan(lib, c, "fp64")
+    f = torch.tensor(c.f, dtype=torch.float64, device="cuda")
+    p = torch.zeros_like(f)
+    res = lib.cb_solve_indent(plan, f, c.target, p, raise_on_error=False, max_iter=1)
+    assert res["status"] == lib.CB_E_NOCONV
+    fbad = f.clone()
+    fbad[3, 3] = float("nan")
+    with pytest.raises(lib.CoatbemError) as e:
+        lib.cb_solve_indent(plan, fbad, c.target, p)
+    assert e.value.status == lib.CB_E_NONFINITE
+    with pytest.raises(lib.CoatbemError) as e:
+        lib.cb_solve_force(plan, f, -1.0, p)
+    assert e.value.status == lib.CB_E_INVALID
+    # no overlap: zero pressure, OK
+    res = lib.cb_solve_indent(plan, f, -1e-3, p)
+    assert res["status"] == 0 and torch.count_nonzero(p).item() == 0
