@@ -1,0 +1,237 @@
+"""Benchmark: contact solves per second at N = 1024 on one MI355X.
+
+Workload (one "step"): the N = 1024 solve set -- 32 force-controlled
+contact problems drawn by the batched recipe (paraboloid / cone / flat
+punch / elliptic punch indenters, coating h/L log-uniform in [1e-3, 0.3],
+E1/E2 log-uniform in [0.01, 100], nu in [0.2, 0.45]), seed 1024, solved
+to relative residual 1e-6 by the FP32 path (FP32 fields and FFT
+convolution, FP64 reductions).  The same set solved by the plain FP64
+path (cold start, residual 1e-10) is timed alongside.
+
+Also measured live: cb_apply_K and its three kernels at N = 1024 (FP32
+and FP64) with HIP events on the plan stream; the roofline object uses
+the dominant kernel's algorithmic bytes per launch over its mean
+duration.  The CPU baseline times the FP64 oracle on the host for a
+bounded number of iterations of the first problem and scales by the
+iteration count that problem needs.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "contact solves/sec at N=1024² (learned+FP32 vs plain FP64); cb_apply_K HBM GB/s"
+PEAK_HBM_GBPS = 8000.0
+
+
+def alg_bytes(N, s):
+    """Algorithmic HBM bytes of the three apply kernels and their sum."""
+    half = 2 * s * N * (N + 1)          # one pass over the complex half spectrum
+    k1 = s * N * N + half
+    k2 = 2 * half + s * (N + 1) ** 2
+    k3 = half + s * N * N
+    return {"k1_rows_fwd": k1, "k2_cols": k2, "k3_rows_inv": k3, "apply": k1 + k2 + k3}
+
+
+def time_apply(cb, plan, p, u, per_graph=50, replays=10):
+    """Mean duration (ms) of cb_apply_K and of each kernel alone.
+
+    The launches are captured into a graph (`per_graph` back-to-back
+    launches on the capture stream, which the plan is pointed at) and the
+    graph is replayed `replays` times between two HIP events recorded on
+    that same stream, so host launch cost does not enter the figure."""
+    import torch
+    out = {}
+    side = torch.cuda.Stream()
+    for name, mask in (("apply", 7), ("k1_rows_fwd", 1), ("k2_cols", 2), ("k3_rows_inv", 4)):
+        cb.cb_apply_K_stages(plan, p, u, mask)          # first call outside capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            cb.cb_plan_set_stream(plan, side)
+            for _ in range(per_graph):
+                cb.cb_apply_K_stages(plan, p, u, mask)
+        cb.cb_plan_set_stream(plan, torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            g.replay()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(side)
+            for _ in range(replays):
+                g.replay()
+            e1.record(side)
+        e1.synchronize()
+        out[name] = e0.elapsed_time(e1) / (replays * per_graph)
+        del g
+    return out
+
+
+def solve_set(cb, plans, fs, ps, cases, tol):
+    res = []
+    for plan, f, p, c in zip(plans, fs, ps, cases):
+        res.append(cb.cb_solve_force(plan, f, c.target, p, tol=tol))
+    return res
+
+
+def cpu_baseline(case, iters_needed, budget_iters):
+    """Oracle FP64 solve of `case` timed for budget_iters iterations, scaled."""
+    import numpy as np  # noqa: F401
+    from oracle import operator as oop
+    from oracle.solvers import solve_pk
+    from oracle.transfer import Material
+    workers = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    op = oop.Operator(case.N, case.L, Material(case.h, case.E1, case.nu1, case.E2, case.nu2),
+                      workers=workers)
+    t0 = time.perf_counter()
+    r = solve_pk(op, case.f, case.target, mode="force", tol=1e-10, max_iter=budget_iters)
+    dt = time.perf_counter() - t0
+    per_iter = dt / max(r.iters, 1)
+    est = per_iter * iters_needed
+    return {"value": 1.0 / est, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": (f"FP64 oracle (numpy/scipy.fft, {workers} workers), first problem of the N=1024 "
+                       f"set, {r.iters} iterations in {dt:.1f} s = {per_iter*1e3:.1f} ms/iteration, "
+                       f"scaled by the {iters_needed} iterations the FP64 solve of that problem needs")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-solves", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--dump", default=None, help="write per-problem results (JSON) here")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(independent solves would shard by problem across GPUs)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1807_01885_amd import coatbem as cb
+    from paper_1807_01885_amd import inputs
+
+    torch.cuda.set_device(0)
+    cases = inputs.headline_set(n=args.n_solves)
+    N = cases[0].N
+
+    def make(prec):
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        plans = [cb.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, prec) for c in cases]
+        fs = [torch.tensor(c.f, dtype=dt, device="cuda") for c in cases]
+        ps = [torch.zeros(c.N, c.N, dtype=dt, device="cuda") for c in cases]
+        return plans, fs, ps
+
+    plans32, fs32, ps32 = make("fp32")
+    plans64, fs64, ps64 = make("fp64")
+    torch.cuda.synchronize()
+
+    # ---- FP32 path (timed steps) --------------------------------------------
+    tol32, tol64 = 1e-6, 1e-10
+    for _ in range(args.warmup):
+        solve_set(cb, plans32, fs32, ps32, cases, tol32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res32 = solve_set(cb, plans32, fs32, ps32, cases, tol32)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    value = len(cases) * args.steps / t32
+
+    # ---- plain FP64 path (one timed step) -------------------------------------
+    solve_set(cb, plans64[:2], fs64[:2], ps64[:2], cases[:2], tol64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res64 = solve_set(cb, plans64, fs64, ps64, cases, tol64)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    value64 = len(cases) / t64
+
+    # ---- accuracy of the FP32 path against the FP64 path ----------------------
+    ep, eF, agr = [], [], []
+    for a, b, ra, rb in zip(ps32, ps64, res32, res64):
+        a = a.double()
+        ep.append((torch.linalg.norm(a - b) / torch.linalg.norm(b)).item())
+        eF.append(abs(ra["F"] - rb["F"]) / rb["F"])
+        sa, sb = a > 0, b > 0
+        uni = (sa | sb).sum().item()
+        agr.append(1.0 - (sa ^ sb).sum().item() / max(uni, 1))
+
+    # ---- apply_K roofline -------------------------------------------------------
+    dev = "cuda"
+    rng = np.random.default_rng(0)
+    pr = rng.standard_normal((N, N))
+    timing = {}
+    for prec, plans, s in (("fp32", plans32, 4), ("fp64", plans64, 8)):
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        p = torch.tensor(pr, dtype=dt, device=dev)
+        u = torch.empty_like(p)
+        ms = time_apply(cb, plans[0], p, u)
+        ab = alg_bytes(N, s)
+        timing[prec] = {k: {"ms": ms[k], "GBps": ab[k] / (ms[k] * 1e-3) / 1e9, "bytes": ab[k]} for k in ms}
+    t32k = timing["fp32"]
+    dom = max(("k1_rows_fwd", "k2_cols", "k3_rows_inv"), key=lambda k: t32k[k]["ms"])
+    ach = t32k[dom]["GBps"]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBPS, "traffic": None,
+            "bytes_per_launch": t32k[dom]["bytes"], "mean_launch_ms": t32k[dom]["ms"]}
+
+    if args.dump:
+        rows = []
+        for c, ra, rb, e1, e2, e3 in zip(cases, res32, res64, ep, eF, agr):
+            rows.append(dict(shape=c.shape, h=c.h, E1=c.E1, nu1=c.nu1, nu2=c.nu2, F=c.target,
+                             it32=ra["iters"], it64=rb["iters"], st32=ra["status"], st64=rb["status"],
+                             res32=ra["resid"], res64=rb["resid"], ms32=ra["ms"], ms64=rb["ms"],
+                             area=rb["area"], d=rb["d"], ep=e1, eF=e2, agr=e3))
+        with open(args.dump, "w") as fh:
+            json.dump(rows, fh, indent=1)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(cases[0], res64[0]["iters"], args.cpu_iters)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{len(cases)} force-controlled contact solves at N={N} (padded {2*N}^2 FFT), "
+                         "batched recipe seed 1024, FP32 fields/FFT + FP64 reductions, residual 1e-6, cold start"),
+            "N": N, "solves_per_step": len(cases), "tol": tol32,
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "plain_fp64": {"value": value64, "unit": "solves/s", "tol": tol64,
+                       "mean_iters": float(np.mean([r["iters"] for r in res64]))},
+        "fp32_mean_iters": float(np.mean([r["iters"] for r in res32])),
+        "fp32_vs_fp64": {"max_rel_L2_p": max(ep), "max_rel_F": max(eF), "min_set_agreement": min(agr)},
+        "apply_K": {prec: {k: {"ms": round(v["ms"], 5), "GBps": round(v["GBps"], 1)} for k, v in t.items()}
+                    for prec, t in timing.items()},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -159,6 +159,16 @@ int cb_plan_set_stream(cb_plan plan, void* stream);
 int cb_apply_K(cb_plan plan, const void* p, void* u);
 
 /*
+ * cb_apply_K_stages -- diagnostic form of cb_apply_K that launches only the
+ *   stages selected in stage_mask: 1 = forward row transform (p -> plan
+ *   intermediate), 2 = column transform with the transfer multiply (in place
+ *   on the intermediate), 4 = inverse row transform (intermediate -> u).
+ *   stage_mask = 7 is cb_apply_K.  For timing single kernels; p or u may be
+ *   NULL when the stages that use them are not selected.
+ */
+int cb_apply_K_stages(cb_plan plan, const void* p, void* u, int stage_mask);
+
+/*
  * cb_solve_indent -- non-adhesive (dgamma = 0) or adhesive (dgamma > 0)
  *   contact at prescribed rigid approach d.
  *   Non-adhesive: the complementarity problem p >= 0, g >= 0, p g = 0 by

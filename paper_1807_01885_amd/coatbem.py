@@ -88,6 +88,7 @@ _SIGS = {
     "cb_plan_set_stream": (_i, [_vp, _vp]),
     "cb_transfer_table": (_i, [_i, _d, _d, _d, _d, _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "cb_apply_K": (_i, [_vp, _vp, _vp]),
+    "cb_apply_K_stages": (_i, [_vp, _vp, _vp, _i]),
     "cb_solve_indent": (_i, [_vp, _vp, _d, _vp, _vp, ctypes.POINTER(cb_solve_opts),
                              ctypes.POINTER(cb_result)]),
     "cb_solve_force": (_i, [_vp, _vp, _d, _vp, _vp, ctypes.POINTER(cb_solve_opts),
@@ -213,6 +214,12 @@ def _opts(tol=0.0, max_iter=0, chunk=0, init=0, attach_tol=-1.0, max_rounds=0):
 def cb_apply_K(plan: Plan, p, u):
     _check(_lib.cb_apply_K(plan.handle, _arr(plan, p, "p"), _arr(plan, u, "u")))
     return u
+
+
+def cb_apply_K_stages(plan: Plan, p, u, stage_mask):
+    pp = _arr(plan, p, "p") if p is not None else None
+    uu = _arr(plan, u, "u") if u is not None else None
+    _check(_lib.cb_apply_K_stages(plan.handle, pp, uu, int(stage_mask)))
 
 
 def cb_solve_indent(plan: Plan, f, d, p, mask=None, raise_on_error=True, **opts):

@@ -299,7 +299,7 @@ static size_t lds_cols(int CB) {
 }
 
 template <typename T, int LOG2N>
-static hipError_t apply_impl(const T* p, T* u, cx<T>* S, const T* Tq, const cx<T>* tw,
+static hipError_t apply_impl(int stages, const T* p, T* u, cx<T>* S, const T* Tq, const cx<T>* tw,
                              hipStream_t st) {
   using SH = Shape<LOG2N>;
   constexpr int N = SH::N, RB = row_tile<T>();
@@ -319,33 +319,33 @@ static hipError_t apply_impl(const T* p, T* u, cx<T>* S, const T* Tq, const cx<T
   }
   const int nb_rows = N / (RB * G);
   const int nb_cols = (NC + SH::CB - 1) / SH::CB;
-  hipLaunchKernelGGL(k1, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw);
-  hipLaunchKernelGGL(k2, dim3(nb_cols), dim3(SH::CB * SH::NT2), lc, st, S, Tq, tw);
-  hipLaunchKernelGGL(k3, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw);
+  if (stages & 1) hipLaunchKernelGGL(k1, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw);
+  if (stages & 2) hipLaunchKernelGGL(k2, dim3(nb_cols), dim3(SH::CB * SH::NT2), lc, st, S, Tq, tw);
+  if (stages & 4) hipLaunchKernelGGL(k3, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw);
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t apply_dispatch(int log2n, const T* p, T* u, cx<T>* S, const T* Tq,
+static hipError_t apply_dispatch(int stages, int log2n, const T* p, T* u, cx<T>* S, const T* Tq,
                                  const cx<T>* tw, hipStream_t st) {
   switch (log2n) {
-    case 4: return apply_impl<T, 4>(p, u, S, Tq, tw, st);
-    case 5: return apply_impl<T, 5>(p, u, S, Tq, tw, st);
-    case 6: return apply_impl<T, 6>(p, u, S, Tq, tw, st);
-    case 7: return apply_impl<T, 7>(p, u, S, Tq, tw, st);
-    case 8: return apply_impl<T, 8>(p, u, S, Tq, tw, st);
-    case 9: return apply_impl<T, 9>(p, u, S, Tq, tw, st);
-    case 10: return apply_impl<T, 10>(p, u, S, Tq, tw, st);
-    case 11: return apply_impl<T, 11>(p, u, S, Tq, tw, st);
+    case 4: return apply_impl<T, 4>(stages, p, u, S, Tq, tw, st);
+    case 5: return apply_impl<T, 5>(stages, p, u, S, Tq, tw, st);
+    case 6: return apply_impl<T, 6>(stages, p, u, S, Tq, tw, st);
+    case 7: return apply_impl<T, 7>(stages, p, u, S, Tq, tw, st);
+    case 8: return apply_impl<T, 8>(stages, p, u, S, Tq, tw, st);
+    case 9: return apply_impl<T, 9>(stages, p, u, S, Tq, tw, st);
+    case 10: return apply_impl<T, 10>(stages, p, u, S, Tq, tw, st);
+    case 11: return apply_impl<T, 11>(stages, p, u, S, Tq, tw, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st) {
+hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages) {
   if (P->precision == 0)
-    return apply_dispatch<double>(P->log2n, (const double*)p, (double*)u, (cx<double>*)P->d_S,
+    return apply_dispatch<double>(stages, P->log2n, (const double*)p, (double*)u, (cx<double>*)P->d_S,
                                   (const double*)P->d_table, (const cx<double>*)P->d_tw, st);
-  return apply_dispatch<float>(P->log2n, (const float*)p, (float*)u, (cx<float>*)P->d_S,
+  return apply_dispatch<float>(stages, P->log2n, (const float*)p, (float*)u, (cx<float>*)P->d_S,
                                (const float*)P->d_table, (const cx<float>*)P->d_tw, st);
 }
 

@@ -58,7 +58,7 @@ struct cb_plan_s {
 };
 
 namespace cb {
-hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st);
+hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages = 7);
 size_t intermediate_elems(int N);
 }  // namespace cb
 

@@ -370,3 +370,11 @@ extern "C" int cb_apply_K(cb_plan P, const void* p, void* u) {
   CB_HIP(cb::launch_apply(P, p, u, P->stream));
   return CB_OK;
 }
+
+extern "C" int cb_apply_K_stages(cb_plan P, const void* p, void* u, int stages) {
+  if (!P) return cb_fail(CB_E_INVALID, "null plan");
+  if (stages < 0 || stages > 7) return cb_fail(CB_E_INVALID, "stage_mask must be in [0, 7]");
+  if (((stages & 1) && !p) || ((stages & 4) && !u)) return cb_fail(CB_E_INVALID, "null array");
+  CB_HIP(cb::launch_apply(P, p, u, P->stream, stages));
+  return CB_OK;
+}
