@@ -16,9 +16,11 @@
  *     u is the surface displacement into the body; f >= 0 is the indenter
  *     profile; d is the rigid approach (positive into the body); the gap is
  *     g = f - d + u; the total force is F = Delta^2 * sum(p).
- *   - Element type of every caller array (p, u, f, state) is the plan's
- *     precision: double for CB_FP64, float for CB_FP32.  Masks are uint8,
- *     1 = in contact.
+ *   - cb_apply_K takes p and u in the plan's precision (double for CB_FP64,
+ *     float for CB_FP32).  The solve and sweep calls take f, p and the
+ *     sweep state as double for every plan: the solution state is kept in
+ *     FP64, and CB_FP32 plans run the convolutions of the search directions
+ *     in FP32 (see cb_plan_opts.precision).  Masks are uint8, 1 = in contact.
  *   - Every array pointer is a DEVICE pointer on the plan's device unless
  *     the name says _host.  The caller owns every array; the library never
  *     frees or retains caller memory beyond the call.  The library owns the
@@ -57,8 +59,12 @@ enum { CB_DC_BZ = 0, CB_DC_ZERO = 1 };
 
 /* Plan options; a NULL pointer selects every default. */
 typedef struct {
-  int precision;   /* CB_FP64 (default) or CB_FP32: FP32 convolution and
-                      FP32 fields with FP64 reductions and scalars */
+  int precision;   /* CB_FP64 (default) or CB_FP32.  CB_FP32: cb_apply_K is
+                      an FP32 convolution; the solvers keep p, u = K p, f,
+                      the gap and every reduction in FP64 and run the
+                      search-direction convolutions in FP32, recomputing u
+                      from p with an FP64 convolution whenever the contact
+                      set changes and every `chunk` iterations */
   int dc_mode;     /* CB_DC_BZ (default): the k = 0 value of the transfer
                       function makes the frequency sum equal its integral
                       over the Brillouin zone [-pi/Delta, pi/Delta]^2;
@@ -72,15 +78,21 @@ typedef struct {
 
 /* Solve options; a NULL pointer selects every default. */
 typedef struct {
-  double tol;        /* relative residual target; <= 0: 1e-10 (FP64), 1e-6 (FP32) */
+  double tol;        /* relative residual target; <= 0: 1e-10 (FP64), 1e-8 (FP32) */
   int max_iter;      /* conjugate-gradient iteration limit per solve; <= 0: 20000 */
   int chunk;         /* iterations run on the device between host checks of
                         the convergence flag; <= 0: 16 */
   int init;          /* 0: cold start; 1: the caller's p_io is the initial guess */
   double attach_tol; /* adhesive: a cell outside the contact attaches when
                         its gap is below -attach_tol (length); < 0: 1e-12 L
-                        (FP64), 1e-6 L (FP32) */
+                        (FP64), 1e-9 L (FP32) */
   int max_rounds;    /* adhesive detach/attach rounds per step; <= 0: 10000 */
+  int precond;       /* non-adhesive solves: -1 (default) automatic, 0 plain
+                        conjugate gradients, 1 gradients preconditioned by the
+                        Fourier multiplier 1/C(kh) = 2/(E1* k K^(k)), which
+                        removes the layer's stiffness contrast; automatic turns
+                        it on for coatings >= 3x stiffer than the substrate
+                        with h <= L/16.  The converged pressure is the same. */
 } cb_solve_opts;
 
 /* Per-solve (or per-step) outcome, filled on the host. */
@@ -180,7 +192,7 @@ int cb_apply_K_stages(cb_plan plan, const void* p, void* u, int stage_mask);
  *   f: profile; p_io: output pressure (input guess when opts->init = 1);
  *   mask_io: optional (NULL) output contact set.  res: host, required.
  */
-int cb_solve_indent(cb_plan plan, const void* f, double d, void* p_io,
+int cb_solve_indent(cb_plan plan, const double* f, double d, double* p_io,
                     unsigned char* mask_io, const cb_solve_opts* opts,
                     cb_result* res);
 
@@ -188,7 +200,7 @@ int cb_solve_indent(cb_plan plan, const void* f, double d, void* p_io,
  * cb_solve_force -- non-adhesive contact at prescribed total force F > 0;
  *   res->d returns the approach found.  Adhesive plans: CB_E_UNSUPPORTED.
  */
-int cb_solve_force(cb_plan plan, const void* f, double F, void* p_io,
+int cb_solve_force(cb_plan plan, const double* f, double F, double* p_io,
                    unsigned char* mask_io, const cb_solve_opts* opts,
                    cb_result* res);
 
@@ -201,8 +213,8 @@ int cb_solve_force(cb_plan plan, const void* f, double F, void* p_io,
  *   so a sweep can be resumed by calling again with the same state.
  *   Zero both for a fresh start.  per_step_host: nsteps results.
  */
-int cb_sweep(cb_plan plan, const void* f, const double* d_steps_host,
-             int nsteps, void* p_state, unsigned char* mask_state,
+int cb_sweep(cb_plan plan, const double* f, const double* d_steps_host,
+             int nsteps, double* p_state, unsigned char* mask_state,
              const cb_solve_opts* opts, cb_result* per_step_host);
 
 /* Status text; cb_last_error: last error message of this thread. */

@@ -46,7 +46,8 @@ class cb_plan_opts(ctypes.Structure):
 class cb_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("chunk", ctypes.c_int), ("init", ctypes.c_int),
-                ("attach_tol", ctypes.c_double), ("max_rounds", ctypes.c_int)]
+                ("attach_tol", ctypes.c_double), ("max_rounds", ctypes.c_int),
+                ("precond", ctypes.c_int)]
 
 
 class cb_result(ctypes.Structure):
@@ -206,9 +207,9 @@ def _arr(plan: Plan, x, name, dtype=None):
     return ctypes.c_void_p(x.data_ptr())
 
 
-def _opts(tol=0.0, max_iter=0, chunk=0, init=0, attach_tol=-1.0, max_rounds=0):
+def _opts(tol=0.0, max_iter=0, chunk=0, init=0, attach_tol=-1.0, max_rounds=0, precond=-1):
     return cb_solve_opts(float(tol), int(max_iter), int(chunk), int(init),
-                         float(attach_tol), int(max_rounds))
+                         float(attach_tol), int(max_rounds), int(precond))
 
 
 def cb_apply_K(plan: Plan, p, u):
@@ -223,9 +224,11 @@ def cb_apply_K_stages(plan: Plan, p, u, stage_mask):
 
 
 def cb_solve_indent(plan: Plan, f, d, p, mask=None, raise_on_error=True, **opts):
+    """f, p: float64 for every plan (the solution state is FP64)."""
     res = cb_result()
     m = _arr(plan, mask, "mask", torch.uint8) if mask is not None else None
-    rc = _lib.cb_solve_indent(plan.handle, _arr(plan, f, "f"), float(d), _arr(plan, p, "p"),
+    rc = _lib.cb_solve_indent(plan.handle, _arr(plan, f, "f", torch.float64), float(d),
+                              _arr(plan, p, "p", torch.float64),
                               m, ctypes.byref(_opts(**opts)), ctypes.byref(res))
     if raise_on_error:
         _check(rc)
@@ -233,9 +236,11 @@ def cb_solve_indent(plan: Plan, f, d, p, mask=None, raise_on_error=True, **opts)
 
 
 def cb_solve_force(plan: Plan, f, F, p, mask=None, raise_on_error=True, **opts):
+    """f, p: float64 for every plan (the solution state is FP64)."""
     res = cb_result()
     m = _arr(plan, mask, "mask", torch.uint8) if mask is not None else None
-    rc = _lib.cb_solve_force(plan.handle, _arr(plan, f, "f"), float(F), _arr(plan, p, "p"),
+    rc = _lib.cb_solve_force(plan.handle, _arr(plan, f, "f", torch.float64), float(F),
+                             _arr(plan, p, "p", torch.float64),
                              m, ctypes.byref(_opts(**opts)), ctypes.byref(res))
     if raise_on_error:
         _check(rc)
@@ -246,7 +251,8 @@ def cb_sweep(plan: Plan, f, d_steps, p_state, mask_state, raise_on_error=True, *
     n = len(d_steps)
     steps = (ctypes.c_double * n)(*[float(x) for x in d_steps])
     out = (cb_result * max(n, 1))()
-    rc = _lib.cb_sweep(plan.handle, _arr(plan, f, "f"), steps, n, _arr(plan, p_state, "p_state"),
+    rc = _lib.cb_sweep(plan.handle, _arr(plan, f, "f", torch.float64), steps, n,
+                       _arr(plan, p_state, "p_state", torch.float64),
                        _arr(plan, mask_state, "mask_state", torch.uint8),
                        ctypes.byref(_opts(**opts)), out)
     if raise_on_error:

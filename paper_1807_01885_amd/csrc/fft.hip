@@ -27,7 +27,9 @@ constexpr int PS = 4;  // LDS padding shift
 // ---------------------------------------------------------------------------
 template <typename T, int LOG2N, int RB, int NT1, int G>
 __global__ void __launch_bounds__(G * RB * NT1)
-k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restrict__ tw_g) {
+k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restrict__ tw_g,
+           const int* __restrict__ skip) {
+  if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
   constexpr int N = 1 << LOG2N, M = 2 * N, L = N, NC = N + 1;
   constexpr int ROWS = G * RB, NTH = ROWS * NT1, E = L / NT1;
@@ -38,14 +40,12 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
   C* buf = tws + TW::NLO + TW::NHI;
 
   const int tid = threadIdx.x;
-  TW::stage(tws, tw_g, tid, NTH);
-  const TW tw{tws, tws + TW::NLO};
   const int lrow = tid / NT1, t = tid % NT1;
   const int row0 = blockIdx.x * ROWS;
   C* line = buf + lrow * LP;
-  __syncthreads();
 
-  // first pass (Ls = 1): packed inputs z[n], n < N/2, from global
+  // first pass (Ls = 1): packed inputs z[n], n < N/2, from global; the
+  // loads are issued before the twiddle tables are built
   {
     constexpr int R = pick_radix(L, E, 1);
     constexpr int NB = L / (R * NT1);
@@ -57,6 +57,7 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
 #pragma unroll
       for (int i = 0; i < R; i++) a[b][i] = (i < R / 2) ? z[j + i * (L / R)] : C{T(0), T(0)};
     }
+    TW::compute(tws, tid, NTH);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = t + b * NT1;
@@ -65,27 +66,32 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
       for (int i = 0; i < R; i++) line[padi<PS>(out_index<R, 1>(j, i))] = a[b][i];
     }
     __syncthreads();
-    MidPasses<T, L, M, NT1, 1, PS, R, L>::run(line, t, tw);
   }
+  const TW tw{tws, tws + TW::NLO};
+  MidPasses<T, L, M, NT1, 1, PS, pick_radix(L, E, 1), L>::run(line, t, tw);
 
   // split into the half spectrum of the length-M real transform:
   // X[k] = (Z[k] + conj Z[N-k])/2 - i/2 W^k (Z[k] - conj Z[N-k]),
   // W = exp(-2 pi i / M), k in [0, N]; items in tile order (k major, rr minor)
   constexpr int ITEMS = G * NC * RB;
   C* out = S + (size_t)blockIdx.x * ITEMS;
-  for (int q = tid; q < ITEMS; q += NTH) {
-    const int g = q / (NC * RB);
-    const int qq = q - g * (NC * RB);
-    const int k = qq / RB;
-    const int rr = qq - k * RB;
-    const C* ln = buf + (g * RB + rr) * LP;
-    const C zk = ln[padi<PS>(k & (N - 1))];
-    const C zn = cconj(ln[padi<PS>((N - k) & (N - 1))]);
-    const C e = cscale(cadd(zk, zn), T(0.5));
-    const C o = cscale(csub(zk, zn), T(0.5));  // times -i below
-    const C w = tw.get(k);
-    const C wo = cmul(w, mul_mi<1>(o));
-    out[q] = cadd(e, wo);
+#pragma unroll
+  for (int it = 0; it < (ITEMS + NTH - 1) / NTH; it++) {
+    const int q = tid + it * NTH;
+    if (q < ITEMS) {
+      const int g = q / (NC * RB);
+      const int qq = q - g * (NC * RB);
+      const int k = qq / RB;
+      const int rr = qq - k * RB;
+      const C* ln = buf + (g * RB + rr) * LP;
+      const C zk = ln[padi<PS>(k & (N - 1))];
+      const C zn = cconj(ln[padi<PS>((N - k) & (N - 1))]);
+      const C e = cscale(cadd(zk, zn), T(0.5));
+      const C o = cscale(csub(zk, zn), T(0.5));  // times -i below
+      const C w = tw.get(k);
+      const C wo = cmul(w, mul_mi<1>(o));
+      out[q] = cadd(e, wo);
+    }
   }
 }
 
@@ -94,7 +100,9 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
 // ---------------------------------------------------------------------------
 template <typename T, int LOG2N, int RB, int NT2, int CB>
 __global__ void __launch_bounds__(CB * NT2)
-k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict__ tw_g) {
+k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict__ tw_g,
+       const int* __restrict__ skip) {
+  if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
   constexpr int N = 1 << LOG2N, M = 2 * N, L = M, NC = N + 1;
   constexpr int NTH = CB * NT2, E = L / NT2;
@@ -106,17 +114,16 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
   C* buf = tws + TW::NLO + TW::NHI;
 
   const int tid = threadIdx.x;
-  TW::stage(tws, tw_g, tid, NTH);
   const TW tw{tws, tws + TW::NLO};
   const int lc = tid / NT2, t = tid % NT2;
   const int kx = xcd_block(blockIdx.x, NBLK) * CB + lc;
   const bool active = kx < NC;
   C* line = buf + lc * LP;
-  __syncthreads();
 
   constexpr int R0 = pick_radix(L, E, 1);
   constexpr int RL = last_radix(L, E);
-  // forward first pass, inputs rows n < N from the tiles (upper half zero)
+  // forward first pass, inputs rows n < N from the tiles (upper half zero);
+  // the loads are issued before the twiddle tables are built
   {
     constexpr int NB = L / (R0 * NT2);
     C a[NB][R0];
@@ -131,6 +138,7 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
                       : C{T(0), T(0)};
       }
     }
+    TW::compute(tws, tid, NTH);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = t + b * NT2;
@@ -202,7 +210,9 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
 // ---------------------------------------------------------------------------
 template <typename T, int LOG2N, int RB, int NT1, int G>
 __global__ void __launch_bounds__(G * RB * NT1)
-k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restrict__ tw_g) {
+k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restrict__ tw_g,
+           const int* __restrict__ skip) {
+  if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
   constexpr int N = 1 << LOG2N, M = 2 * N, L = N, NC = N + 1;
   constexpr int ROWS = G * RB, NTH = ROWS * NT1, E = L / NT1;
@@ -213,21 +223,37 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
   C* buf = tws + TW::NLO + TW::NHI;
 
   const int tid = threadIdx.x;
-  TW::stage(tws, tw_g, tid, NTH);
   const TW tw{tws, tws + TW::NLO};
   constexpr int ITEMS = G * NC * RB;
+  constexpr int NIT = (ITEMS + NTH - 1) / NTH;
   const C* in = S + (size_t)blockIdx.x * ITEMS;
-  for (int q = tid; q < ITEMS; q += NTH) {
-    const int g = q / (NC * RB);
-    const int qq = q - g * (NC * RB);
-    const int k = qq / RB;
-    const int rr = qq - k * RB;
-    buf[(g * RB + rr) * LP + padi<PS>(k)] = in[q];
+  {
+    C v[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+      const int q = tid + it * NTH;
+      if (q < ITEMS) v[it] = in[q];
+    }
+    TW::compute(tws, tid, NTH);
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+      const int q = tid + it * NTH;
+      if (q < ITEMS) {
+        const int g = q / (NC * RB);
+        const int qq = q - g * (NC * RB);
+        const int k = qq / RB;
+        const int rr = qq - k * RB;
+        buf[(g * RB + rr) * LP + padi<PS>(k)] = v[it];
+      }
+    }
   }
   __syncthreads();
   // Z[k] = (X[k] + conj X[N-k]) + i W^-k (X[k] - conj X[N-k]), pairs (k, N-k)
   constexpr int PAIRS = N / 2 + 1;
-  for (int q = tid; q < ROWS * PAIRS; q += NTH) {
+#pragma unroll
+  for (int it = 0; it < (ROWS * PAIRS + NTH - 1) / NTH; it++) {
+    const int q = tid + it * NTH;
+    if (q >= ROWS * PAIRS) break;
     const int lr = q / PAIRS;
     const int k = q - lr * PAIRS;
     C* ln = buf + lr * LP;
@@ -299,7 +325,7 @@ static size_t lds_cols(int CB) {
 }
 
 template <typename T, int LOG2N>
-static hipError_t apply_impl(int stages, const T* p, T* u, cx<T>* S, const T* Tq, const cx<T>* tw,
+static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T>* S, const T* Tq, const cx<T>* tw,
                              hipStream_t st) {
   using SH = Shape<LOG2N>;
   constexpr int N = SH::N, RB = row_tile<T>();
@@ -319,36 +345,65 @@ static hipError_t apply_impl(int stages, const T* p, T* u, cx<T>* S, const T* Tq
   }
   const int nb_rows = N / (RB * G);
   const int nb_cols = (NC + SH::CB - 1) / SH::CB;
-  if (stages & 1) hipLaunchKernelGGL(k1, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw);
-  if (stages & 2) hipLaunchKernelGGL(k2, dim3(nb_cols), dim3(SH::CB * SH::NT2), lc, st, S, Tq, tw);
-  if (stages & 4) hipLaunchKernelGGL(k3, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw);
+  if (stages & 1) hipLaunchKernelGGL(k1, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw, skip);
+  if (stages & 2) hipLaunchKernelGGL(k2, dim3(nb_cols), dim3(SH::CB * SH::NT2), lc, st, S, Tq, tw, skip);
+  if (stages & 4) hipLaunchKernelGGL(k3, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw, skip);
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t apply_dispatch(int stages, int log2n, const T* p, T* u, cx<T>* S, const T* Tq,
+static hipError_t apply_dispatch(int stages, const int* skip, int log2n, const T* p, T* u, cx<T>* S, const T* Tq,
                                  const cx<T>* tw, hipStream_t st) {
   switch (log2n) {
-    case 4: return apply_impl<T, 4>(stages, p, u, S, Tq, tw, st);
-    case 5: return apply_impl<T, 5>(stages, p, u, S, Tq, tw, st);
-    case 6: return apply_impl<T, 6>(stages, p, u, S, Tq, tw, st);
-    case 7: return apply_impl<T, 7>(stages, p, u, S, Tq, tw, st);
-    case 8: return apply_impl<T, 8>(stages, p, u, S, Tq, tw, st);
-    case 9: return apply_impl<T, 9>(stages, p, u, S, Tq, tw, st);
-    case 10: return apply_impl<T, 10>(stages, p, u, S, Tq, tw, st);
-    case 11: return apply_impl<T, 11>(stages, p, u, S, Tq, tw, st);
+    case 4: return apply_impl<T, 4>(stages, skip, p, u, S, Tq, tw, st);
+    case 5: return apply_impl<T, 5>(stages, skip, p, u, S, Tq, tw, st);
+    case 6: return apply_impl<T, 6>(stages, skip, p, u, S, Tq, tw, st);
+    case 7: return apply_impl<T, 7>(stages, skip, p, u, S, Tq, tw, st);
+    case 8: return apply_impl<T, 8>(stages, skip, p, u, S, Tq, tw, st);
+    case 9: return apply_impl<T, 9>(stages, skip, p, u, S, Tq, tw, st);
+    case 10: return apply_impl<T, 10>(stages, skip, p, u, S, Tq, tw, st);
+    case 11: return apply_impl<T, 11>(stages, skip, p, u, S, Tq, tw, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages) {
-  if (P->precision == 0)
-    return apply_dispatch<double>(stages, P->log2n, (const double*)p, (double*)u, (cx<double>*)P->d_S,
-                                  (const double*)P->d_table, (const cx<double>*)P->d_tw, st);
-  return apply_dispatch<float>(stages, P->log2n, (const float*)p, (float*)u, (cx<float>*)P->d_S,
-                               (const float*)P->d_table, (const cx<float>*)P->d_tw, st);
+hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages,
+                        const int* skip, const void* table, int prec) {
+  if (prec < 0) prec = P->precision;
+  if (prec == 0) {
+    if (!table) table = P->precision == 0 ? P->d_table : P->d_table64;
+    return apply_dispatch<double>(stages, skip, P->log2n, (const double*)p, (double*)u, (cx<double>*)P->d_S,
+                                  (const double*)table, nullptr, st);
+  }
+  if (!table) table = P->d_table;
+  return apply_dispatch<float>(stages, skip, P->log2n, (const float*)p, (float*)u, (cx<float>*)P->d_S,
+                               (const float*)table, nullptr, st);
 }
 
 size_t intermediate_elems(int N) { return (size_t)N * (N + 1); }
+
+// Set the dynamic-LDS attributes of every convolution kernel of this size
+// (both precisions) up front, so that no attribute call happens while a
+// stream is being captured.
+template <int LOG2N>
+static void prepare_n() {
+  float* nf = nullptr;
+  double* nd = nullptr;
+  (void)apply_impl<float, LOG2N>(0, nullptr, nf, nf, nullptr, nullptr, nullptr, nullptr);
+  (void)apply_impl<double, LOG2N>(0, nullptr, nd, nd, nullptr, nullptr, nullptr, nullptr);
+}
+void prepare_apply(int log2n) {
+  switch (log2n) {
+    case 4: prepare_n<4>(); break;
+    case 5: prepare_n<5>(); break;
+    case 6: prepare_n<6>(); break;
+    case 7: prepare_n<7>(); break;
+    case 8: prepare_n<8>(); break;
+    case 9: prepare_n<9>(); break;
+    case 10: prepare_n<10>(); break;
+    case 11: prepare_n<11>(); break;
+    default: break;
+  }
+}
 
 }  // namespace cb

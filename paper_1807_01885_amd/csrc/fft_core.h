@@ -95,9 +95,15 @@ struct Tw {
     if constexpr (LT <= 64) return lo[e];
     else return cmul(hi[e >> 6], lo[e & 63]);
   }
-  // cooperative copy of the global tables (lo then hi) into LDS
-  __device__ __forceinline__ static void stage(cx<T>* dst, const cx<T>* __restrict__ src, int tid, int nthreads) {
-    for (int i = tid; i < NLO + NHI; i += nthreads) dst[i] = src[i];
+  // cooperative evaluation of both tables into LDS (lo then hi), in FP64
+  // (sincospi of an exact binary fraction) rounded once to T
+  __device__ __forceinline__ static void compute(cx<T>* dst, int tid, int nthreads) {
+    for (int i = tid; i < NLO + NHI; i += nthreads) {
+      const int e = i < NLO ? i : 64 * (i - NLO);
+      double s, c;
+      sincospi(2.0 * (double)e / (double)LT, &s, &c);
+      dst[i] = cx<T>{T(c), T(-s)};
+    }
   }
 };
 

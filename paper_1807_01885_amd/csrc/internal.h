@@ -7,27 +7,54 @@
 
 #include "../../include/coatbem.h"
 
-// Device-resident scalar state of one iterative solve.  Kernels read and
-// write it so that a whole chunk of iterations runs without host traffic.
+// Device-resident scalar state of one iterative solve.  The host writes the
+// inputs before a solve; kernels carry the iteration scalars so that a whole
+// chunk of iterations runs (as one captured graph) without host traffic.
 struct SolverState {
-  double G_old;      // previous sum of squared gaps on the contact set
-  double delta;      // 1: conjugate direction kept, 0: restart
-  double tau;        // step length of the current iteration
-  double d;          // rigid approach (prescribed, or found under force control)
-  double gbar;       // mean gap on the contact set (force control)
-  double rmean;      // mean of K t on the contact set (force control)
+  // inputs
+  double tol;        // relative residual target
+  double Ftarget;    // force control: total force
+  double dA;         // cell area Delta^2
+  double k00;        // self-influence (fallback step length 1/k00)
+  double d_in;       // displacement control: rigid approach
+  int force;         // 1: force control
+  int pad0;
+  // carried / outputs
+  double d;          // rigid approach (found under force control)
+  double gbar;       // force control: shift used by the next gap kernel
+  double gdev;       // stored gap minus true gap in the current iteration
   double resid;      // relative residual of the last check
-  double F;          // current total force
-  double rr;         // masked CG: r.r
-  double bnorm;      // masked CG: ||b||
-  int done;          // 1 once converged (kernels of later iterations exit)
+  double bnorm;      // fixed-set CG: ||b||
+  double nact;       // |Ic| of the current iteration
+  // skip_u, done, zero are adjacent: a convolution kernel given &skip_u
+  // returns if either of the first two is set, given &done if done is set
+  int skip_u;        // 1: u was updated linearly, its recomputation is skipped
+  int done;          // 1 once converged: kernels of later iterations return
+  int zero;          // always 0
   int iters;         // iterations performed
   int nonfinite;     // 1 if a NaN/Inf was met
-  int viol;          // penetrating cells outside the contact at last check
-  int nactive;       // |Ic|
-  int changed;       // adhesive: cells that changed state in the last round
-  int pad[2];
+  int breakdown;     // fixed-set CG: non-positive curvature met
 };
+
+// Partial-sum regions (doubles) in the plan's reduction buffer: each holds
+// an 8-double header and up to RED_BLOCKS_MAX x 8 block partials.
+enum {
+  R_GAP0 = 0, R_GAP1, R_STEP, R_UPD, R_RR0, R_RR1, R_ZQ, R_INIT, R_MISC, R_PZ0, R_PZ1, R_NUM
+};
+constexpr int RED_BLOCKS_MAX = 256;
+constexpr int REG_STRIDE = 8 + 8 * RED_BLOCKS_MAX;
+constexpr int SCRATCH_OFF = R_NUM * REG_STRIDE;   // 32 doubles of host-read results
+
+struct GraphEntry {
+  int kind = -1;          // 0: constrained CG chunk, 1: fixed-set CG chunk
+  const void* a = nullptr;
+  const void* b = nullptr;
+  const void* c = nullptr;
+  int chunk = 0;
+  hipGraphExec_t exec = nullptr;
+  unsigned long long used = 0;
+};
+constexpr int GRAPH_CACHE = 6;
 
 struct cb_plan_s {
   int N = 0, M = 0, log2n = 0, precision = 0, dc_mode = 0;
@@ -39,7 +66,9 @@ struct cb_plan_s {
   std::vector<double> table64;   // (N+1)^2, no 1/M^2
   // device memory owned by the plan
   void* d_table = nullptr;       // (N+1)^2, 1/M^2 folded, plan type
-  void* d_tw = nullptr;          // twiddles lo|hi, plan complex type
+  void* d_table64 = nullptr;     // FP64 copy for FP32 plans (exact refreshes)
+  void* d_ptable = nullptr;      // preconditioner symbol (N+1)^2, 1/M^2 folded
+  int precond_auto = 0;          // 1: constrained CG preconditioned by default
   void* d_S = nullptr;           // N x (N+1) complex intermediate
   // solver workspace (plan type unless noted)
   void* d_u = nullptr;
@@ -50,16 +79,25 @@ struct cb_plan_s {
   unsigned char* d_mask = nullptr;   // scratch contact set (N*N)
   unsigned char* d_mask2 = nullptr;  // second contact-set buffer (N*N)
   unsigned char* d_det = nullptr;    // detached-in-this-step flags (N*N)
-  double* d_part = nullptr;          // per-block FP64 partial sums
+  double* d_part = nullptr;          // partial-sum regions + scratch
   SolverState* d_state = nullptr;
-  SolverState* h_state = nullptr;    // pinned host mirror
+  SolverState* h_state = nullptr;    // pinned host mirror (2 slots)
   size_t workspace_bytes = 0;
-  int nblk_red = 0;                  // blocks of the reduction kernels
+  int nbr = 0;                       // blocks of the reduction kernels
+  hipStream_t istream = nullptr;     // plan-owned stream for captured solves
+  hipEvent_t ev_in = nullptr, ev_state[2] = {nullptr, nullptr};
+  GraphEntry graphs[GRAPH_CACHE];
+  unsigned long long graph_clock = 0;
+  int use_graphs = 1;
 };
 
 namespace cb {
-hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages = 7);
+// prec: -1 the plan's precision, 0 FP64, 1 FP32 (the table defaults to the
+// transfer table of that precision)
+hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages = 7,
+                        const int* skip = nullptr, const void* table = nullptr, int prec = -1);
 size_t intermediate_elems(int N);
+void prepare_apply(int log2n);
 }  // namespace cb
 
 // error reporting (thread-local message)

@@ -201,7 +201,13 @@ extern "C" int cb_transfer_table(int N, double L, double h, double E1, double nu
 }
 
 static void free_plan_memory(cb_plan_s* P) {
-  void* ptrs[] = {P->d_table, P->d_tw, P->d_S, P->d_u, P->d_t, P->d_r, P->d_g,
+  for (auto& g : P->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (P->ev_in) (void)hipEventDestroy(P->ev_in);
+  for (auto& e : P->ev_state)
+    if (e) (void)hipEventDestroy(e);
+  if (P->istream) (void)hipStreamDestroy(P->istream);
+  void* ptrs[] = {P->d_table, P->d_table64, P->d_ptable, P->d_S, P->d_u, P->d_t, P->d_r, P->d_g,
                   P->d_pold, P->d_mask, P->d_mask2, P->d_det, P->d_part, P->d_state};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -249,21 +255,25 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
 
   // ---- device memory ---------------------------------------------------------
   const size_t es = P->precision == CB_FP64 ? 8 : 4;
-  const int NLO = M < 64 ? M : 64, NHI = M <= 64 ? 1 : M / 64;
-  std::vector<double> tw((size_t)2 * (NLO + NHI));
-  for (int e = 0; e < NLO; e++) {
-    const double ang = -2.0 * M_PI * e / M;
-    tw[2 * e] = std::cos(ang);
-    tw[2 * e + 1] = std::sin(ang);
-  }
-  for (int e = 0; e < NHI; e++) {
-    const double ang = -2.0 * M_PI * (64.0 * e) / M;
-    tw[2 * (NLO + e)] = std::cos(ang);
-    tw[2 * (NLO + e) + 1] = std::sin(ang);
-  }
   std::vector<double> tdev(P->table64);
   const double inv = 1.0 / ((double)M * M);
   for (double& v : tdev) v *= inv;
+  // Preconditioner symbol of the constrained CG: 1 / C(k h) with
+  // C = E1* k K^ / 2, i.e. the ratio of the homogeneous-coating kernel to
+  // the layered one (tends to 1 at high k), with the same 1/M^2 folded in.
+  std::vector<double> pdev((size_t)NC * NC);
+  {
+    const Coef cf = coefficients(E1, nu1, E2, nu2);
+    const double dk = 2.0 * M_PI / (M * P->dx);
+    for (int a = 0; a < NC; a++)
+      for (int b = 0; b < NC; b++) {
+        const double k = dk * std::sqrt((double)a * a + (double)b * b);
+        pdev[(size_t)a * NC + b] = inv / shape(k * h, cf);
+      }
+  }
+  // automatic use: a coating at least 3x stiffer than the substrate and
+  // thin relative to the domain
+  P->precond_auto = (P->E1s >= 3.0 * P->E2s && h <= L / 16.0) ? 1 : 0;
 
   const size_t n2 = (size_t)N * N;
   int rc = CB_OK;
@@ -276,36 +286,56 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
     P->workspace_bytes += bytes;
   };
   (void)hipGetDevice(&P->device);
-  P->nblk_red = 1024;
+  {
+    const long long n = (long long)N * N;
+    long long nb = (n + 1023) / 1024;
+    P->nbr = (int)(nb < RED_BLOCKS_MAX ? (nb < 1 ? 1 : nb) : RED_BLOCKS_MAX);
+  }
   alloc(&P->d_table, (size_t)NC * NC * es);
-  alloc(&P->d_tw, (size_t)2 * (NLO + NHI) * es);
-  alloc(&P->d_S, cb::intermediate_elems(N) * 2 * es);
-  alloc(&P->d_u, n2 * es);
-  alloc(&P->d_t, n2 * es);
-  alloc(&P->d_r, n2 * es);
-  alloc(&P->d_g, n2 * es);
-  alloc(&P->d_pold, n2 * es);
+  alloc(&P->d_ptable, (size_t)NC * NC * es);
+  // the intermediate and the solver arrays are sized for FP64 in both
+  // precisions: solves keep their state (p, u, f, gap) in FP64 and FP32
+  // plans refresh u with an FP64 convolution
+  alloc(&P->d_S, cb::intermediate_elems(N) * 2 * 8);
+  alloc(&P->d_u, n2 * 8);
+  alloc(&P->d_t, n2 * 8);
+  alloc(&P->d_r, n2 * 8);
+  alloc(&P->d_g, n2 * 8);
+  alloc(&P->d_pold, n2 * 8);
+  if (P->precision == CB_FP32) alloc(&P->d_table64, (size_t)NC * NC * 8);
   alloc((void**)&P->d_mask, n2);
   alloc((void**)&P->d_mask2, n2);
   alloc((void**)&P->d_det, n2);
-  // partials (nblk_red x 8) | 16 scratch doubles | reduction counter
-  alloc((void**)&P->d_part, ((size_t)P->nblk_red * 8 + 32) * sizeof(double));
+  // partial-sum regions | 32 scratch doubles
+  const size_t part_doubles = (size_t)SCRATCH_OFF + 32;
+  alloc((void**)&P->d_part, part_doubles * sizeof(double));
   alloc((void**)&P->d_state, sizeof(SolverState));
-  if (rc == CB_OK && hipHostMalloc((void**)&P->h_state, sizeof(SolverState), 0) != hipSuccess)
+  if (rc == CB_OK && hipHostMalloc((void**)&P->h_state, 2 * sizeof(SolverState), 0) != hipSuccess)
     rc = cb_fail(CB_E_NOMEM, "hipHostMalloc failed");
   if (rc == CB_OK) {
     hipError_t e1, e2;
     if (P->precision == CB_FP64) {
       e1 = hipMemcpy(P->d_table, tdev.data(), tdev.size() * 8, hipMemcpyHostToDevice);
-      e2 = hipMemcpy(P->d_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice);
+      e2 = hipMemcpy(P->d_ptable, pdev.data(), pdev.size() * 8, hipMemcpyHostToDevice);
     } else {
-      std::vector<float> tf(tdev.begin(), tdev.end()), twf(tw.begin(), tw.end());
+      std::vector<float> tf(tdev.begin(), tdev.end()), pf(pdev.begin(), pdev.end());
       e1 = hipMemcpy(P->d_table, tf.data(), tf.size() * 4, hipMemcpyHostToDevice);
-      e2 = hipMemcpy(P->d_tw, twf.data(), twf.size() * 4, hipMemcpyHostToDevice);
+      if (e1 == hipSuccess)
+        e1 = hipMemcpy(P->d_table64, tdev.data(), tdev.size() * 8, hipMemcpyHostToDevice);
+      e2 = hipMemcpy(P->d_ptable, pf.data(), pf.size() * 4, hipMemcpyHostToDevice);
     }
-    const hipError_t e3 = hipMemset(P->d_part, 0, ((size_t)P->nblk_red * 8 + 32) * sizeof(double));
+    const hipError_t e3 = hipMemset(P->d_part, 0, part_doubles * sizeof(double));
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
       rc = cb_fail(CB_E_DEVICE, "table upload failed");
+  }
+  if (rc == CB_OK) cb::prepare_apply(P->log2n);
+  if (rc == CB_OK) {
+    // default priority, no implicit sync with the null stream
+    if (hipStreamCreateWithFlags(&P->istream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_state[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&P->ev_state[1], hipEventDisableTiming) != hipSuccess)
+      rc = cb_fail(CB_E_DEVICE, "stream/event creation failed");
   }
   if (rc != CB_OK) {
     free_plan_memory(P);
@@ -318,6 +348,7 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
 
 extern "C" int cb_plan_destroy(cb_plan P) {
   if (!P) return CB_OK;
+  if (P->istream) (void)hipStreamSynchronize(P->istream);
   if (P->stream) (void)hipStreamSynchronize(P->stream);
   else (void)hipDeviceSynchronize();
   free_plan_memory(P);

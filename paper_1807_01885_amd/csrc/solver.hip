@@ -4,15 +4,32 @@
 // Non-adhesive: constrained conjugate gradients (Polonsky-Keer reading of
 // the paper's reference [8]); the converged pressure solves
 //   p >= 0, g = K p + f - d >= 0, p g = 0.
+// Optionally the direction is preconditioned by the Fourier multiplier
+// 1/C(kh) = 2/(E1* k K^(k)) (the layered kernel relative to a homogeneous
+// one of the coating), which removes the stiffness contrast of thin stiff
+// coatings; the converged pressure is the same.
 // Adhesive: plain conjugate gradients on the contact set S ((K p)_i = d - f_i
 // on S, p = 0 off S), then the Eq. 12 detachment of boundary cells with
 // tension above sigma_c and attachment of penetrating cells, repeated until
 // nothing changes.
 //
-// Every reduction accumulates in FP64 (also for FP32 fields), per block in a
-// fixed order, and the last block to finish folds the block partials in a
-// fixed order and updates the device-resident SolverState: results are
-// bitwise reproducible and no host round trip is needed per iteration.
+// Precision: the solution state (p, u = K p, f, the gap, residuals) is FP64
+// in every plan.  The direction vectors (t, K t, M^-1 g, fixed-set CG
+// directions) and their convolutions use the plan type TD (FP32 or FP64).
+// u is advanced linearly (u -= tau K t) while no cell changes state, and
+// recomputed from p by an FP64 convolution whenever a cell is clipped or
+// activated and at the end of every chunk, so FP32 direction errors do not
+// accumulate in u (iterative refinement inside the iteration).
+//
+// Reductions: every reduction kernel writes one FP64 partial per block (a
+// fixed-order wave/LDS tree); the kernel that needs the total folds the
+// partials itself, redundantly in every block and in a fixed order, so all
+// blocks hold bitwise-identical scalars and no atomics or grid-wide fences
+// are needed.  Scalars that live across iterations are in SolverState;
+// those written and read within one iteration are double-buffered by the
+// iteration parity.  A chunk of iterations is captured once as a hipGraph
+// on the plan's own stream and replayed; the host looks at the convergence
+// flag once per chunk.
 #include <chrono>
 #include <cmath>
 #include <string>
@@ -22,8 +39,7 @@
 
 namespace cb {
 
-constexpr int RED_THREADS = 256;
-constexpr int MAXQ = 6;  // reduced quantities per kernel
+constexpr int RT = 256;  // threads per solver block
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -36,472 +52,582 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Reduce Q values per thread to block totals in `out` (thread 0 holds them).
-// ISMAX[q] selects max instead of sum for quantity q.
+// Every thread receives the block totals (identical in all threads).
 template <int Q>
-__device__ __forceinline__ void block_reduce(double (&v)[Q], const bool (&ismax)[Q], double* sh) {
+__device__ __forceinline__ void block_allreduce(double (&v)[Q], const bool (&mx)[Q]) {
+  __shared__ double sh[RT / 64 * Q];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < Q; q++) v[q] = ismax[q] ? wave_max(v[q]) : wave_sum(v[q]);
+  for (int q = 0; q < Q; q++) v[q] = mx[q] ? wave_max(v[q]) : wave_sum(v[q]);
   if (lane == 0) {
 #pragma unroll
     for (int q = 0; q < Q; q++) sh[w * Q + q] = v[q];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    constexpr int NW = RED_THREADS / 64;
 #pragma unroll
-    for (int q = 0; q < Q; q++) {
-      double a = sh[q];
-      for (int i = 1; i < NW; i++) a = ismax[q] ? fmax(a, sh[i * Q + q]) : a + sh[i * Q + q];
-      v[q] = a;
-    }
+  for (int q = 0; q < Q; q++) {
+    double a = sh[q];
+    for (int i = 1; i < RT / 64; i++) a = mx[q] ? fmax(a, sh[i * Q + q]) : a + sh[i * Q + q];
+    v[q] = a;
   }
   __syncthreads();
 }
 
-// Write this block's partials; the last block to arrive folds all partials
-// (fixed order) into tot[] and returns true in every thread of that block.
 template <int Q>
-__device__ bool last_block_fold(double (&v)[Q], const bool (&ismax)[Q], double* part,
-                                unsigned int* counter, double (&tot)[Q], double* sh) {
-  __shared__ int am_last;
+__device__ __forceinline__ void write_partials(double* region, const double (&v)[Q]) {
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < Q; q++) part[blockIdx.x * Q + q] = v[q];
-    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    am_last = (prev == gridDim.x - 1);
+    for (int q = 0; q < Q; q++) region[8 + blockIdx.x * Q + q] = v[q];
   }
-  __syncthreads();
-  if (!am_last) return false;
-  __atomic_thread_fence(__ATOMIC_ACQUIRE);
-  double a[Q];
-#pragma unroll
-  for (int q = 0; q < Q; q++) a[q] = ismax[q] ? -INFINITY : 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += RED_THREADS) {
-#pragma unroll
-    for (int q = 0; q < Q; q++) {
-      const double x = __hip_atomic_load(&part[b * Q + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      a[q] = ismax[q] ? fmax(a[q], x) : a[q] + x;
-    }
-  }
-  block_reduce<Q>(a, ismax, sh);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < Q; q++) tot[q] = a[q];
-    *counter = 0u;
-  }
-  return true;
 }
 
-template <typename T>
-__device__ __forceinline__ bool finite_val(T x) { return isfinite(x); }
+template <int Q>
+__device__ __forceinline__ void fold(const double* __restrict__ region, int nb, const bool (&mx)[Q],
+                                     double (&tot)[Q]) {
+#pragma unroll
+  for (int q = 0; q < Q; q++) tot[q] = mx[q] ? -INFINITY : 0.0;
+  for (int b = threadIdx.x; b < nb; b += RT) {
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      const double x = region[8 + b * Q + q];
+      tot[q] = mx[q] ? fmax(tot[q], x) : tot[q] + x;
+    }
+  }
+  block_allreduce<Q>(tot, mx);
+}
+
+__device__ __forceinline__ double* region(double* part, int r) { return part + (size_t)r * REG_STRIDE; }
+__device__ __forceinline__ const double* region(const double* part, int r) { return part + (size_t)r * REG_STRIDE; }
+
+#define GRID_LOOP(i, n) for (int i = blockIdx.x * RT + threadIdx.x; i < (n); i += gridDim.x * RT)
 
 // ---------------------------------------------------------------------------
-// Non-adhesive constrained CG kernels
+// Constrained CG (non-adhesive), one iteration =
+//   gap -> dir -> K t -> step -> update -> post [-> K p]
+// (preconditioned: gap -> gmask -> M^-1 gm -> zdot -> dir_pc -> K t -> ...)
 // ---------------------------------------------------------------------------
-struct KParams {
-  int n;            // N*N
-  int force;        // 1: force control
-  double tol;
-  double Ftarget;
-  double dA;
-  double k00;
+// stored gap g' = u + f - s (s = d, or under force control the shift
+// gbar[par], the previous mean); partials over Ic = {p > 0}:
+// S1 = sum g', S2 = sum g'^2, n, A1 = sum (s - f), A2 = sum (s - f)^2;
+// over the rest: max(-g'); and a non-finite flag.
+__global__ void __launch_bounds__(RT)
+k_pk_gap(const double* __restrict__ p, const double* __restrict__ u, const double* __restrict__ f,
+         double* __restrict__ g, const SolverState* __restrict__ st, const double* __restrict__ gbar2,
+         double* part, int n, int par) {
+  if (st->done) return;
+  const double s = st->force ? gbar2[par] : st->d_in;
+  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, 0.0};
+  const bool mx[7] = {false, false, false, false, false, true, true};
+#pragma unroll 4
+  GRID_LOOP(i, n) {
+    const double fi = f[i];
+    const double x = u[i] + fi - s;
+    g[i] = x;
+    if (!isfinite(x)) v[6] = 1.0;
+    if (p[i] > 0.0) {
+      const double a = s - fi;
+      v[0] += x;
+      v[1] += x * x;
+      v[2] += 1.0;
+      v[3] += a;
+      v[4] += a * a;
+    } else {
+      v[5] = fmax(v[5], -x);
+    }
+  }
+  block_allreduce<7>(v, mx);
+  write_partials<7>(region(part, R_GAP0 + par), v);
+}
+
+struct GapTotals {
+  double m, G, resid, n;
+  bool conv, nonfinite;
 };
 
-// Force control: mean of u + f over Ic -> state.d (the approach)
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-k_mean_gap(const T* __restrict__ p, const T* __restrict__ u, const T* __restrict__ f, KParams kp,
-           SolverState* st, double* part, unsigned* counter) {
-  if (st->done) return;
-  __shared__ double sh[RED_THREADS / 64 * 2];
-  double v[2] = {0.0, 0.0};
-  const bool mx[2] = {false, false};
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < kp.n; i += gridDim.x * RED_THREADS) {
-    if (p[i] > T(0)) {
-      v[0] += (double)u[i] + (double)f[i];
-      v[1] += 1.0;
-    }
-  }
-  block_reduce<2>(v, mx, sh);
-  double tot[2];
-  if (last_block_fold<2>(v, mx, part, counter, tot, sh) && threadIdx.x == 0) {
-    if (tot[1] > 0.0) st->d = tot[0] / tot[1];
-    else { st->nonfinite = 1; st->done = 1; }
-  }
+__device__ __forceinline__ GapTotals gap_totals(const double (&a)[7], const SolverState* st) {
+  GapTotals r;
+  const bool force = st->force;
+  const double nn = a[2];
+  r.n = nn;
+  r.m = (force && nn > 0.0) ? a[0] / nn : 0.0;
+  double G = force ? a[1] - a[0] * r.m : a[1];
+  G = G > 0.0 ? G : 0.0;
+  r.G = G;
+  const double rhs2 = force ? a[4] + 2.0 * r.m * a[3] + nn * r.m * r.m : a[4];
+  r.resid = rhs2 > 0.0 ? sqrt(G / rhs2) : sqrt(G);
+  const double scale = sqrt((rhs2 > 0.0 ? rhs2 : 0.0) / (nn > 1.0 ? nn : 1.0));
+  const double gmin_off = -a[5] - r.m;  // +inf when every cell is in contact
+  const bool viol = gmin_off < -st->tol * scale;
+  r.nonfinite = a[6] > 0.0;
+  r.conv = (r.resid <= st->tol) && !viol;
+  return r;
 }
 
-// g = u + f - d; residual check; conjugate-direction coefficient
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-k_gap(const T* __restrict__ p, const T* __restrict__ u, const T* __restrict__ f, T* __restrict__ g,
-      KParams kp, SolverState* st, double* part, unsigned* counter) {
-  if (st->done) return;
-  __shared__ double sh[RED_THREADS / 64 * 5];
-  const double d = st->d;
-  // G = sum_Ic g^2, rhs2 = sum_Ic (d-f)^2, n_Ic, max_{!Ic} (-g), nonfinite
-  double v[5] = {0.0, 0.0, 0.0, -INFINITY, 0.0};
-  const bool mx[5] = {false, false, false, true, true};
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < kp.n; i += gridDim.x * RED_THREADS) {
-    const double gi = (double)u[i] + (double)f[i] - d;
-    const T gt = (T)gi;
-    g[i] = gt;
-    if (!finite_val(gt)) v[4] = 1.0;
-    if (p[i] > T(0)) {
-      v[0] += (double)gt * (double)gt;
-      const double r = d - (double)f[i];
-      v[1] += r * r;
-      v[2] += 1.0;
-    } else {
-      v[3] = fmax(v[3], -(double)gt);
-    }
-  }
-  block_reduce<5>(v, mx, sh);
-  double tot[5];
-  if (last_block_fold<5>(v, mx, part, counter, tot, sh) && threadIdx.x == 0) {
+// block 0 records the check; returns true when the solve stops here
+__device__ __forceinline__ bool record_check(const GapTotals& gt, SolverState* st, double* gbar2, double s,
+                                             int par) {
+  const bool stop = gt.conv || gt.nonfinite;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->iters += 1;
-    if (tot[4] > 0.0) { st->nonfinite = 1; st->done = 1; return; }
-    const double G = tot[0];
-    const double rn = sqrt(tot[1]);
-    const double res = rn > 0.0 ? sqrt(G) / rn : sqrt(G);
-    const double scale = rn / sqrt(fmax(tot[2], 1.0));
-    st->resid = res;
-    st->nactive = (int)tot[2];
-    st->viol = (tot[3] > kp.tol * scale) ? 1 : 0;
-    if (res <= kp.tol && !st->viol) { st->done = 1; return; }
-    st->rr = (st->delta > 0.0) ? G / st->G_old : 0.0;  // beta
-    st->G_old = G;
+    st->resid = gt.resid;
+    st->nact = gt.n;
+    st->gdev = gt.m;
+    if (st->force) {
+      st->d = s + gt.m;
+      gbar2[par ^ 1] = s + gt.m;
+    }
+    if (gt.nonfinite) st->nonfinite = 1;
+    if (stop) st->done = 1;
   }
+  return stop;
 }
 
-// t = Ic ? g + beta t : 0
-template <typename T>
-__global__ void k_dir(const T* __restrict__ p, const T* __restrict__ g, T* __restrict__ t, int n,
-                      const SolverState* st) {
+// convergence check, conjugate coefficient, t = Ic ? g + beta t : 0
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_pk_dir(const double* __restrict__ p, const double* __restrict__ g, TD* __restrict__ t, SolverState* st,
+         double* gbar2, double* part, int nb, int n, int par) {
   if (st->done) return;
-  const T beta = (T)st->rr;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    t[i] = p[i] > T(0) ? g[i] + beta * t[i] : T(0);
+  const bool mx7[7] = {false, false, false, false, false, true, true};
+  const bool mx3[3] = {false, false, false};
+  double a[7], u3[3];
+  fold<7>(region(part, R_GAP0 + par), nb, mx7, a);
+  fold<3>(region(part, R_UPD), nb, mx3, u3);
+  const double s = st->force ? gbar2[par] : st->d_in;
+  const GapTotals gt = gap_totals(a, st);
+  if (record_check(gt, st, gbar2, s, par)) return;
+  double beta = 0.0;
+  if (u3[1] == 0.0) {  // no restart requested by the previous update
+    double b[7];
+    fold<7>(region(part, R_GAP0 + (par ^ 1)), nb, mx7, b);
+    const double nb2 = b[2];
+    const double mb = (st->force && nb2 > 0.0) ? b[0] / nb2 : 0.0;
+    const double Gp = st->force ? b[1] - b[0] * mb : b[1];
+    beta = Gp > 0.0 ? gt.G / Gp : 0.0;
+  }
+  const double m = gt.m;
+#pragma unroll 4
+  GRID_LOOP(i, n) t[i] = p[i] > 0.0 ? (TD)((g[i] - m) + beta * (double)t[i]) : TD(0);
 }
 
-// Force control: mean of r over Ic
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-k_mean_r(const T* __restrict__ p, const T* __restrict__ r, KParams kp, SolverState* st, double* part,
-         unsigned* counter) {
+// preconditioned: convergence check and gm = Ic ? g : 0
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_pk_gmask(const double* __restrict__ p, const double* __restrict__ g, TD* __restrict__ gm, SolverState* st,
+           double* gbar2, double* part, int nb, int n, int par) {
   if (st->done) return;
-  __shared__ double sh[RED_THREADS / 64 * 2];
+  const bool mx7[7] = {false, false, false, false, false, true, true};
+  double a[7];
+  fold<7>(region(part, R_GAP0 + par), nb, mx7, a);
+  const double s = st->force ? gbar2[par] : st->d_in;
+  const GapTotals gt = gap_totals(a, st);
+  if (record_check(gt, st, gbar2, s, par)) return;
+  const double m = gt.m;
+#pragma unroll 4
+  GRID_LOOP(i, n) gm[i] = p[i] > 0.0 ? (TD)(g[i] - m) : TD(0);
+}
+
+// preconditioned: partials over Ic of sum z', sum g z' (z' = M^-1 gm)
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_pk_zdot(const double* __restrict__ p, const double* __restrict__ g, const TD* __restrict__ zp,
+          const SolverState* __restrict__ st, double* part, int n, int par) {
+  if (st->done) return;
+  const double m = st->gdev;
   double v[2] = {0.0, 0.0};
   const bool mx[2] = {false, false};
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < kp.n; i += gridDim.x * RED_THREADS) {
-    if (p[i] > T(0)) {
-      v[0] += (double)r[i];
-      v[1] += 1.0;
+#pragma unroll 4
+  GRID_LOOP(i, n) {
+    if (p[i] > 0.0) {
+      const double z = (double)zp[i];
+      v[0] += z;
+      v[1] += (g[i] - m) * z;
     }
   }
-  block_reduce<2>(v, mx, sh);
-  double tot[2];
-  if (last_block_fold<2>(v, mx, part, counter, tot, sh) && threadIdx.x == 0)
-    st->rmean = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
+  block_allreduce<2>(v, mx);
+  write_partials<2>(region(part, R_PZ0 + par), v);
 }
 
-// tau = sum_Ic g t / sum_Ic (r - rmean) t
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-k_step(const T* __restrict__ p, const T* __restrict__ g, const T* __restrict__ t,
-       const T* __restrict__ r, KParams kp, SolverState* st, double* part, unsigned* counter) {
+// preconditioned: t = Ic ? (z' - mean) + beta t : 0, beta = (g.z)/(g.z)_prev
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_pk_dir_pc(const double* __restrict__ p, const TD* __restrict__ zp, TD* __restrict__ t,
+            const SolverState* __restrict__ st, double* part, int nb, int n, int par) {
   if (st->done) return;
-  __shared__ double sh[RED_THREADS / 64 * 2];
-  const double rm = kp.force ? st->rmean : 0.0;
-  double v[2] = {0.0, 0.0};
-  const bool mx[2] = {false, false};
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < kp.n; i += gridDim.x * RED_THREADS) {
-    if (p[i] > T(0)) {
-      const double ti = (double)t[i];
-      v[0] += (double)g[i] * ti;
-      v[1] += ((double)r[i] - rm) * ti;
+  const bool mx2[2] = {false, false}, mx3[3] = {false, false, false};
+  double a[2], u3[3];
+  fold<2>(region(part, R_PZ0 + par), nb, mx2, a);
+  fold<3>(region(part, R_UPD), nb, mx3, u3);
+  const double nn = st->nact;
+  const double zbar = (st->force && nn > 0.0) ? a[0] / nn : 0.0;
+  double beta = 0.0;
+  if (u3[1] == 0.0) {
+    double b[2];
+    fold<2>(region(part, R_PZ0 + (par ^ 1)), nb, mx2, b);
+    beta = b[1] > 0.0 ? a[1] / b[1] : 0.0;
+  }
+#pragma unroll 4
+  GRID_LOOP(i, n) t[i] = p[i] > 0.0 ? (TD)(((double)zp[i] - zbar) + beta * (double)t[i]) : TD(0);
+}
+
+// partials over Ic: sum g t, sum r t, sum r, sum t (g = g' - gdev)
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_pk_step(const double* __restrict__ p, const double* __restrict__ g, const TD* __restrict__ t,
+          const TD* __restrict__ r, const SolverState* __restrict__ st, double* part, int n) {
+  if (st->done) return;
+  const double m = st->gdev;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const bool mx[4] = {false, false, false, false};
+#pragma unroll 4
+  GRID_LOOP(i, n) {
+    if (p[i] > 0.0) {
+      const double ti = (double)t[i], ri = (double)r[i];
+      v[0] += (g[i] - m) * ti;
+      v[1] += ri * ti;
+      v[2] += ri;
+      v[3] += ti;
     }
   }
-  block_reduce<2>(v, mx, sh);
-  double tot[2];
-  if (last_block_fold<2>(v, mx, part, counter, tot, sh) && threadIdx.x == 0)
-    st->tau = tot[1] > 0.0 ? tot[0] / tot[1] : 1.0 / kp.k00;
+  block_allreduce<4>(v, mx);
+  write_partials<4>(region(part, R_STEP), v);
 }
 
-// p <- max(p - tau t, 0) on Ic; p = 0 & g < 0 -> p = -tau g (restart)
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-k_update(T* __restrict__ p, const T* __restrict__ g, const T* __restrict__ t, KParams kp,
-         SolverState* st, double* part, unsigned* counter) {
+// tau; p <- max(p - tau t, 0) on Ic; p = 0 and g < 0 -> p = -tau g
+// (restart); u <- u - tau K t (exact while no cell is clipped or
+// activated); partials: sum p, activations, clipped cells
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_pk_update(double* __restrict__ p, double* __restrict__ u, const double* __restrict__ g,
+            const TD* __restrict__ t, const TD* __restrict__ r, const SolverState* __restrict__ st, double* part,
+            int nb, int n) {
   if (st->done) return;
-  __shared__ double sh[RED_THREADS / 64 * 2];
-  const double tau = st->tau;
-  double v[2] = {0.0, 0.0};
-  const bool mx[2] = {false, false};
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < kp.n; i += gridDim.x * RED_THREADS) {
-    double pi = (double)p[i];
-    if (pi > 0.0) pi = pi - tau * (double)t[i];
-    T pn = (T)(pi > 0.0 ? pi : 0.0);
-    const T gi = g[i];
-    if (pn == T(0) && gi < T(0)) {
-      pn = (T)(-tau * (double)gi);
+  const bool mx4[4] = {false, false, false, false};
+  double a[4];
+  fold<4>(region(part, R_STEP), nb, mx4, a);
+  const double nn = st->nact;
+  const double rm = (st->force && nn > 0.0) ? a[2] / nn : 0.0;
+  const double rt = a[1] - rm * a[3];
+  const double tau = rt > 0.0 ? a[0] / rt : 1.0 / st->k00;
+  const double m = st->gdev;
+  double v[3] = {0.0, 0.0, 0.0};
+  const bool mx[3] = {false, false, false};
+#pragma unroll 4
+  GRID_LOOP(i, n) {
+    double pi = p[i];
+    const bool on = pi > 0.0;
+    if (on) pi -= tau * (double)t[i];
+    double pn = pi > 0.0 ? pi : 0.0;
+    if (on && pn == 0.0) v[2] += 1.0;
+    const double gi = g[i] - m;
+    if (pn == 0.0 && gi < 0.0) {
+      pn = -tau * gi;
       v[1] += 1.0;
     }
     p[i] = pn;
-    v[0] += (double)pn;
+    u[i] -= tau * (double)r[i];
+    v[0] += pn;
   }
-  block_reduce<2>(v, mx, sh);
-  double tot[2];
-  if (last_block_fold<2>(v, mx, part, counter, tot, sh) && threadIdx.x == 0) {
-    st->delta = tot[1] > 0.0 ? 0.0 : 1.0;
-    st->F = kp.dA * tot[0];
-    st->bnorm = (kp.force && tot[0] > 0.0) ? kp.Ftarget / (kp.dA * tot[0]) : 1.0;  // rescale
-  }
+  block_allreduce<3>(v, mx);
+  write_partials<3>(region(part, R_UPD), v);
 }
 
-template <typename T>
-__global__ void k_rescale(T* __restrict__ p, int n, const SolverState* st) {
+// force control: p, u *= F / (dA sum p); block 0 decides whether u must be
+// recomputed from p (a cell changed state, or a refresh is due)
+__global__ void __launch_bounds__(RT)
+k_pk_post(double* __restrict__ p, double* __restrict__ u, SolverState* st, const double* part, int nb, int n,
+          int refresh) {
   if (st->done) return;
-  const double s = st->bnorm;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    p[i] = (T)((double)p[i] * s);
+  const bool mx3[3] = {false, false, false};
+  double a[3];
+  fold<3>(region(part, R_UPD), nb, mx3, a);
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    st->skip_u = (refresh || a[1] > 0.0 || a[2] > 0.0) ? 0 : 1;
+  if (!st->force || !(a[0] > 0.0)) return;
+  const double sc = st->Ftarget / (st->dA * a[0]);
+#pragma unroll 4
+  GRID_LOOP(i, n) {
+    p[i] *= sc;
+    u[i] *= sc;
+  }
+}
+
+// sum p -> R_UPD with the restart flag set (first iteration: no beta)
+__global__ void __launch_bounds__(RT) k_pk_seed(const double* __restrict__ p, double* part, int n) {
+  double v[3] = {0.0, blockIdx.x == 0 && threadIdx.x == 0 ? 1.0 : 0.0, 0.0};
+  const bool mx[3] = {false, false, false};
+  GRID_LOOP(i, n) v[0] += p[i];
+  block_allreduce<3>(v, mx);
+  write_partials<3>(region(part, R_UPD), v);
+}
+
+// force control start: p *= F / (dA sum p)
+__global__ void __launch_bounds__(RT) k_pk_scale0(double* __restrict__ p, const SolverState* st, const double* part,
+                                                  int nb, int n) {
+  const bool mx3[3] = {false, false, false};
+  double a[3];
+  fold<3>(region(part, R_UPD), nb, mx3, a);
+  if (!(a[0] > 0.0)) return;
+  const double sc = st->Ftarget / (st->dA * a[0]);
+  GRID_LOOP(i, n) p[i] *= sc;
 }
 
 // ---------------------------------------------------------------------------
-// initial guesses, statistics, masks
+// Fixed-set CG (adhesive inner solve), one iteration =
+//   K z -> zq -> upd -> dir   (x, r in FP64; z, K z in the plan type)
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-k_minmax(const T* __restrict__ x, int n, double* part, unsigned* counter, double* out) {
-  __shared__ double sh[RED_THREADS / 64 * 3];
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_mcg_init(const double* __restrict__ f, const double* __restrict__ u, const unsigned char* __restrict__ S,
+           double* __restrict__ r, TD* __restrict__ z, const SolverState* __restrict__ st, double* part, int n) {
+  const double d = st->d_in;
+  double v[2] = {0.0, 0.0}, w[1] = {0.0};
+  const bool mx[2] = {false, true}, mx1[1] = {false};
+#pragma unroll 4
+  GRID_LOOP(i, n) {
+    double ri = 0.0;
+    if (S[i]) {
+      const double b = d - f[i];
+      ri = b - u[i];
+      w[0] += b * b;
+    }
+    r[i] = ri;
+    z[i] = (TD)ri;
+    v[0] += ri * ri;
+    if (!isfinite(ri)) v[1] = 1.0;
+  }
+  block_allreduce<2>(v, mx);
+  write_partials<2>(region(part, R_RR1), v);
+  block_allreduce<1>(w, mx1);
+  write_partials<1>(region(part, R_INIT), w);
+}
+
+__global__ void __launch_bounds__(RT) k_mcg_init_fin(SolverState* st, const double* part, int nb) {
+  const bool mx[2] = {false, true}, mx1[1] = {false};
+  double a[2], b[1];
+  fold<2>(region(part, R_RR1), nb, mx, a);
+  fold<1>(region(part, R_INIT), nb, mx1, b);
+  if (threadIdx.x == 0) {
+    const double bn = sqrt(b[0]);
+    st->bnorm = bn;
+    st->resid = bn > 0.0 ? sqrt(a[0]) / bn : 0.0;
+    if (a[1] > 0.0) { st->nonfinite = 1; st->done = 1; }
+    else if (bn == 0.0 || st->resid <= st->tol) st->done = 1;
+  }
+}
+
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_mcg_zq(const TD* __restrict__ z, const TD* __restrict__ q, const unsigned char* __restrict__ S,
+         const SolverState* __restrict__ st, double* part, int n) {
+  if (st->done) return;
+  double v[1] = {0.0};
+  const bool mx[1] = {false};
+#pragma unroll 4
+  GRID_LOOP(i, n) if (S[i]) v[0] += (double)z[i] * (double)q[i];
+  block_allreduce<1>(v, mx);
+  write_partials<1>(region(part, R_ZQ), v);
+}
+
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_mcg_upd(double* __restrict__ x, double* __restrict__ r, const TD* __restrict__ z, const TD* __restrict__ q,
+          const unsigned char* __restrict__ S, SolverState* st, double* part, int nb, int n, int par) {
+  if (st->done) return;
+  const bool mx1[1] = {false}, mx2[2] = {false, true};
+  double zq[1], rr[2];
+  fold<1>(region(part, R_ZQ), nb, mx1, zq);
+  fold<2>(region(part, R_RR0 + (par ^ 1)), nb, mx2, rr);
+  if (!(zq[0] > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) { st->breakdown = 1; st->done = 1; }
+    return;
+  }
+  const double al = rr[0] / zq[0];
+  double v[2] = {0.0, 0.0};
+#pragma unroll 4
+  GRID_LOOP(i, n) {
+    if (S[i]) {
+      x[i] += al * (double)z[i];
+      const double ri = r[i] - al * (double)q[i];
+      r[i] = ri;
+      v[0] += ri * ri;
+      if (!isfinite(ri)) v[1] = 1.0;
+    }
+  }
+  block_allreduce<2>(v, mx2);
+  write_partials<2>(region(part, R_RR0 + par), v);
+}
+
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_mcg_dir(TD* __restrict__ z, const double* __restrict__ r, const unsigned char* __restrict__ S, SolverState* st,
+          double* part, int nb, int n, int par) {
+  if (st->done) return;
+  const bool mx2[2] = {false, true};
+  double a[2], b[2];
+  fold<2>(region(part, R_RR0 + par), nb, mx2, a);
+  fold<2>(region(part, R_RR0 + (par ^ 1)), nb, mx2, b);
+  const double bn = st->bnorm;
+  const double resid = bn > 0.0 ? sqrt(a[0]) / bn : 0.0;
+  const bool stop = a[1] > 0.0 || resid <= st->tol;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->iters += 1;
+    st->resid = resid;
+    if (a[1] > 0.0) st->nonfinite = 1;
+    if (stop) st->done = 1;
+  }
+  if (stop) return;
+  const double beta = b[0] > 0.0 ? a[0] / b[0] : 0.0;
+#pragma unroll 4
+  GRID_LOOP(i, n) z[i] = S[i] ? (TD)(r[i] + beta * (double)z[i]) : TD(0);
+}
+
+// ---------------------------------------------------------------------------
+// small kernels: initial guesses, masks, statistics
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(RT) k_init_disp(double* __restrict__ p, const double* __restrict__ f, int n,
+                                                  double d, double k00) {
+  GRID_LOOP(i, n) {
+    const double v = d - f[i];
+    p[i] = v > 0.0 ? v / k00 : 0.0;
+  }
+}
+__global__ void __launch_bounds__(RT) k_fill(double* __restrict__ p, int n, double v) { GRID_LOOP(i, n) p[i] = v; }
+__global__ void __launch_bounds__(RT) k_clamp_pos(double* __restrict__ p, int n) {
+  GRID_LOOP(i, n) p[i] = p[i] > 0.0 ? p[i] : 0.0;
+}
+__global__ void __launch_bounds__(RT) k_mask_from_p(const double* __restrict__ p, unsigned char* __restrict__ S,
+                                                    int n) {
+  GRID_LOOP(i, n) S[i] = p[i] > 0.0 ? 1 : 0;
+}
+__global__ void __launch_bounds__(RT) k_zero_off(double* __restrict__ p, const unsigned char* __restrict__ S,
+                                                 int n) {
+  GRID_LOOP(i, n) if (!S[i]) p[i] = 0.0;
+}
+__global__ void __launch_bounds__(RT) k_zero_bytes(unsigned char* __restrict__ a, int n) { GRID_LOOP(i, n) a[i] = 0; }
+
+// min f, max f, non-finite -> R_MISC (as max of -f, max of f, flag)
+__global__ void __launch_bounds__(RT) k_minmax(const double* __restrict__ x, double* part, int n) {
   double v[3] = {-INFINITY, -INFINITY, 0.0};
   const bool mx[3] = {true, true, true};
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += gridDim.x * RED_THREADS) {
-    const double a = (double)x[i];
+  GRID_LOOP(i, n) {
+    const double a = x[i];
     v[0] = fmax(v[0], -a);
     v[1] = fmax(v[1], a);
     if (!isfinite(a)) v[2] = 1.0;
   }
-  block_reduce<3>(v, mx, sh);
-  double tot[3];
-  if (last_block_fold<3>(v, mx, part, counter, tot, sh) && threadIdx.x == 0) {
-    out[0] = -tot[0];
-    out[1] = tot[1];
-    out[2] = tot[2];
-  }
+  block_allreduce<3>(v, mx);
+  write_partials<3>(region(part, R_MISC), v);
 }
 
-// p = max(d - f, 0) / k00 (cold start at prescribed approach)
-template <typename T>
-__global__ void k_init_disp(T* __restrict__ p, const T* __restrict__ f, int n, double d, double k00) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const double v = d - (double)f[i];
-    p[i] = (T)(v > 0.0 ? v / k00 : 0.0);
-  }
-}
-template <typename T>
-__global__ void k_fill(T* __restrict__ p, int n, double v) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = (T)v;
-}
-template <typename T>
-__global__ void k_clamp_pos(T* __restrict__ p, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    p[i] = p[i] > T(0) ? p[i] : T(0);
-}
-
-// F = dA sum p, area = dA |S|, U_el = dA/2 sum p u; out[0..3]: sum p, count, sum p u, nonfinite
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-k_stats(const T* __restrict__ p, const T* __restrict__ u, const unsigned char* __restrict__ S, int n,
-        double* part, unsigned* counter, double* out) {
-  __shared__ double sh[RED_THREADS / 64 * 4];
+// sum p, |S| (or |p > 0|), sum p u, non-finite -> R_MISC
+__global__ void __launch_bounds__(RT)
+k_stats(const double* __restrict__ p, const double* __restrict__ u, const unsigned char* __restrict__ S, double* part,
+        int n) {
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const bool mx[4] = {false, false, false, true};
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += gridDim.x * RED_THREADS) {
-    const double pi = (double)p[i];
+  GRID_LOOP(i, n) {
+    const double pi = p[i];
     v[0] += pi;
     v[1] += S ? (S[i] ? 1.0 : 0.0) : (pi > 0.0 ? 1.0 : 0.0);
-    v[2] += pi * (double)u[i];
+    v[2] += pi * u[i];
     if (!isfinite(pi)) v[3] = 1.0;
   }
-  block_reduce<4>(v, mx, sh);
-  double tot[4];
-  if (last_block_fold<4>(v, mx, part, counter, tot, sh) && threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < 4; q++) out[q] = tot[q];
-  }
+  block_allreduce<4>(v, mx);
+  write_partials<4>(region(part, R_MISC), v);
 }
 
-template <typename T>
-__global__ void k_mask_from_p(const T* __restrict__ p, unsigned char* __restrict__ S, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    S[i] = p[i] > T(0) ? 1 : 0;
+// fold R_MISC (Q quantities, max-mask bits) into the scratch area
+template <int Q>
+__global__ void __launch_bounds__(RT) k_fold_misc(double* part, int nb, int maxmask) {
+  bool mx[Q];
+#pragma unroll
+  for (int q = 0; q < Q; q++) mx[q] = (maxmask >> q) & 1;
+  double tot[Q];
+#pragma unroll
+  for (int q = 0; q < Q; q++) tot[q] = mx[q] ? -INFINITY : 0.0;
+  const double* reg = region(part, R_MISC);
+  for (int b = threadIdx.x; b < nb; b += RT) {
+#pragma unroll
+    for (int q = 0; q < Q; q++) {
+      const double x = reg[8 + b * Q + q];
+      tot[q] = mx[q] ? fmax(tot[q], x) : tot[q] + x;
+    }
+  }
+  __shared__ double sh[RT / 64 * Q];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < Q; q++) tot[q] = mx[q] ? wave_max(tot[q]) : wave_sum(tot[q]);
+  if (lane == 0)
+    for (int q = 0; q < Q; q++) sh[w * Q + q] = tot[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < Q; q++) {
+      double a = sh[q];
+      for (int i = 1; i < RT / 64; i++) a = mx[q] ? fmax(a, sh[i * Q + q]) : a + sh[i * Q + q];
+      part[SCRATCH_OFF + q] = a;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Adhesive kernels
 // ---------------------------------------------------------------------------
-// S0 = {f - d <= 0}, p = 0
-template <typename T>
-__global__ void k_mask_overlap(const T* __restrict__ f, double d, unsigned char* __restrict__ S,
-                               T* __restrict__ p, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    S[i] = ((double)f[i] - d <= 0.0) ? 1 : 0;
-    p[i] = T(0);
+// S0 = {f - d <= 0}, p = 0, no cell detached yet
+__global__ void __launch_bounds__(RT)
+k_mask_overlap(const double* __restrict__ f, double d, unsigned char* __restrict__ S, unsigned char* __restrict__ det,
+               double* __restrict__ p, int n) {
+  GRID_LOOP(i, n) {
+    S[i] = (f[i] - d <= 0.0) ? 1 : 0;
+    det[i] = 0;
+    p[i] = 0.0;
   }
 }
 
 // Start of a displacement step: S |= {f - d + u < 0}, p = 0 off S, det = 0
-template <typename T>
-__global__ void k_attach_start(const T* __restrict__ f, const T* __restrict__ u, double d,
-                               unsigned char* __restrict__ S, unsigned char* __restrict__ det,
-                               T* __restrict__ p, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const bool s = S[i] || ((double)f[i] - d + (double)u[i] < 0.0);
+__global__ void __launch_bounds__(RT)
+k_attach_start(const double* __restrict__ f, const double* __restrict__ u, double d, unsigned char* __restrict__ S,
+               unsigned char* __restrict__ det, double* __restrict__ p, int n) {
+  GRID_LOOP(i, n) {
+    const bool s = S[i] || (f[i] - d + u[i] < 0.0);
     S[i] = s ? 1 : 0;
     det[i] = 0;
-    if (!s) p[i] = T(0);
+    if (!s) p[i] = 0.0;
   }
 }
 
-// Fixed-set CG: r = S ? d - f - u : 0; z = r; rr, bnorm
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-k_mcg_init(const T* __restrict__ f, const T* __restrict__ u, const unsigned char* __restrict__ S,
-           T* __restrict__ r, T* __restrict__ z, KParams kp, SolverState* st, double* part,
-           unsigned* counter) {
-  __shared__ double sh[RED_THREADS / 64 * 3];
-  const double d = st->d;
-  double v[3] = {0.0, 0.0, 0.0};
-  const bool mx[3] = {false, false, true};
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < kp.n; i += gridDim.x * RED_THREADS) {
-    T ri = T(0);
-    if (S[i]) {
-      const double b = d - (double)f[i];
-      ri = (T)(b - (double)u[i]);
-      v[1] += b * b;
-    }
-    r[i] = ri;
-    z[i] = ri;
-    v[0] += (double)ri * (double)ri;
-    if (!finite_val(ri)) v[2] = 1.0;
-  }
-  block_reduce<3>(v, mx, sh);
-  double tot[3];
-  if (last_block_fold<3>(v, mx, part, counter, tot, sh) && threadIdx.x == 0) {
-    st->rr = tot[0];
-    st->bnorm = sqrt(tot[1]);
-    st->resid = st->bnorm > 0.0 ? sqrt(tot[0]) / st->bnorm : 0.0;
-    if (tot[2] > 0.0) { st->nonfinite = 1; st->done = 1; }
-    else if (st->bnorm == 0.0 || st->resid <= kp.tol) st->done = 1;
-  }
-}
-
-// alpha = rr / sum_S z q
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-k_mcg_alpha(const T* __restrict__ z, const T* __restrict__ q, const unsigned char* __restrict__ S,
-            KParams kp, SolverState* st, double* part, unsigned* counter) {
-  if (st->done) return;
-  __shared__ double sh[RED_THREADS / 64];
-  double v[1] = {0.0};
-  const bool mx[1] = {false};
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < kp.n; i += gridDim.x * RED_THREADS)
-    if (S[i]) v[0] += (double)z[i] * (double)q[i];
-  block_reduce<1>(v, mx, sh);
-  double tot[1];
-  if (last_block_fold<1>(v, mx, part, counter, tot, sh) && threadIdx.x == 0) {
-    if (tot[0] > 0.0) st->tau = st->rr / tot[0];
-    else { st->tau = 0.0; st->done = 1; }
-  }
-}
-
-// x += alpha z, r -= alpha q on S; beta = rr_new / rr; convergence
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-k_mcg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ z, const T* __restrict__ q,
-             const unsigned char* __restrict__ S, KParams kp, SolverState* st, double* part,
-             unsigned* counter) {
-  if (st->done) return;
-  __shared__ double sh[RED_THREADS / 64 * 2];
-  const double a = st->tau;
-  double v[2] = {0.0, 0.0};
-  const bool mx[2] = {false, true};
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < kp.n; i += gridDim.x * RED_THREADS) {
-    if (S[i]) {
-      x[i] = (T)((double)x[i] + a * (double)z[i]);
-      const T ri = (T)((double)r[i] - a * (double)q[i]);
-      r[i] = ri;
-      v[0] += (double)ri * (double)ri;
-      if (!finite_val(ri)) v[1] = 1.0;
-    }
-  }
-  block_reduce<2>(v, mx, sh);
-  double tot[2];
-  if (last_block_fold<2>(v, mx, part, counter, tot, sh) && threadIdx.x == 0) {
-    st->iters += 1;
-    if (tot[1] > 0.0) { st->nonfinite = 1; st->done = 1; return; }
-    const double rr = tot[0];
-    st->G_old = st->rr > 0.0 ? rr / st->rr : 0.0;  // beta
-    st->rr = rr;
-    st->resid = st->bnorm > 0.0 ? sqrt(rr) / st->bnorm : 0.0;
-    if (st->resid <= kp.tol) st->done = 1;
-  }
-}
-
-template <typename T>
-__global__ void k_mcg_dir(T* __restrict__ z, const T* __restrict__ r, const unsigned char* __restrict__ S,
-                          int n, const SolverState* st) {
-  if (st->done) return;
-  const T beta = (T)st->G_old;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    z[i] = S[i] ? r[i] + beta * z[i] : T(0);
-}
-
-// Eq. 12 detachment of boundary cells and attachment of penetrating cells.
-// Reads S_in (old set), writes S_out; out[0] = changed cells.
-template <typename T>
-__global__ void __launch_bounds__(RED_THREADS)
-k_detach_attach(const T* __restrict__ f, const T* __restrict__ u, T* __restrict__ p,
+// Eq. 12 detachment of boundary cells (a 4-neighbour outside S, or on the
+// grid edge) with p < -sigma_c, attachment of cells outside S with
+// f - d + u < -atol that were not detached in this step.  Reads Sin,
+// writes Sout; partials (detached, attached) -> R_MISC.
+__global__ void __launch_bounds__(RT)
+k_detach_attach(const double* __restrict__ f, const double* __restrict__ u, double* __restrict__ p,
                 const unsigned char* __restrict__ Sin, unsigned char* __restrict__ Sout,
-                unsigned char* __restrict__ det, int N, double d, double sigma_c, double atol,
-                double* part, unsigned* counter, int* changed) {
-  __shared__ double sh[RED_THREADS / 64 * 2];
+                unsigned char* __restrict__ det, int N, double d, double sigma_c, double atol, double* part) {
   const int n = N * N;
   double v[2] = {0.0, 0.0};
   const bool mx[2] = {false, false};
-  for (int i = blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += gridDim.x * RED_THREADS) {
+  GRID_LOOP(i, n) {
     const int r = i / N, c = i - r * N;
     const bool s = Sin[i] != 0;
     bool ns = s;
     if (s) {
       const bool inner = r > 0 && r < N - 1 && c > 0 && c < N - 1 && Sin[i - 1] && Sin[i + 1] &&
                          Sin[i - N] && Sin[i + N];
-      if (!inner && (double)p[i] < -sigma_c) {
+      if (!inner && p[i] < -sigma_c) {
         ns = false;
         det[i] = 1;
-        p[i] = T(0);
+        p[i] = 0.0;
         v[0] += 1.0;
       }
-    } else if (!det[i] && ((double)f[i] - d + (double)u[i] < -atol)) {
+    } else if (!det[i] && (f[i] - d + u[i] < -atol)) {
       ns = true;
       v[1] += 1.0;
     }
     Sout[i] = ns ? 1 : 0;
   }
-  block_reduce<2>(v, mx, sh);
-  double tot[2];
-  if (last_block_fold<2>(v, mx, part, counter, tot, sh) && threadIdx.x == 0) {
-    changed[0] = (int)tot[0];
-    changed[1] = (int)tot[1];
-  }
-}
-
-template <typename T>
-__global__ void k_zero_off(T* __restrict__ p, const unsigned char* __restrict__ S, int n) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    if (!S[i]) p[i] = T(0);
+  block_allreduce<2>(v, mx);
+  write_partials<2>(region(part, R_MISC), v);
 }
 
 // ---------------------------------------------------------------------------
@@ -509,115 +635,239 @@ __global__ void k_zero_off(T* __restrict__ p, const unsigned char* __restrict__ 
 // ---------------------------------------------------------------------------
 struct Ctx {
   cb_plan_s* P;
-  hipStream_t st;
-  int n;
-  int nblk;          // reduction grid
-  int eblk;          // elementwise grid
-  unsigned* counter;
-  double* part;
-  double* scratch;   // small device result area (after the partials)
+  hipStream_t st;   // the plan's own stream
+  int n, nb;
 };
 
 static Ctx make_ctx(cb_plan_s* P) {
   Ctx c;
   c.P = P;
-  c.st = P->stream;
+  c.st = P->istream;
   c.n = P->N * P->N;
-  int nb = (c.n + RED_THREADS * 4 - 1) / (RED_THREADS * 4);
-  if (nb > P->nblk_red - 2) nb = P->nblk_red - 2;
-  if (nb < 1) nb = 1;
-  c.nblk = nb;
-  c.eblk = (c.n + 255) / 256 < 2048 ? (c.n + 255) / 256 : 2048;
-  // d_part: [nblk_red * 8 partials | 16 scratch doubles | counter]
-  c.part = P->d_part;
-  c.scratch = P->d_part + (size_t)P->nblk_red * 8;
-  c.counter = reinterpret_cast<unsigned*>(P->d_part + (size_t)P->nblk_red * 8 + 24);
+  c.nb = P->nbr;
   return c;
 }
 
-static int sync_state(cb_plan_s* P) {
-  CB_HIP(hipMemcpyAsync(P->h_state, P->d_state, sizeof(SolverState), hipMemcpyDeviceToHost, P->stream));
-  CB_HIP(hipStreamSynchronize(P->stream));
+// Order the plan stream after the caller's stream.
+static int enter(cb_plan_s* P) {
+  CB_HIP(hipEventRecord(P->ev_in, P->stream));
+  CB_HIP(hipStreamWaitEvent(P->istream, P->ev_in, 0));
   return CB_OK;
 }
 
 static int read_scratch(const Ctx& c, double* out, int k) {
-  CB_HIP(hipMemcpyAsync(out, c.scratch, k * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  CB_HIP(hipMemcpyAsync(out, c.P->d_part + SCRATCH_OFF, k * sizeof(double), hipMemcpyDeviceToHost, c.st));
   CB_HIP(hipStreamSynchronize(c.st));
   return CB_OK;
 }
 
-template <typename T>
-static int apply(const Ctx& c, const void* x, void* y) {
-  CB_HIP(launch_apply(c.P, x, y, c.st));
+static int read_state(cb_plan_s* P, SolverState* out) {
+  CB_HIP(hipMemcpyAsync(P->h_state, P->d_state, sizeof(SolverState), hipMemcpyDeviceToHost, P->istream));
+  CB_HIP(hipStreamSynchronize(P->istream));
+  *out = *P->h_state;
   return CB_OK;
 }
 
-// One constrained-CG iteration (enqueue only).
-template <typename T>
-static int pk_iteration(const Ctx& c, T* p, const T* f, const KParams& kp) {
+static int write_state(cb_plan_s* P, const SolverState& s) {
+  P->h_state[0] = s;
+  CB_HIP(hipMemcpyAsync(P->d_state, P->h_state, sizeof(SolverState), hipMemcpyHostToDevice, P->istream));
+  return CB_OK;
+}
+
+// direction-type convolution (plan precision), optionally with another table
+static hipError_t apply_dir(const Ctx& c, const void* x, void* y, const int* skip, const void* table = nullptr) {
+  return launch_apply(c.P, x, y, c.st, 7, skip, table, -1);
+}
+// FP64 convolution of the FP64 state
+static hipError_t apply64(const Ctx& c, const double* x, double* y, const int* skip) {
+  return launch_apply(c.P, x, y, c.st, 7, skip, nullptr, 0);
+}
+
+// gbar double buffer lives in the scratch tail (2 doubles)
+static double* gbar2_ptr(cb_plan_s* P) { return P->d_part + SCRATCH_OFF + 24; }
+
+template <typename TD>
+static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, bool force, bool pc, int chunk) {
   cb_plan_s* P = c.P;
-  T* u = (T*)P->d_u;
-  T* g = (T*)P->d_g;
-  T* t = (T*)P->d_t;
-  T* r = (T*)P->d_r;
+  double* u = (double*)P->d_u;
+  double* g = (double*)P->d_g;
+  TD* t = (TD*)P->d_t;
+  TD* r = (TD*)P->d_r;
+  TD* gm = (TD*)P->d_pold;
   SolverState* st = P->d_state;
-  if (kp.force)
-    hipLaunchKernelGGL(k_mean_gap<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, p, u, f, kp, st, c.part, c.counter);
-  hipLaunchKernelGGL(k_gap<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, p, u, f, g, kp, st, c.part, c.counter);
-  hipLaunchKernelGGL(k_dir<T>, dim3(c.eblk), dim3(256), 0, c.st, p, g, t, c.n, st);
-  if (int rc = apply<T>(c, t, r)) return rc;
-  if (kp.force)
-    hipLaunchKernelGGL(k_mean_r<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, p, r, kp, st, c.part, c.counter);
-  hipLaunchKernelGGL(k_step<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, p, g, t, r, kp, st, c.part, c.counter);
-  hipLaunchKernelGGL(k_update<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, p, g, t, kp, st, c.part, c.counter);
-  if (kp.force) hipLaunchKernelGGL(k_rescale<T>, dim3(c.eblk), dim3(256), 0, c.st, p, c.n, st);
-  if (int rc = apply<T>(c, p, u)) return rc;
-  CB_HIP(hipGetLastError());
-  return CB_OK;
+  double* part = P->d_part;
+  double* gb = gbar2_ptr(P);
+  const dim3 grid(c.nb), blk(RT);
+  const int* skip_done = &st->done;   // {done, zero}
+  const int* skip_u = &st->skip_u;    // {skip_u, done}
+  for (int i = 0; i < chunk; i++) {
+    const int par = i & 1;
+    hipLaunchKernelGGL(k_pk_gap, grid, blk, 0, c.st, p, u, f, g, st, gb, part, c.n, par);
+    if (pc) {
+      hipLaunchKernelGGL(k_pk_gmask<TD>, grid, blk, 0, c.st, p, g, gm, st, gb, part, c.nb, c.n, par);
+      // z' = M^-1 gm (into r, free until K t is formed)
+      if (hipError_t e = apply_dir(c, gm, r, skip_done, P->d_ptable)) return e;
+      hipLaunchKernelGGL(k_pk_zdot<TD>, grid, blk, 0, c.st, p, g, r, st, part, c.n, par);
+      hipLaunchKernelGGL(k_pk_dir_pc<TD>, grid, blk, 0, c.st, p, r, t, st, part, c.nb, c.n, par);
+    } else {
+      hipLaunchKernelGGL(k_pk_dir<TD>, grid, blk, 0, c.st, p, g, t, st, gb, part, c.nb, c.n, par);
+    }
+    if (hipError_t e = apply_dir(c, t, r, skip_done)) return e;
+    hipLaunchKernelGGL(k_pk_step<TD>, grid, blk, 0, c.st, p, g, t, r, st, part, c.n);
+    hipLaunchKernelGGL(k_pk_update<TD>, grid, blk, 0, c.st, p, u, g, t, r, st, part, c.nb, c.n);
+    hipLaunchKernelGGL(k_pk_post, force ? grid : dim3(1), blk, 0, c.st, p, u, st, part, c.nb, c.n,
+                       i == chunk - 1 ? 1 : 0);
+    if (hipError_t e = apply64(c, p, u, skip_u)) return e;
+  }
+  return hipGetLastError();
 }
 
-static void fill_opts(const cb_plan_s* P, const cb_solve_opts* o, double& tol, int& max_iter, int& chunk,
-                      int& init, double& atol, int& max_rounds) {
+template <typename TD>
+static hipError_t mcg_enqueue_chunk(const Ctx& c, double* x, const unsigned char* S, int chunk) {
+  cb_plan_s* P = c.P;
+  double* r = (double*)P->d_g;
+  TD* z = (TD*)P->d_t;
+  TD* q = (TD*)P->d_r;
+  SolverState* st = P->d_state;
+  double* part = P->d_part;
+  const dim3 grid(c.nb), blk(RT);
+  for (int i = 0; i < chunk; i++) {
+    const int par = i & 1;
+    if (hipError_t e = apply_dir(c, z, q, &st->done)) return e;
+    hipLaunchKernelGGL(k_mcg_zq<TD>, grid, blk, 0, c.st, (const TD*)z, (const TD*)q, S, st, part, c.n);
+    hipLaunchKernelGGL(k_mcg_upd<TD>, grid, blk, 0, c.st, x, r, (const TD*)z, (const TD*)q, S, st, part, c.nb, c.n,
+                       par);
+    hipLaunchKernelGGL(k_mcg_dir<TD>, grid, blk, 0, c.st, z, (const double*)r, S, st, part, c.nb, c.n, par);
+  }
+  return hipGetLastError();
+}
+
+// Captured graph of one chunk, cached per (kind, pointers, chunk).
+template <class Enq>
+static hipGraphExec_t chunk_graph(cb_plan_s* P, int kind, const void* a, const void* b, const void* cc, int chunk,
+                                  Enq enqueue) {
+  if (!P->use_graphs) return nullptr;
+  GraphEntry* lru = &P->graphs[0];
+  for (auto& e : P->graphs) {
+    if (e.exec && e.kind == kind && e.a == a && e.b == b && e.c == cc && e.chunk == chunk) {
+      e.used = ++P->graph_clock;
+      return e.exec;
+    }
+    if (!e.exec || e.used < lru->used) lru = &e;
+  }
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  if (hipStreamBeginCapture(P->istream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    P->use_graphs = 0;
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  const hipError_t e1 = enqueue();
+  const hipError_t e2 = hipStreamEndCapture(P->istream, &g);
+  if (e1 != hipSuccess || e2 != hipSuccess || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    P->use_graphs = 0;
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  (void)hipGraphDestroy(g);
+  if (lru->exec) (void)hipGraphExecDestroy(lru->exec);
+  lru->kind = kind;
+  lru->a = a;
+  lru->b = b;
+  lru->c = cc;
+  lru->chunk = chunk;
+  lru->exec = ex;
+  lru->used = ++P->graph_clock;
+  return ex;
+}
+
+// Run chunks until the device flags convergence (or max_iter launched).
+// Up to two chunks are in flight while the host checks the older one.
+template <class Enq>
+static int run_chunks(cb_plan_s* P, int kind, const void* a, const void* b, const void* cc, int chunk, int max_iter,
+                      Enq enqueue, SolverState* out) {
+  hipGraphExec_t ex = chunk_graph(P, kind, a, b, cc, chunk, enqueue);
+  int launched = 0, slot = 0;
+  int inflight[2], nin = 0;  // state-copy slots of launched, unchecked chunks (oldest first)
+  while (true) {
+    if (launched < max_iter && nin < 2) {
+      if (ex) CB_HIP(hipGraphLaunch(ex, P->istream));
+      else CB_HIP(enqueue());
+      launched += chunk;
+      CB_HIP(hipMemcpyAsync(&P->h_state[slot], P->d_state, sizeof(SolverState), hipMemcpyDeviceToHost, P->istream));
+      CB_HIP(hipEventRecord(P->ev_state[slot], P->istream));
+      inflight[nin++] = slot;
+      slot ^= 1;
+      continue;
+    }
+    if (nin == 0) break;
+    const int chk = inflight[0];
+    inflight[0] = inflight[1];
+    nin--;
+    CB_HIP(hipEventSynchronize(P->ev_state[chk]));
+    const SolverState& s = P->h_state[chk];
+    if (s.done || s.nonfinite) break;
+  }
+  CB_HIP(hipStreamSynchronize(P->istream));
+  return read_state(P, out);
+}
+
+struct Opts {
+  double tol, atol;
+  int max_iter, chunk, init, max_rounds, precond;
+};
+
+static Opts fill_opts(const cb_plan_s* P, const cb_solve_opts* o) {
   cb_solve_opts d{};
+  d.precond = -1;
+  d.attach_tol = -1.0;
   if (o) d = *o;
-  tol = d.tol > 0 ? d.tol : (P->precision == CB_FP64 ? 1e-10 : 1e-6);
-  max_iter = d.max_iter > 0 ? d.max_iter : 20000;
-  chunk = d.chunk > 0 ? d.chunk : 16;
-  init = d.init;
-  atol = d.attach_tol >= 0 ? d.attach_tol : (P->precision == CB_FP64 ? 1e-12 : 1e-6) * P->L;
-  max_rounds = d.max_rounds > 0 ? d.max_rounds : 10000;
+  Opts r;
+  r.tol = d.tol > 0 ? d.tol : (P->precision == CB_FP64 ? 1e-10 : 1e-8);
+  r.max_iter = d.max_iter > 0 ? d.max_iter : 20000;
+  r.chunk = d.chunk > 0 ? d.chunk : 16;
+  r.chunk += r.chunk & 1;  // even: iteration parity restarts at 0 in every chunk
+  if (r.chunk > r.max_iter) r.chunk = r.max_iter + (r.max_iter & 1);
+  r.init = d.init;
+  r.atol = d.attach_tol >= 0 ? d.attach_tol : (P->precision == CB_FP64 ? 1e-12 : 1e-9) * P->L;
+  r.max_rounds = d.max_rounds > 0 ? d.max_rounds : 10000;
+  r.precond = d.precond;
+  return r;
 }
 
-static void reset_state(cb_plan_s* P, double d) {
+static SolverState base_state(const cb_plan_s* P, double tol, double d_in, bool force, double F) {
   SolverState s{};
-  s.G_old = 1.0;
-  s.delta = 0.0;
-  s.d = d;
-  s.bnorm = 1.0;
-  *P->h_state = s;
+  s.tol = tol;
+  s.Ftarget = F;
+  s.dA = P->dx * P->dx;
+  s.k00 = P->k00;
+  s.d_in = d_in;
+  s.force = force ? 1 : 0;
+  s.d = d_in;
+  return s;
 }
 
-template <typename T>
-static int pk_solve(cb_plan_s* P, const T* f, double target, bool force, T* p, unsigned char* mask,
+template <typename TD>
+static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, double* p, unsigned char* mask,
                     const cb_solve_opts* o, cb_result* res) {
   const auto t0 = std::chrono::steady_clock::now();
   Ctx c = make_ctx(P);
-  double tol, atol;
-  int max_iter, chunk, init, max_rounds;
-  fill_opts(P, o, tol, max_iter, chunk, init, atol, max_rounds);
+  const Opts op = fill_opts(P, o);
   const double dA = P->dx * P->dx;
   *res = cb_result{};
-  // profile range and finiteness
-  hipLaunchKernelGGL(k_minmax<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, f, c.n, c.part, c.counter, c.scratch);
+  if (int rc = enter(P)) return rc;
+  const dim3 grid(c.nb), blk(RT);
+  hipLaunchKernelGGL(k_minmax, grid, blk, 0, c.st, f, P->d_part, c.n);
+  hipLaunchKernelGGL(k_fold_misc<3>, dim3(1), blk, 0, c.st, P->d_part, c.nb, 7);
   double mm[3];
-  if (int rc = read_scratch(c, mm, 3)) return rc;  // (synchronises)
+  if (int rc = read_scratch(c, mm, 3)) return rc;
   if (mm[2] > 0.0) return cb_fail(CB_E_NONFINITE, "profile f contains NaN/Inf");
-  const double fmin = mm[0];
-  bool trivial = force ? !(target > 0.0) : (target <= fmin);
+  const double fmin = -mm[0];
+  const bool trivial = force ? !(target > 0.0) : (target <= fmin);
   if (trivial) {
-    hipLaunchKernelGGL(k_fill<T>, dim3(c.eblk), dim3(256), 0, c.st, p, c.n, 0.0);
-    if (mask) CB_HIP(hipMemsetAsync(mask, 0, c.n, c.st));
+    hipLaunchKernelGGL(k_fill, grid, blk, 0, c.st, p, c.n, 0.0);
+    if (mask) hipLaunchKernelGGL(k_zero_bytes, grid, blk, 0, c.st, mask, c.n);
     CB_HIP(hipStreamSynchronize(c.st));
     res->status = CB_OK;
     res->d = force ? fmin : target;
@@ -625,55 +875,37 @@ static int pk_solve(cb_plan_s* P, const T* f, double target, bool force, T* p, u
     return CB_OK;
   }
   // initial pressure
-  if (init == 1) {
-    hipLaunchKernelGGL(k_clamp_pos<T>, dim3(c.eblk), dim3(256), 0, c.st, p, c.n);
-  } else if (force) {
-    hipLaunchKernelGGL(k_fill<T>, dim3(c.eblk), dim3(256), 0, c.st, p, c.n, target / (dA * c.n));
-  } else {
-    hipLaunchKernelGGL(k_init_disp<T>, dim3(c.eblk), dim3(256), 0, c.st, p, f, c.n, target, P->k00);
-  }
-  reset_state(P, force ? 0.0 : target);
-  if (force) {
-    // rescale to the target force
-    hipLaunchKernelGGL(k_stats<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, p, p, (const unsigned char*)nullptr,
-                       c.n, c.part, c.counter, c.scratch);
-    double s4[4];
-    if (int rc = read_scratch(c, s4, 4)) return rc;
-    if (!(s4[0] > 0.0) || s4[3] > 0.0) return cb_fail(CB_E_NONFINITE, "initial pressure has no positive finite part");
-    P->h_state->bnorm = target / (dA * s4[0]);
-  }
-  CB_HIP(hipMemcpyAsync(P->d_state, P->h_state, sizeof(SolverState), hipMemcpyHostToDevice, c.st));
-  if (force) hipLaunchKernelGGL(k_rescale<T>, dim3(c.eblk), dim3(256), 0, c.st, p, c.n, P->d_state);
-  if (int rc = apply<T>(c, p, P->d_u)) return rc;
-  KParams kp{c.n, force ? 1 : 0, tol, force ? target : 0.0, dA, P->k00};
-  int status = CB_E_NOCONV;
-  int launched = 0;
-  while (launched < max_iter) {
-    const int k = chunk < max_iter - launched ? chunk : max_iter - launched;
-    for (int i = 0; i < k; i++)
-      if (int rc = pk_iteration<T>(c, p, f, kp)) return rc;
-    launched += k;
-    if (int rc = sync_state(P)) return rc;
-    if (P->h_state->nonfinite) { status = CB_E_NONFINITE; break; }
-    if (P->h_state->done) { status = CB_OK; break; }
-  }
-  if (status == CB_E_NOCONV) {
-    // the last launched check may have converged
-    if (P->h_state->done) status = CB_OK;
-  }
-  SolverState s = *P->h_state;
-  hipLaunchKernelGGL(k_stats<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, p, (const T*)P->d_u,
-                     (const unsigned char*)nullptr, c.n, c.part, c.counter, c.scratch);
+  if (op.init == 1) hipLaunchKernelGGL(k_clamp_pos, grid, blk, 0, c.st, p, c.n);
+  else if (force) hipLaunchKernelGGL(k_fill, grid, blk, 0, c.st, p, c.n, target / (dA * c.n));
+  else hipLaunchKernelGGL(k_init_disp, grid, blk, 0, c.st, p, f, c.n, target, P->k00);
+  if (int rc = write_state(P, base_state(P, op.tol, force ? 0.0 : target, force, force ? target : 0.0))) return rc;
+  CB_HIP(hipMemsetAsync(gbar2_ptr(P), 0, 2 * sizeof(double), c.st));
+  // direction buffers start at zero so that a solve never depends on what a
+  // previous call left in the workspace
+  CB_HIP(hipMemsetAsync(P->d_t, 0, (size_t)c.n * 8, c.st));
+  CB_HIP(hipMemsetAsync(P->d_r, 0, (size_t)c.n * 8, c.st));
+  CB_HIP(hipMemsetAsync(P->d_pold, 0, (size_t)c.n * 8, c.st));
+  hipLaunchKernelGGL(k_pk_seed, grid, blk, 0, c.st, (const double*)p, P->d_part, c.n);
+  if (force) hipLaunchKernelGGL(k_pk_scale0, grid, blk, 0, c.st, p, P->d_state, P->d_part, c.nb, c.n);
+  CB_HIP(apply64(c, p, (double*)P->d_u, nullptr));
+  SolverState s;
+  const bool pc = op.precond < 0 ? P->precond_auto != 0 : op.precond > 0;
+  auto enq = [&]() { return pk_enqueue_chunk<TD>(c, p, f, force, pc, op.chunk); };
+  if (int rc = run_chunks(P, (force ? 1 : 0) + (pc ? 4 : 0), p, f, nullptr, op.chunk, op.max_iter, enq, &s)) return rc;
+  const int status = s.nonfinite ? CB_E_NONFINITE : (s.done ? CB_OK : CB_E_NOCONV);
+  hipLaunchKernelGGL(k_stats, grid, blk, 0, c.st, (const double*)p, (const double*)P->d_u,
+                     (const unsigned char*)nullptr, P->d_part, c.n);
+  hipLaunchKernelGGL(k_fold_misc<4>, dim3(1), blk, 0, c.st, P->d_part, c.nb, 8);
   double s4[4];
   if (int rc = read_scratch(c, s4, 4)) return rc;
-  if (mask) hipLaunchKernelGGL(k_mask_from_p<T>, dim3(c.eblk), dim3(256), 0, c.st, p, mask, c.n);
+  if (mask) hipLaunchKernelGGL(k_mask_from_p, grid, blk, 0, c.st, (const double*)p, mask, c.n);
   CB_HIP(hipStreamSynchronize(c.st));
   res->status = status;
   res->iters = s.iters;
   res->rounds = 0;
   res->resid = s.resid;
   res->F = dA * s4[0];
-  res->d = s.d;
+  res->d = force ? s.d : target;
   res->area = dA * s4[1];
   res->U_el = 0.5 * dA * s4[2];
   res->U_ad = 0.0;
@@ -683,87 +915,72 @@ static int pk_solve(cb_plan_s* P, const T* f, double target, bool force, T* p, u
   return CB_OK;
 }
 
-// CG on the fixed set S (device mask); x in/out.  The recurrence residual
-// is confirmed by a true residual b - K x after convergence; if that is
-// still above tol the CG restarts from x (at most twice more).
-template <typename T>
-static int set_solve(const Ctx& c, const T* f, double d, const unsigned char* S, T* x, double tol,
+// CG on the fixed set S; x in/out.  The recurrence residual is confirmed by
+// the true residual b - K x computed with an FP64 convolution; if that is
+// still above tol the CG restarts from x (iterative refinement; at most two
+// restarts).
+template <typename TD>
+static int set_solve(const Ctx& c, const double* f, double d, const unsigned char* S, double* x, double tol,
                      int max_iter, int chunk, int& iters, double& resid) {
   cb_plan_s* P = c.P;
-  T* u = (T*)P->d_u;
-  T* r = (T*)P->d_g;
-  T* z = (T*)P->d_t;
-  T* q = (T*)P->d_r;
-  KParams kp{c.n, 0, tol, 0.0, P->dx * P->dx, P->k00};
+  double* u = (double*)P->d_u;
+  double* r = (double*)P->d_g;
+  TD* z = (TD*)P->d_t;
+  const dim3 grid(c.nb), blk(RT);
   int budget = max_iter;
   for (int attempt = 0; attempt < 3; attempt++) {
-    reset_state(P, d);
-    CB_HIP(hipMemcpyAsync(P->d_state, P->h_state, sizeof(SolverState), hipMemcpyHostToDevice, c.st));
-    hipLaunchKernelGGL(k_zero_off<T>, dim3(c.eblk), dim3(256), 0, c.st, x, S, c.n);
-    if (int rc = apply<T>(c, x, u)) return rc;
-    hipLaunchKernelGGL(k_mcg_init<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, f, (const T*)u, S, r, z, kp,
-                       P->d_state, c.part, c.counter);
-    if (int rc = sync_state(P)) return rc;
-    if (P->h_state->nonfinite) return CB_E_NONFINITE;
-    resid = P->h_state->resid;
-    if (P->h_state->done || attempt == 2) return CB_OK;  // true residual checked
-    int launched = 0;
-    while (launched < budget && !P->h_state->done) {
-      const int k = chunk < budget - launched ? chunk : budget - launched;
-      for (int i = 0; i < k; i++) {
-        if (int rc = apply<T>(c, z, q)) return rc;
-        hipLaunchKernelGGL(k_mcg_alpha<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, (const T*)z, (const T*)q, S, kp,
-                           P->d_state, c.part, c.counter);
-        hipLaunchKernelGGL(k_mcg_update<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, x, r, (const T*)z,
-                           (const T*)q, S, kp, P->d_state, c.part, c.counter);
-        hipLaunchKernelGGL(k_mcg_dir<T>, dim3(c.eblk), dim3(256), 0, c.st, z, (const T*)r, S, c.n, P->d_state);
-      }
-      launched += k;
-      if (int rc = sync_state(P)) return rc;
-      if (P->h_state->nonfinite) return CB_E_NONFINITE;
-    }
-    iters += P->h_state->iters;
-    budget -= launched;
-    if (!P->h_state->done) return CB_E_NOCONV;
+    if (int rc = write_state(P, base_state(P, tol, d, false, 0.0))) return rc;
+    hipLaunchKernelGGL(k_zero_off, grid, blk, 0, c.st, x, S, c.n);
+    CB_HIP(apply64(c, x, u, nullptr));
+    hipLaunchKernelGGL(k_mcg_init<TD>, grid, blk, 0, c.st, f, (const double*)u, S, r, z, P->d_state, P->d_part, c.n);
+    hipLaunchKernelGGL(k_mcg_init_fin, dim3(1), blk, 0, c.st, P->d_state, P->d_part, c.nb);
+    SolverState s;
+    if (int rc = read_state(P, &s)) return rc;
+    if (s.nonfinite) return CB_E_NONFINITE;
+    resid = s.resid;
+    if (s.done || attempt == 2 || budget <= 0) return (s.done || attempt == 2) ? CB_OK : CB_E_NOCONV;
+    auto enq = [&]() { return mcg_enqueue_chunk<TD>(c, x, S, chunk); };
+    if (int rc = run_chunks(P, 2, x, S, f, chunk, budget, enq, &s)) return rc;
+    iters += s.iters;
+    budget -= s.iters;
+    if (s.nonfinite) return CB_E_NONFINITE;
+    if (!s.done) return CB_E_NOCONV;
   }
   return CB_OK;
 }
 
-// One adhesive displacement step on state (S in P->d_mask via `S`, p).
-// Returns status; fills res (without timing).
-template <typename T>
-static int adhesive_step(const Ctx& c, const T* f, double d, T* p, unsigned char*& S, unsigned char*& Salt,
-                         bool attach_start, double tol, int max_iter, int chunk, double atol, int max_rounds,
-                         cb_result* res) {
+// One adhesive displacement step on the state (S, p); S/Salt are the two
+// contact-set buffers (swapped as rounds proceed).
+template <typename TD>
+static int adhesive_step(const Ctx& c, const double* f, double d, double* p, unsigned char*& S,
+                         unsigned char*& Salt, bool attach_start, const Opts& op, cb_result* res) {
   cb_plan_s* P = c.P;
-  T* u = (T*)P->d_u;
+  double* u = (double*)P->d_u;
   const double dA = P->dx * P->dx;
+  const dim3 grid(c.nb), blk(RT);
   int iters = 0, rounds = 0, status = CB_OK;
   double resid = 0.0;
   if (attach_start) {
-    if (int rc = apply<T>(c, p, u)) return rc;
-    hipLaunchKernelGGL(k_attach_start<T>, dim3(c.eblk), dim3(256), 0, c.st, f, (const T*)u, d, S, P->d_det, p, c.n);
-  } else {
-    CB_HIP(hipMemsetAsync(P->d_det, 0, c.n, c.st));
+    CB_HIP(apply64(c, p, u, nullptr));
+    hipLaunchKernelGGL(k_attach_start, grid, blk, 0, c.st, f, (const double*)u, d, S, P->d_det, p, c.n);
   }
-  int* changed = reinterpret_cast<int*>(c.scratch + 8);
-  while (rounds < max_rounds) {
+  while (rounds < op.max_rounds) {
     rounds++;
-    int rc = set_solve<T>(c, f, d, S, p, tol, max_iter, chunk, iters, resid);
+    const int rc = set_solve<TD>(c, f, d, S, p, op.tol, op.max_iter, op.chunk, iters, resid);
     if (rc != CB_OK) { status = rc; break; }
-    if (int e = apply<T>(c, p, u)) return e;
-    hipLaunchKernelGGL(k_detach_attach<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, f, (const T*)u, p,
-                       (const unsigned char*)S, Salt, P->d_det, P->N, d, P->sigma_c, atol, c.part, c.counter,
-                       changed);
-    int ch[2];
-    CB_HIP(hipMemcpyAsync(ch, changed, sizeof(ch), hipMemcpyDeviceToHost, c.st));
-    CB_HIP(hipStreamSynchronize(c.st));
+    CB_HIP(apply64(c, p, u, nullptr));
+    hipLaunchKernelGGL(k_detach_attach, grid, blk, 0, c.st, f, (const double*)u, p, (const unsigned char*)S, Salt,
+                       P->d_det, P->N, d, P->sigma_c, op.atol, P->d_part);
+    hipLaunchKernelGGL(k_fold_misc<2>, dim3(1), blk, 0, c.st, P->d_part, c.nb, 0);
+    double ch[2];
+    if (int e = read_scratch(c, ch, 2)) return e;
     std::swap(S, Salt);
-    if (ch[0] == 0 && ch[1] == 0) break;
-    if (rounds == max_rounds) status = CB_E_NOCONV;
+    if (ch[0] == 0.0 && ch[1] == 0.0) break;
+    if (rounds == op.max_rounds) status = CB_E_NOCONV;
   }
-  hipLaunchKernelGGL(k_stats<T>, dim3(c.nblk), dim3(RED_THREADS), 0, c.st, (const T*)p, (const T*)u,
-                     (const unsigned char*)S, c.n, c.part, c.counter, c.scratch);
+  hipLaunchKernelGGL(k_stats, grid, blk, 0, c.st, (const double*)p, (const double*)u, (const unsigned char*)S,
+                     P->d_part, c.n);
+  hipLaunchKernelGGL(k_fold_misc<4>, dim3(1), blk, 0, c.st, P->d_part, c.nb, 8);
   double s4[4];
   if (int rc = read_scratch(c, s4, 4)) return rc;
   res->status = status;
@@ -778,40 +995,38 @@ static int adhesive_step(const Ctx& c, const T* f, double d, T* p, unsigned char
   return status;
 }
 
-template <typename T>
-static int adhesive_indent(cb_plan_s* P, const T* f, double d, T* p, unsigned char* mask_io,
+template <typename TD>
+static int adhesive_indent(cb_plan_s* P, const double* f, double d, double* p, unsigned char* mask_io,
                            const cb_solve_opts* o, cb_result* res) {
   const auto t0 = std::chrono::steady_clock::now();
   Ctx c = make_ctx(P);
-  double tol, atol;
-  int max_iter, chunk, init, max_rounds;
-  fill_opts(P, o, tol, max_iter, chunk, init, atol, max_rounds);
+  const Opts op = fill_opts(P, o);
   *res = cb_result{};
+  if (int rc = enter(P)) return rc;
   unsigned char* S = P->d_mask;
   unsigned char* Salt = P->d_mask2;
-  hipLaunchKernelGGL(k_mask_overlap<T>, dim3(c.eblk), dim3(256), 0, c.st, f, d, S, p, c.n);
-  int rc = adhesive_step<T>(c, f, d, p, S, Salt, false, tol, max_iter, chunk, atol, max_rounds, res);
-  if (mask_io && S != mask_io) CB_HIP(hipMemcpyAsync(mask_io, S, c.n, hipMemcpyDeviceToDevice, c.st));
+  hipLaunchKernelGGL(k_mask_overlap, dim3(c.nb), dim3(RT), 0, c.st, f, d, S, P->d_det, p, c.n);
+  const int rc = adhesive_step<TD>(c, f, d, p, S, Salt, false, op, res);
+  if (mask_io) CB_HIP(hipMemcpyAsync(mask_io, S, c.n, hipMemcpyDeviceToDevice, c.st));
   CB_HIP(hipStreamSynchronize(c.st));
   res->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (rc != CB_OK) return cb_fail(rc, "adhesive solve did not converge");
   return CB_OK;
 }
 
-template <typename T>
-static int sweep_impl(cb_plan_s* P, const T* f, const double* dsteps, int nsteps, T* p, unsigned char* mask,
-                      const cb_solve_opts* o, cb_result* out) {
+template <typename TD>
+static int sweep_impl(cb_plan_s* P, const double* f, const double* dsteps, int nsteps, double* p,
+                      unsigned char* mask, const cb_solve_opts* o, cb_result* out) {
   Ctx c = make_ctx(P);
-  double tol, atol;
-  int max_iter, chunk, init, max_rounds;
-  fill_opts(P, o, tol, max_iter, chunk, init, atol, max_rounds);
+  const Opts op = fill_opts(P, o);
+  if (int rc = enter(P)) return rc;
   unsigned char* S = mask;
   unsigned char* Salt = P->d_mask;
   int first_err = CB_OK;
   for (int k = 0; k < nsteps; k++) {
     const auto t0 = std::chrono::steady_clock::now();
     out[k] = cb_result{};
-    int rc = adhesive_step<T>(c, f, dsteps[k], p, S, Salt, true, tol, max_iter, chunk, atol, max_rounds, &out[k]);
+    const int rc = adhesive_step<TD>(c, f, dsteps[k], p, S, Salt, true, op, &out[k]);
     out[k].ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (rc != CB_OK && first_err == CB_OK) first_err = rc;
     if (rc == CB_E_DEVICE || rc == CB_E_NONFINITE) break;
@@ -826,38 +1041,34 @@ static int sweep_impl(cb_plan_s* P, const T* f, const double* dsteps, int nsteps
 
 using namespace cb;
 
-extern "C" int cb_solve_indent(cb_plan P, const void* f, double d, void* p_io, unsigned char* mask_io,
+extern "C" int cb_solve_indent(cb_plan P, const double* f, double d, double* p_io, unsigned char* mask_io,
                                const cb_solve_opts* o, cb_result* res) {
   if (!P || !f || !p_io || !res) return cb_fail(CB_E_INVALID, "null argument");
   if (!std::isfinite(d)) return cb_fail(CB_E_INVALID, "d must be finite");
   if (P->dgamma > 0.0) {
-    if (P->precision == CB_FP64)
-      return adhesive_indent<double>(P, (const double*)f, d, (double*)p_io, mask_io, o, res);
-    return adhesive_indent<float>(P, (const float*)f, d, (float*)p_io, mask_io, o, res);
+    if (P->precision == CB_FP64) return adhesive_indent<double>(P, f, d, p_io, mask_io, o, res);
+    return adhesive_indent<float>(P, f, d, p_io, mask_io, o, res);
   }
-  if (P->precision == CB_FP64)
-    return pk_solve<double>(P, (const double*)f, d, false, (double*)p_io, mask_io, o, res);
-  return pk_solve<float>(P, (const float*)f, d, false, (float*)p_io, mask_io, o, res);
+  if (P->precision == CB_FP64) return pk_solve<double>(P, f, d, false, p_io, mask_io, o, res);
+  return pk_solve<float>(P, f, d, false, p_io, mask_io, o, res);
 }
 
-extern "C" int cb_solve_force(cb_plan P, const void* f, double F, void* p_io, unsigned char* mask_io,
+extern "C" int cb_solve_force(cb_plan P, const double* f, double F, double* p_io, unsigned char* mask_io,
                               const cb_solve_opts* o, cb_result* res) {
   if (!P || !f || !p_io || !res) return cb_fail(CB_E_INVALID, "null argument");
   if (!std::isfinite(F) || F < 0.0) return cb_fail(CB_E_INVALID, "F must be finite and >= 0");
   if (P->dgamma > 0.0) return cb_fail(CB_E_UNSUPPORTED, "force control is provided for non-adhesive plans");
-  if (P->precision == CB_FP64)
-    return pk_solve<double>(P, (const double*)f, F, true, (double*)p_io, mask_io, o, res);
-  return pk_solve<float>(P, (const float*)f, F, true, (float*)p_io, mask_io, o, res);
+  if (P->precision == CB_FP64) return pk_solve<double>(P, f, F, true, p_io, mask_io, o, res);
+  return pk_solve<float>(P, f, F, true, p_io, mask_io, o, res);
 }
 
-extern "C" int cb_sweep(cb_plan P, const void* f, const double* d_steps, int nsteps, void* p_state,
+extern "C" int cb_sweep(cb_plan P, const double* f, const double* d_steps, int nsteps, double* p_state,
                         unsigned char* mask_state, const cb_solve_opts* o, cb_result* per_step) {
   if (!P || !f || !d_steps || !p_state || !mask_state || !per_step || nsteps < 0)
     return cb_fail(CB_E_INVALID, "null argument or negative step count");
   if (!(P->dgamma > 0.0)) return cb_fail(CB_E_UNSUPPORTED, "sweep needs an adhesive plan (dgamma > 0)");
   for (int k = 0; k < nsteps; k++)
     if (!std::isfinite(d_steps[k])) return cb_fail(CB_E_INVALID, "non-finite displacement step");
-  if (P->precision == CB_FP64)
-    return sweep_impl<double>(P, (const double*)f, d_steps, nsteps, (double*)p_state, mask_state, o, per_step);
-  return sweep_impl<float>(P, (const float*)f, d_steps, nsteps, (float*)p_state, mask_state, o, per_step);
+  if (P->precision == CB_FP64) return sweep_impl<double>(P, f, d_steps, nsteps, p_state, mask_state, o, per_step);
+  return sweep_impl<float>(P, f, d_steps, nsteps, p_state, mask_state, o, per_step);
 }

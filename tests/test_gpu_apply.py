@@ -74,6 +74,19 @@ def test_apply_zero_and_determinism(lib):
     assert torch.equal(u1, u2)
 
 
+@pytest.mark.parametrize("N", [128, 1024])
+def test_apply_fp32_deterministic(lib, N):
+    plan = lib.cb_plan_create(N, 1.0, 0.1, 10.0, 0.3, 1.0, 0.3, 0.0, "fp32")
+    g = torch.Generator("cuda").manual_seed(2)
+    p = torch.rand(N, N, dtype=torch.float32, device="cuda", generator=g)
+    us = [torch.empty_like(p) for _ in range(4)]
+    for u in us:
+        lib.cb_apply_K(plan, p, u)
+    torch.cuda.synchronize()
+    for u in us[1:]:
+        assert torch.equal(us[0], u)
+
+
 def test_apply_on_side_stream(lib):
     N = 64
     s = torch.cuda.Stream()

@@ -4,8 +4,9 @@ Metrics (both sides on the same seeded inputs):
   pressure relative L2 error, total-force relative error, contact-set
   agreement 1 - |S_gpu ^ S_ora| / |S_gpu u S_ora|.
 Bars: FP64 path 1e-8 / 1e-10 / identical sets (the LCP solution is unique
-and both sides converge to 1e-10); FP32 path (FP32 fields and FFT, FP64
-reductions) 1e-4 / 1e-5 / >= 0.999.
+and both sides converge to 1e-10); FP32 path (FP32 search-direction
+convolutions, FP64 state and reductions, residual 1e-8) 1e-4 / 1e-5 /
+>= 0.999 (the spec bar; observed errors are far smaller).
 """
 import math
 
@@ -40,10 +41,10 @@ def test_config1_indent(lib, prec):
     op = Operator(c.N, c.L, Material(c.h, c.E1, c.nu1, c.E2, c.nu2))
     ref = solve_pk(op, c.f, c.target, tol=1e-10)
     plan = _plan(lib, c, prec)
-    f = torch.tensor(c.f, dtype=DT[prec], device="cuda")
+    f = torch.tensor(c.f, dtype=torch.float64, device="cuda")
     p = torch.zeros_like(f)
     mask = torch.zeros(c.N, c.N, dtype=torch.uint8, device="cuda")
-    res = lib.cb_solve_indent(plan, f, c.target, p, mask, tol=1e-10 if prec == "fp64" else 1e-6)
+    res = lib.cb_solve_indent(plan, f, c.target, p, mask, tol=1e-10 if prec == "fp64" else 1e-8)
     pg = p.double().cpu().numpy()
     e_p = np.linalg.norm(pg - ref.p) / np.linalg.norm(ref.p)
     e_F = abs(res["F"] - ref.F) / ref.F
@@ -68,9 +69,9 @@ def test_indent_and_force_N256(lib, prec, shape):
     op = Operator(N, L, mat)
     ref = solve_pk(op, f, d, tol=1e-10)
     plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, 0.0, prec)
-    ft = torch.tensor(f, dtype=DT[prec], device="cuda")
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
     p = torch.zeros_like(ft)
-    tol = 1e-10 if prec == "fp64" else 1e-6
+    tol = 1e-10 if prec == "fp64" else 1e-8
     res = lib.cb_solve_indent(plan, ft, d, p, tol=tol)
     e_p = np.linalg.norm(p.double().cpu().numpy() - ref.p) / np.linalg.norm(ref.p)
     print(f"  indent iters {res['iters']} (oracle {ref.iters}) e_p {e_p:.2e}")
@@ -117,10 +118,10 @@ def test_adhesive_sweep_short(lib, prec):
     sc = critical_stress(mat, dg, L / N)
     out, st = sweep(op, f, steps, sc, 1e-12 * L, dg, tol=1e-10)
     plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, dg, prec)
-    ft = torch.tensor(f, dtype=DT[prec], device="cuda")
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
     p = torch.zeros_like(ft)
     mask = torch.zeros(N, N, dtype=torch.uint8, device="cuda")
-    res = lib.cb_sweep(plan, ft, steps, p, mask, tol=1e-10 if prec == "fp64" else 1e-6)
+    res = lib.cb_sweep(plan, ft, steps, p, mask, tol=1e-10 if prec == "fp64" else 1e-8)
     Fspan = max(abs(o["F"]) for o in out)
     for o, r in zip(out, res):
         print(f"  d={o['d']:+.4e} F {r['F']:+.6e} vs {o['F']:+.6e} A {r['area']:.5f} vs {o['area']:.5f}")
@@ -152,3 +153,24 @@ def test_error_paths(lib):
     # no overlap: zero pressure, OK
     res = lib.cb_solve_indent(plan, f, -1e-3, p)
     assert res["status"] == 0 and torch.count_nonzero(p).item() == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_repeat_solves_replay_graphs_bitwise(lib, prec):
+    """The second and third solves on a plan replay the captured iteration
+    graphs (with eager host/device work in between); every replay must
+    reproduce the first solve bit for bit."""
+    N, L = 128, 1.0
+    mat = Material(0.02, 5.0, 0.3, 1.0, 0.3)
+    plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, 0.0, prec)
+    f = torch.tensor(inputs.paraboloid(N, L, 1.0), dtype=torch.float64, device="cuda")
+    ps = []
+    p = torch.zeros_like(f)          # same buffers every time: the cached graphs are replayed
+    for k in range(3):
+        p.zero_()
+        r = lib.cb_solve_force(plan, f, 2e-4, p, tol=1e-10 if prec == "fp64" else 1e-8)
+        ps.append(p.clone())
+        junk = torch.randn(N, N, device="cuda").sum().item()  # eager work between replays
+        assert math.isfinite(junk)
+        assert r["status"] == 0
+    assert torch.equal(ps[0], ps[1]) and torch.equal(ps[0], ps[2])
