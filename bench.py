@@ -76,11 +76,12 @@ def time_apply(cb, plan, p, u, per_graph=50, replays=10):
     return out
 
 
-def solve_set(cb, plans, fs, ps, cases, tol):
-    res = []
-    for plan, f, p, c in zip(plans, fs, ps, cases):
-        res.append(cb.cb_solve_force(plan, f, c.target, p, tol=tol))
-    return res
+def solve_set(cb, plans, fs, ps, cases, tol, sequential=False):
+    """One step: every problem of the set, through the batched driver
+    (concurrent plan streams) or one after another."""
+    if sequential:
+        return [cb.cb_solve_force(pl, f, c.target, p, tol=tol) for pl, f, p, c in zip(plans, fs, ps, cases)]
+    return cb.cb_solve_batch(plans, fs, [c.target for c in cases], [1] * len(cases), ps, tol=tol)
 
 
 def cpu_baseline(case, iters_needed, budget_iters):
@@ -112,6 +113,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--dump", default=None, help="write per-problem results (JSON) here")
+    ap.add_argument("--sequential", action="store_true", help="solve the set one problem at a time")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -142,11 +144,11 @@ def main():
     # ---- FP32 path (timed steps) --------------------------------------------
     tol32, tol64 = 1e-8, 1e-10
     for _ in range(args.warmup):
-        solve_set(cb, plans32, fs32, ps32, cases, tol32)
+        solve_set(cb, plans32, fs32, ps32, cases, tol32, args.sequential)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        res32 = solve_set(cb, plans32, fs32, ps32, cases, tol32)
+        res32 = solve_set(cb, plans32, fs32, ps32, cases, tol32, args.sequential)
     torch.cuda.synchronize()
     t32 = time.perf_counter() - t0
     value = len(cases) * args.steps / t32
@@ -155,7 +157,7 @@ def main():
     solve_set(cb, plans64[:2], fs64[:2], ps64[:2], cases[:2], tol64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res64 = solve_set(cb, plans64, fs64, ps64, cases, tol64)
+    res64 = solve_set(cb, plans64, fs64, ps64, cases, tol64, args.sequential)
     torch.cuda.synchronize()
     t64 = time.perf_counter() - t0
     value64 = len(cases) / t64
@@ -217,7 +219,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"{len(cases)} force-controlled contact solves at N={N} (padded {2*N}^2 FFT), "
-                         "batched recipe seed 1024, FP32 direction convolutions + FP64 state/reductions, residual 1e-8, cold start"),
+                         "batched recipe seed 1024, FP32 direction convolutions + FP64 state/reductions, residual 1e-8, cold start, "
+                         "solved concurrently by cb_solve_batch"),
             "N": N, "solves_per_step": len(cases), "tol": tol32,
         },
         "roofline": roof,

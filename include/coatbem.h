@@ -217,6 +217,23 @@ int cb_sweep(cb_plan plan, const double* f, const double* d_steps_host,
              int nsteps, double* p_state, unsigned char* mask_state,
              const cb_solve_opts* opts, cb_result* per_step_host);
 
+/*
+ * cb_solve_batch -- n independent contact problems solved concurrently.
+ *   Problem i uses plans[i] (grid sizes and materials may differ; distinct
+ *   plans are required), profile f[i] and pressure p_io[i] (device, double,
+ *   plans[i]'s N x N), target[i] and mode[i]: 0 = prescribed approach d
+ *   (cb_solve_indent; adhesive plans use the adhesive procedure), 1 =
+ *   prescribed force F (cb_solve_force).  Every problem runs its own
+ *   graph-captured iteration chunks on its plan's stream; up to `workers`
+ *   problems (<= 0: 8) are in flight at once, largest (N^2) first.
+ *   opts (nullable) applies to every problem.  out_host: n results, each
+ *   with its own status.  Returns CB_OK if every problem succeeded, else
+ *   the first failing status in problem order.  Blocks until all are done.
+ */
+int cb_solve_batch(int n, const cb_plan* plans, const double* const* f,
+                   const double* target, const int* mode, double* const* p_io,
+                   const cb_solve_opts* opts, int workers, cb_result* out_host);
+
 /* Status text; cb_last_error: last error message of this thread. */
 const char* cb_status_string(int status);
 const char* cb_last_error(void);

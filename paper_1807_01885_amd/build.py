@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcoatbem.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["plan.cpp", "fft.hip", "solver.hip"]
+SOURCES = ["plan.cpp", "fft.hip", "solver.hip", "batch.cpp"]
 ARCH = os.environ.get("COATBEM_ARCH", "gfx950")
 
 COMMON = [
@@ -50,7 +50,7 @@ def build(verbose=True):
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-lpthread", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

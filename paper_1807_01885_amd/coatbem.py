@@ -96,6 +96,9 @@ _SIGS = {
                             ctypes.POINTER(cb_result)]),
     "cb_sweep": (_i, [_vp, _vp, ctypes.POINTER(_d), _i, _vp, _vp,
                       ctypes.POINTER(cb_solve_opts), ctypes.POINTER(cb_result)]),
+    "cb_solve_batch": (_i, [_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_d),
+                            ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(cb_solve_opts), _i,
+                            ctypes.POINTER(cb_result)]),
     "cb_status_string": (ctypes.c_char_p, [_i]),
     "cb_last_error": (ctypes.c_char_p, []),
     "cb_version": (_i, []),
@@ -255,6 +258,22 @@ def cb_sweep(plan: Plan, f, d_steps, p_state, mask_state, raise_on_error=True, *
                        _arr(plan, p_state, "p_state", torch.float64),
                        _arr(plan, mask_state, "mask_state", torch.uint8),
                        ctypes.byref(_opts(**opts)), out)
+    if raise_on_error:
+        _check(rc)
+    return [out[i].as_dict() for i in range(n)]
+
+
+def cb_solve_batch(plans, fs, targets, modes, ps, workers=0, raise_on_error=True, **opts):
+    """Solve len(plans) independent problems concurrently.  modes: 0 approach,
+    1 force.  fs, ps: float64 GPU tensors of each plan's N x N."""
+    n = len(plans)
+    hp = (_vp * n)(*[pl.handle for pl in plans])
+    hf = (_vp * n)(*[_arr(pl, f, "f", torch.float64).value for pl, f in zip(plans, fs)])
+    hpp = (_vp * n)(*[_arr(pl, p, "p", torch.float64).value for pl, p in zip(plans, ps)])
+    ht = (_d * n)(*[float(t) for t in targets])
+    hm = (_i * n)(*[int(m) for m in modes])
+    out = (cb_result * max(n, 1))()
+    rc = _lib.cb_solve_batch(n, hp, hf, ht, hm, hpp, ctypes.byref(_opts(**opts)), int(workers), out)
     if raise_on_error:
         _check(rc)
     return [out[i].as_dict() for i in range(n)]

@@ -26,6 +26,7 @@ struct SolverState {
   double resid;      // relative residual of the last check
   double bnorm;      // fixed-set CG: ||b||
   double nact;       // |Ic| of the current iteration
+  double theta;      // activation threshold (residual level) of the iteration
   // skip_u, done, zero are adjacent: a convolution kernel given &skip_u
   // returns if either of the first two is set, given &done if done is set
   int skip_u;        // 1: u was updated linearly, its recomputation is skipped

@@ -140,7 +140,7 @@ k_pk_gap(const double* __restrict__ p, const double* __restrict__ u, const doubl
 }
 
 struct GapTotals {
-  double m, G, resid, n;
+  double m, G, resid, n, scale;
   bool conv, nonfinite;
 };
 
@@ -160,6 +160,7 @@ __device__ __forceinline__ GapTotals gap_totals(const double (&a)[7], const Solv
   const bool viol = gmin_off < -st->tol * scale;
   r.nonfinite = a[6] > 0.0;
   r.conv = (r.resid <= st->tol) && !viol;
+  r.scale = scale;
   return r;
 }
 
@@ -172,6 +173,7 @@ __device__ __forceinline__ bool record_check(const GapTotals& gt, SolverState* s
     st->resid = gt.resid;
     st->nact = gt.n;
     st->gdev = gt.m;
+    st->theta = gt.resid * gt.scale;
     if (st->force) {
       st->d = s + gt.m;
       gbar2[par ^ 1] = s + gt.m;
@@ -293,9 +295,15 @@ k_pk_step(const double* __restrict__ p, const double* __restrict__ g, const TD* 
   write_partials<4>(region(part, R_STEP), v);
 }
 
-// tau; p <- max(p - tau t, 0) on Ic; p = 0 and g < 0 -> p = -tau g
-// (restart); u <- u - tau K t (exact while no cell is clipped or
-// activated); partials: sum p, activations, clipped cells
+// tau; p <- max(p - tau t, 0) on Ic; p = 0 and g < -theta -> p = -tau g
+// (activation, restarts the conjugate directions); u <- u - tau K t (exact
+// while no cell is clipped or activated); partials: sum p, activations,
+// clipped cells.  theta = current relative residual x rms of (d - f) on
+// Ic: a cell whose penetration is below the residual level of the contact
+// set is not activated yet (Polonsky-Keer activate at any g < 0, which
+// makes edge cells cycle between clipping and activation, each cycle a
+// restart); the stopping test still requires g >= -tol x rms everywhere,
+// so the converged solution is the same.
 template <typename TD>
 __global__ void __launch_bounds__(RT)
 k_pk_update(double* __restrict__ p, double* __restrict__ u, const double* __restrict__ g,
@@ -310,6 +318,7 @@ k_pk_update(double* __restrict__ p, double* __restrict__ u, const double* __rest
   const double rt = a[1] - rm * a[3];
   const double tau = rt > 0.0 ? a[0] / rt : 1.0 / st->k00;
   const double m = st->gdev;
+  const double theta = st->theta;
   double v[3] = {0.0, 0.0, 0.0};
   const bool mx[3] = {false, false, false};
 #pragma unroll 4
@@ -320,7 +329,7 @@ k_pk_update(double* __restrict__ p, double* __restrict__ u, const double* __rest
     double pn = pi > 0.0 ? pi : 0.0;
     if (on && pn == 0.0) v[2] += 1.0;
     const double gi = g[i] - m;
-    if (pn == 0.0 && gi < 0.0) {
+    if (pn == 0.0 && gi < -theta) {
       pn = -tau * gi;
       v[1] += 1.0;
     }
