@@ -234,6 +234,72 @@ int cb_solve_batch(int n, const cb_plan* plans, const double* const* f,
                    const double* target, const int* mode, double* const* p_io,
                    const cb_solve_opts* opts, int workers, cb_result* out_host);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start (not part of the paper).  A small U-Net maps the
+ * indenter profile and the problem scalars, on a G x G grid, to an initial
+ * pressure field for the constrained conjugate-gradient solve (the
+ * non-adhesive procedure of Sec. 3); only the solve it seeds decides the
+ * result, so a poor guess costs iterations, never accuracy.
+ *   Network: 16 channels, twelve 3x3 convolutions (two per level on G,
+ *   G/2, G/4, G/8 with 2x2 average pooling, three decoder convolutions
+ *   after nearest 2x upsampling with the encoder output added before the
+ *   ReLU, one head convolution); q = softplus(z), p^ = q / mean(q).
+ *   Training loss per sample: sum (p^ - t)^2 / sum t^2, t the solved
+ *   pressure normalised to unit mean, averaged over the batch.
+ *   Parameters: cb_net_num_params() floats, per layer 9*16*16 weights
+ *   W[tap][co][ci] (tap = 3 (dy+1) + (dx+1)) then 16 biases.
+ *   Activations: NHWC, 16 channels; x inputs are float (n, G, G, 16).
+ * Activations are BF16 and every convolution runs on the BF16 matrix
+ * cores with FP32 accumulation; master weights, gradients and Adam state
+ * are FP32.  All pointers are device pointers unless named _host; a net
+ * is not thread-safe and owns its buffers (sized at creation).
+ * ------------------------------------------------------------------------ */
+typedef struct cb_net_s* cb_net;
+
+/* Number of parameters (floats). */
+int cb_net_num_params(void);
+
+/* Create a net for batches of up to `batch` samples on an H x W grid
+ * (multiples of 32 in [32, 4096]) working on `stream` (NULL: the default
+ * stream).  Parameters start at zero: call cb_net_set_params. */
+int cb_net_create(cb_net* out, int batch, int H, int W, void* stream);
+int cb_net_destroy(cb_net net);
+
+/* Copy the FP32 parameters in (resets the Adam state and step) / out. */
+int cb_net_set_params(cb_net net, const float* params);
+int cb_net_get_params(cb_net net, float* params);
+
+/* Forward pass of n <= batch samples x (n, H, W, 16); z16 (n, H, W, 16)
+ * receives the head output (channel 0 is z), may be NULL.  Asynchronous. */
+int cb_net_forward(cb_net net, int n, const float* x, float* z16);
+
+/* Loss and parameter gradient for inputs x (n, H, W, 16) and targets
+ * t (n, H, W); grad (cb_net_num_params floats) may be NULL, the gradient
+ * is also kept for cb_net_adam_step.  Synchronises the stream. */
+int cb_net_loss_grad(cb_net net, int n, const float* x, const float* t,
+                     double* loss_host, float* grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the kept gradient. */
+int cb_net_adam_step(cb_net net, float lr);
+
+/* Input features of one problem on the net grid (H = W = G): the profile
+ * f (Nf x Nf, Nf a multiple or a divisor of G) as its gap to the lowest
+ * point, cell-averaged or repeated onto G x G and clipped at three
+ * scales (0.005, 0.02, 0.08) L, plus the scalars log10(h/L)/3,
+ * log10(E1/E2)/2, 2 nu1, 2 nu2, log10(F/(E2* L^2))/4 and 1 broadcast.
+ * x: (G, G, 16) float.  Asynchronous. */
+int cb_net_features(cb_net net, const double* f, int Nf, double L, double h,
+                    double E1, double nu1, double E2, double nu2, double F,
+                    float* x);
+
+/* Warm start for a force-controlled solve on `plan`: features, forward
+ * pass, q normalised to unit mean with values below `cut` set to zero,
+ * interpolated (bilinear, cell-centred) or averaged onto the plan's
+ * N x N grid into p_out (double).  Pass p_out to cb_solve_force with
+ * opts.init = 1.  Synchronises the net's stream. */
+int cb_net_warmstart(cb_net net, cb_plan plan, const double* f, double F,
+                     double cut, double* p_out);
+
 /* Status text; cb_last_error: last error message of this thread. */
 const char* cb_status_string(int status);
 const char* cb_last_error(void);

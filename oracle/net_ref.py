@@ -225,3 +225,55 @@ def backward(params, x, t):
     grads[0] = (dW, db)
     flat = np.concatenate([np.concatenate([g[0].ravel(), g[1]]) for g in grads])
     return loss, flat
+
+
+# ---------------------------------------------------------------------------
+# Input features and output interpolation of the warm start
+# ---------------------------------------------------------------------------
+GAP_SCALES = (0.005, 0.02, 0.08)
+
+
+def features(f, G, L, h, E1, nu1, E2, nu2, F):
+    """(G, G, 16) inputs: the gap to the lowest point of f, cell-averaged
+    (N >= G) or repeated (N < G) onto G x G, clipped at three length
+    scales s L; then log10(h/L)/3, log10(E1/E2)/2, 2 nu1, 2 nu2,
+    log10(F/(E2* L^2))/4 and 1; the rest zero."""
+    f = np.asarray(f, dtype=np.float64)
+    N = f.shape[0]
+    g = f - f.min()
+    if N >= G:
+        r = N // G
+        g = g.reshape(G, r, G, r).mean(axis=(1, 3))
+    else:
+        r = G // N
+        g = np.repeat(np.repeat(g, r, axis=0), r, axis=1)
+    x = np.zeros((G, G, C))
+    for c, s in enumerate(GAP_SCALES):
+        x[..., c] = np.minimum(g / (s * L), 1.0)
+    E2s = E2 / (1.0 - nu2 * nu2)
+    scal = [np.log10(max(h, 1e-12) / L) / 3.0, np.log10(E1 / E2) / 2.0, 2.0 * nu1, 2.0 * nu2,
+            np.log10(max(F, 1e-300) / (E2s * L * L)) / 4.0, 1.0]
+    for c, v in enumerate(scal):
+        x[..., 3 + c] = v
+    return x
+
+
+def prolong(z, N, cut=0.0):
+    """Initial pressure on N x N from the head output z (G x G):
+    q = softplus(z) / mean(q), zero below cut, then cell-centred bilinear
+    interpolation with clamped edges (N >= G) or cell averages (N < G)."""
+    z = np.asarray(z, dtype=np.float64)
+    G = z.shape[0]
+    q = softplus(z)
+    q = q / q.mean()
+    q = np.where(q < cut, 0.0, q)
+    if N < G:
+        r = G // N
+        return q.reshape(N, r, N, r).mean(axis=(1, 3))
+    s = (np.arange(N) + 0.5) * G / N - 0.5
+    i0 = np.floor(s).astype(int)
+    w = s - i0
+    lo = np.clip(i0, 0, G - 1)
+    hi = np.clip(i0 + 1, 0, G - 1)
+    rows = (1 - w)[:, None] * q[lo, :] + w[:, None] * q[hi, :]
+    return (1 - w)[None, :] * rows[:, lo] + w[None, :] * rows[:, hi]

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcoatbem.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["plan.cpp", "fft.hip", "solver.hip", "batch.cpp"]
+SOURCES = ["plan.cpp", "fft.hip", "solver.hip", "batch.cpp", "net.hip"]
 ARCH = os.environ.get("COATBEM_ARCH", "gfx950")
 
 COMMON = [

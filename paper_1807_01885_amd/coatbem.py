@@ -99,6 +99,16 @@ _SIGS = {
     "cb_solve_batch": (_i, [_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_d),
                             ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(cb_solve_opts), _i,
                             ctypes.POINTER(cb_result)]),
+    "cb_net_num_params": (_i, []),
+    "cb_net_create": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _vp]),
+    "cb_net_destroy": (_i, [_vp]),
+    "cb_net_set_params": (_i, [_vp, _vp]),
+    "cb_net_get_params": (_i, [_vp, _vp]),
+    "cb_net_forward": (_i, [_vp, _i, _vp, _vp]),
+    "cb_net_loss_grad": (_i, [_vp, _i, _vp, _vp, ctypes.POINTER(_d), _vp]),
+    "cb_net_adam_step": (_i, [_vp, ctypes.c_float]),
+    "cb_net_features": (_i, [_vp, _vp, _i, _d, _d, _d, _d, _d, _d, _d, _vp]),
+    "cb_net_warmstart": (_i, [_vp, _vp, _vp, _d, _d, _vp]),
     "cb_status_string": (ctypes.c_char_p, [_i]),
     "cb_last_error": (ctypes.c_char_p, []),
     "cb_version": (_i, []),
@@ -139,7 +149,8 @@ class Plan:
     device: torch.device
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.cb_plan_destroy(self.handle)
             self.handle = None
 
@@ -277,3 +288,92 @@ def cb_solve_batch(plans, fs, targets, modes, ps, workers=0, raise_on_error=True
     if raise_on_error:
         _check(rc)
     return [out[i].as_dict() for i in range(n)]
+
+
+# ---------------------------------------------------------------------------
+# Learned warm start
+# ---------------------------------------------------------------------------
+def cb_net_num_params():
+    return _lib.cb_net_num_params()
+
+
+@dataclass
+class Net:
+    handle: ctypes.c_void_p
+    batch: int
+    H: int
+    W: int
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.cb_net_destroy(self.handle)
+            self.handle = None
+
+
+def _dev(x, name, dtype, shape):
+    if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if x.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {x.dtype}")
+    if tuple(x.shape) != tuple(shape) or not x.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous tensor of shape {tuple(shape)}")
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def cb_net_create(batch, H, W=None, stream=None):
+    W = H if W is None else W
+    h_ = ctypes.c_void_p()
+    _check(_lib.cb_net_create(ctypes.byref(h_), int(batch), int(H), int(W), _stream_ptr(stream)))
+    return Net(h_, int(batch), int(H), int(W))
+
+
+def cb_net_destroy(net: Net):
+    if net.handle:
+        _check(_lib.cb_net_destroy(net.handle))
+        net.handle = None
+
+
+def cb_net_set_params(net: Net, params):
+    _check(_lib.cb_net_set_params(net.handle, _dev(params, "params", torch.float32, (cb_net_num_params(),))))
+
+
+def cb_net_get_params(net: Net, out=None):
+    if out is None:
+        out = torch.empty(cb_net_num_params(), dtype=torch.float32, device="cuda")
+    _check(_lib.cb_net_get_params(net.handle, _dev(out, "params", torch.float32, (cb_net_num_params(),))))
+    return out
+
+
+def cb_net_forward(net: Net, x, z16=None):
+    n = x.shape[0]
+    xx = _dev(x, "x", torch.float32, (n, net.H, net.W, 16))
+    zz = _dev(z16, "z16", torch.float32, (n, net.H, net.W, 16)) if z16 is not None else None
+    _check(_lib.cb_net_forward(net.handle, int(n), xx, zz))
+    return z16
+
+
+def cb_net_loss_grad(net: Net, x, t, grad=None):
+    n = x.shape[0]
+    loss = ctypes.c_double()
+    gg = _dev(grad, "grad", torch.float32, (cb_net_num_params(),)) if grad is not None else None
+    _check(_lib.cb_net_loss_grad(net.handle, int(n), _dev(x, "x", torch.float32, (n, net.H, net.W, 16)),
+                                 _dev(t, "t", torch.float32, (n, net.H, net.W)), ctypes.byref(loss), gg))
+    return loss.value
+
+
+def cb_net_adam_step(net: Net, lr):
+    _check(_lib.cb_net_adam_step(net.handle, ctypes.c_float(lr)))
+
+
+def cb_net_features(net: Net, f, L, h, E1, nu1, E2, nu2, F, x):
+    Nf = f.shape[0]
+    _check(_lib.cb_net_features(net.handle, _dev(f, "f", torch.float64, (Nf, Nf)), int(Nf), float(L), float(h),
+                                float(E1), float(nu1), float(E2), float(nu2), float(F),
+                                _dev(x, "x", torch.float32, (net.H, net.W, 16))))
+    return x
+
+
+def cb_net_warmstart(net: Net, plan: Plan, f, F, p_out, cut=0.0):
+    _check(_lib.cb_net_warmstart(net.handle, plan.handle, _arr(plan, f, "f", torch.float64), float(F), float(cut),
+                                 _arr(plan, p_out, "p_out", torch.float64)))
+    return p_out

@@ -1,0 +1,228 @@
+"""GPU parity of the warm-start network (BF16 matrix-core convolutions, FP32
+accumulation) against the FP64 reference network: forward output, loss,
+full parameter gradient, the Adam update, the input features and the
+interpolated initial pressure.
+
+Two kinds of check.  (1) Exact: with weights of +-1, integer biases and
+small integer inputs chosen so that every activation of the reference is
+representable in BF16, the GPU forward pass must equal the FP64 reference
+bit for bit; this pins the matrix-core operand layout, the tap order,
+pooling, upsampling and the skip connections without any tolerance.
+(2) Rounded: on random inputs the BF16 activations and gradients (unit
+roundoff 2^-8, twelve layers each way, ReLU decisions that flip near zero)
+give relative errors of a few 1e-2; the bars sit above that and far below
+the O(1) errors of a transposed, shifted or dropped term."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import net_ref as nr
+from paper_1807_01885_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed + 100)
+    p = nr.init_params(seed)
+    for l in range(nr.NLAYER):
+        b = l * nr.LAYER_PARAMS + 9 * nr.C * nr.C
+        p[b:b + nr.C] = 0.1 * rng.standard_normal(nr.C)
+    # a larger head so that z varies over the softplus knee
+    b = (nr.NLAYER - 1) * nr.LAYER_PARAMS
+    p[b:b + 9 * nr.C * nr.C] *= 10.0
+    return p
+
+
+def _problem(n, H, W, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, H, W, nr.C))
+    t = rng.uniform(0.0, 2.0, (n, H, W)) * (rng.uniform(size=(n, H, W)) < 0.4)
+    t /= t.mean(axis=(1, 2), keepdims=True)
+    return x, t
+
+
+def _net(lib, params, n, H, W):
+    net = lib.cb_net_create(n, H, W)
+    lib.cb_net_set_params(net, torch.tensor(params, dtype=torch.float32, device="cuda"))
+    return net
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("n,H,W,seed", [(2, 32, 32, 0), (3, 64, 32, 1), (1, 96, 128, 2)])
+def test_loss_and_gradient(lib, n, H, W, seed):
+    print(f"net grad n={n} {H}x{W} seed={seed}", flush=True)
+    params = _params(seed)
+    x, t = _problem(n, H, W, seed)
+    loss_ref, g_ref = nr.backward(params, x, t)
+    z_ref = nr.forward(params, x)
+    net = _net(lib, params, n, H, W)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    tt = torch.tensor(t, dtype=torch.float32, device="cuda")
+    z16 = torch.empty((n, H, W, 16), dtype=torch.float32, device="cuda")
+    lib.cb_net_forward(net, xt, z16)
+    grad = torch.empty(lib.cb_net_num_params(), dtype=torch.float32, device="cuda")
+    loss = lib.cb_net_loss_grad(net, xt, tt, grad)
+    z = z16[..., 0].double().cpu().numpy()
+    g = grad.double().cpu().numpy()
+    ez = _rel(z, z_ref)
+    el = abs(loss - loss_ref) / loss_ref
+    cos = float(g @ g_ref / np.linalg.norm(g) / np.linalg.norm(g_ref))
+    per = [_rel(g[l * nr.LAYER_PARAMS:(l + 1) * nr.LAYER_PARAMS],
+                g_ref[l * nr.LAYER_PARAMS:(l + 1) * nr.LAYER_PARAMS]) for l in range(nr.NLAYER)]
+    print(f"  z rel {ez:.2e} loss rel {el:.2e} grad cos {cos:.6f} worst layer {max(per):.2e}", flush=True)
+    eg = _rel(g, g_ref)
+    print(f"  grad rel {eg:.2e}", flush=True)
+    assert ez < 3e-2
+    assert el < 1e-2
+    assert cos > 0.999 and eg < 4e-2
+    assert max(per) < 0.2
+    # head-channel bias gradient: channels 1..15 do not reach the loss
+    hb = (nr.NLAYER - 1) * nr.LAYER_PARAMS + 9 * nr.C * nr.C
+    assert np.all(g[hb + 1:hb + nr.C] == 0.0)
+    # bitwise repeatable
+    grad2 = torch.empty_like(grad)
+    loss2 = lib.cb_net_loss_grad(net, xt, tt, grad2)
+    assert loss2 == loss and torch.equal(grad, grad2)
+
+
+def test_batch_smaller_than_capacity(lib):
+    """n < batch uses the first n samples only."""
+    params = _params(4)
+    x, t = _problem(2, 32, 32, 4)
+    net = _net(lib, params, 4, 32, 32)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    tt = torch.tensor(t, dtype=torch.float32, device="cuda")
+    g = torch.empty(lib.cb_net_num_params(), dtype=torch.float32, device="cuda")
+    lib.cb_net_loss_grad(net, xt, tt, g)
+    loss_ref, g_ref = nr.backward(params, x, t)
+    assert _rel(g.double().cpu().numpy(), g_ref) < 4e-2
+
+
+def test_forward_full_grid(lib):
+    """Forward pass on the 256 x 256 grid the warm start uses."""
+    print("net forward 256", flush=True)
+    params = _params(5)
+    x, _ = _problem(1, 256, 256, 5)
+    net = _net(lib, params, 1, 256, 256)
+    z16 = torch.empty((1, 256, 256, 16), dtype=torch.float32, device="cuda")
+    lib.cb_net_forward(net, torch.tensor(x, dtype=torch.float32, device="cuda"), z16)
+    z = z16[..., 0].double().cpu().numpy()
+    e = _rel(z, nr.forward(params, x))
+    print(f"  z rel {e:.2e}", flush=True)
+    assert e < 3e-2
+
+
+def _bf16_exact(a):
+    f = np.asarray(a, dtype=np.float64).astype(np.float32)
+    return np.array_equal(f.astype(np.float64), a) and bool(np.all((f.view(np.uint32) & 0xFFFF) == 0))
+
+
+def _exact_case(n, H, W):
+    """Sparse +-1 weights, integer biases, inputs in {0..3}; the first seed
+    whose reference activations are all BF16-representable."""
+    for seed in range(400):
+        rng = np.random.default_rng(seed)
+        p = np.zeros(nr.NPARAM)
+        for l in range(nr.NLAYER):
+            b = l * nr.LAYER_PARAMS
+            Wt = np.zeros((9, nr.C, nr.C))
+            for co in range(nr.C):
+                for _ in range(int(rng.integers(1, 4))):
+                    Wt[rng.integers(0, 9), co, rng.integers(0, nr.C)] = rng.choice([-1.0, 1.0])
+            p[b:b + 9 * nr.C * nr.C] = Wt.ravel()
+            p[b + 9 * nr.C * nr.C:b + nr.LAYER_PARAMS] = rng.integers(-1, 2, nr.C)
+        x = rng.integers(0, 4, (n, H, W, nr.C)).astype(np.float64)
+        z, a = nr.forward(p, x, keep=True)
+        if all(_bf16_exact(v) for v in a.values()) and np.mean(z != 0) > 0.5 and np.mean(a["s3"] > 0) > 0.1:
+            return p, x, a
+    raise AssertionError("no exactly representable case found")
+
+
+@pytest.mark.parametrize("n,H,W", [(2, 32, 32), (1, 64, 96)])
+def test_forward_exact(lib, n, H, W):
+    print(f"net exact forward n={n} {H}x{W}", flush=True)
+    params, x, a = _exact_case(n, H, W)
+    W11, b11 = nr.unpack(params)[nr.NLAYER - 1]
+    head = nr.conv(a["e0"], W11, b11)
+    net = _net(lib, params, n, H, W)
+    z16 = torch.empty((n, H, W, 16), dtype=torch.float32, device="cuda")
+    lib.cb_net_forward(net, torch.tensor(x, dtype=torch.float32, device="cuda"), z16)
+    got = z16.double().cpu().numpy()
+    assert np.array_equal(got, head), f"{np.count_nonzero(got != head)} of {got.size} differ"
+
+
+def test_adam_step(lib):
+    params = _params(6)
+    x, t = _problem(2, 32, 32, 6)
+    net = _net(lib, params, 2, 32, 32)
+    xt = torch.tensor(x, dtype=torch.float32, device="cuda")
+    tt = torch.tensor(t, dtype=torch.float32, device="cuda")
+    p32 = torch.tensor(params, dtype=torch.float32).numpy().astype(np.float64)
+    m = np.zeros_like(p32)
+    v = np.zeros_like(p32)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    for step in (1, 2):
+        g = torch.empty(lib.cb_net_num_params(), dtype=torch.float32, device="cuda")
+        lib.cb_net_loss_grad(net, xt, tt, g)
+        lib.cb_net_adam_step(net, lr)
+        gg = g.double().cpu().numpy()
+        m = b1 * m + (1 - b1) * gg
+        v = b2 * v + (1 - b2) * gg * gg
+        p32 = p32 - lr * (m / (1 - b1 ** step)) / (np.sqrt(v / (1 - b2 ** step)) + eps)
+        got = lib.cb_net_get_params(net).double().cpu().numpy()
+        np.testing.assert_allclose(got, p32, rtol=1e-5, atol=1e-7)
+
+
+@pytest.mark.parametrize("Nf", [1024, 256, 128])
+def test_features(lib, Nf):
+    L = 1.0
+    f = inputs.cone(Nf, L, 0.11)
+    net = lib.cb_net_create(1, 256, 256)
+    x = torch.empty((256, 256, 16), dtype=torch.float32, device="cuda")
+    args = (L, 0.013, 7.5, 0.31, 1.0, 0.27, 2.2e-3)
+    lib.cb_net_features(net, torch.tensor(f, dtype=torch.float64, device="cuda"), *args, x)
+    ref = nr.features(f, 256, *args)
+    np.testing.assert_allclose(x.double().cpu().numpy(), ref, rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("N", [512, 256, 128])
+def test_warmstart_prolongation(lib, N):
+    """The initial pressure equals the reference network's output carried
+    through the reference interpolation (to the BF16 forward's accuracy)."""
+    print(f"warm start N={N}", flush=True)
+    L = 1.0
+    params = _params(7)
+    f = inputs.paraboloid(N, L, 1.0)
+    plan = lib.cb_plan_create(N, L, 0.02, 10.0, 0.3, 1.0, 0.3, 0.0, "fp32")
+    net = _net(lib, params, 1, 256, 256)
+    F = 1.5e-3
+    p = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    lib.cb_net_warmstart(net, plan, torch.tensor(f, dtype=torch.float64, device="cuda"), F, p, cut=0.0)
+    x = nr.features(f, 256, L, 0.02, 10.0, 0.3, 1.0, 0.3, F)
+    ref = nr.prolong(nr.forward(params, x[None])[0], N)
+    e = _rel(p.cpu().numpy(), ref)
+    print(f"  p0 rel {e:.2e}", flush=True)
+    assert e < 2e-2
+    lib.cb_net_warmstart(net, plan, torch.tensor(f, dtype=torch.float64, device="cuda"), F, p, cut=1e30)
+    assert torch.count_nonzero(p).item() == 0
+
+
+def test_net_errors(lib):
+    with pytest.raises(lib.CoatbemError):
+        lib.cb_net_create(1, 48, 48)
+    with pytest.raises(lib.CoatbemError):
+        lib.cb_net_create(0, 64, 64)
+    net = lib.cb_net_create(2, 32, 32)
+    x = torch.zeros((3, 32, 32, 16), dtype=torch.float32, device="cuda")
+    with pytest.raises(lib.CoatbemError):
+        lib.cb_net_forward(net, x)
+    plan = lib.cb_plan_create(64, 1.0, 0.02, 10.0, 0.3, 1.0, 0.3, 0.0, "fp32")
+    f = torch.zeros((64, 64), dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.CoatbemError):  # grid not square
+        lib.cb_net_warmstart(lib.cb_net_create(1, 64, 32), plan, f, 1.0, torch.empty_like(f))
+    with pytest.raises(lib.CoatbemError):  # negative cut
+        lib.cb_net_warmstart(lib.cb_net_create(1, 32, 32), plan, f, 1.0, torch.empty_like(f), cut=-1.0)

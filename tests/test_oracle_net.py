@@ -76,3 +76,44 @@ def test_normalised_output_has_unit_mean():
     z = np.random.default_rng(5).standard_normal((3, 8, 8))
     ph = nr.normalised_pressure(z)
     np.testing.assert_allclose(ph.mean(axis=(1, 2)), 1.0, rtol=1e-14)
+
+
+def test_features_pins():
+    """Flat profile: zero gap; a step of height 0.05 L: the three channels
+    read 1, 1 and 0.625 outside; the scalars at round values."""
+    G, L = 32, 2.0
+    f = np.zeros((64, 64))
+    f[:, 32:] = 0.05 * L
+    x = nr.features(f, G, L, h=0.002, E1=100.0, nu1=0.25, E2=1.0, nu2=0.0, F=1e-4 * L * L)
+    assert np.all(x[:, :16, :3] == 0.0)
+    np.testing.assert_allclose(x[:, 16:, 0], 1.0)
+    np.testing.assert_allclose(x[:, 16:, 1], 1.0)
+    np.testing.assert_allclose(x[:, 16:, 2], 0.625)
+    np.testing.assert_allclose(x[0, 0, 3:9], [-1.0, 1.0, 0.5, 0.0, -1.0, 1.0])
+    assert np.all(x[..., 9:] == 0.0)
+    # coarser profile than the grid: repeated cells
+    x2 = nr.features(f[::4, ::4], G, L, 0.002, 100.0, 0.25, 1.0, 0.0, 1e-4 * L * L)
+    np.testing.assert_array_equal(x2[..., :3], x[..., :3])
+
+
+def test_prolong_pins():
+    """Constant field -> constant 1; a field linear in the cell-centre
+    coordinate is reproduced exactly away from the clamped edge; the
+    N < G branch averages; cut zeroes small values."""
+    G = 16
+    np.testing.assert_allclose(nr.prolong(np.full((G, G), 0.3), 64), 1.0)
+    # choose z so that softplus(z) is linear in y: z = log(expm1(q))
+    yc = np.arange(G) + 0.5
+    q = np.repeat((1.0 + 0.1 * yc)[:, None], G, axis=1)
+    z = np.log(np.expm1(q))
+    p = nr.prolong(z, 64)
+    yf = (np.arange(64) + 0.5) * G / 64
+    interior = (yf > 0.5) & (yf < G - 0.5)
+    expect = (1.0 + 0.1 * yf) / q.mean()
+    np.testing.assert_allclose(p[interior, 5], expect[interior], rtol=1e-12)
+    pc = nr.prolong(z, 4)
+    np.testing.assert_allclose(pc.mean(), 1.0, rtol=1e-12)
+    np.testing.assert_allclose(pc[:, 0], [(q[4 * i:4 * i + 4, :4] / q.mean()).mean() for i in range(4)],
+                               rtol=1e-12)
+    zz = np.array([[-10.0, 5.0], [5.0, 5.0]]).repeat(8, 0).repeat(8, 1)
+    assert np.all(nr.prolong(zz, 16, cut=0.01)[:8, :8] == 0.0)
