@@ -19,7 +19,8 @@ zero "same" padding, weights W[tap][co][ci] with tap = 3 (dy+1) + (dx+1)):
   e0 = relu(c(up(e1)) + s0)                    HxW     (layer 10)
   z  = c(e0)[..., 0]                           HxW     (layer 11, no relu)
   q  = softplus(z);  p^ = q / mean(q)          per sample
-  loss = mean over the batch of sum (p^ - t)^2 / sum t^2
+  t^ = t / mean(t)                             per sample (t: solved pressure)
+  loss = mean over the batch of sum (p^ - t^)^2 / sum t^^2
 pool = 2x2 average, up = 2x2 nearest copy; c(.) includes the bias.
 """
 from __future__ import annotations
@@ -158,8 +159,9 @@ def normalised_pressure(z):
 
 
 def loss_and_dz(z, t):
-    """loss = mean_n sum (p^ - t)^2 / sum t^2 and dloss/dz."""
+    """loss = mean_n sum (p^ - t^)^2 / sum t^^2 and dloss/dz, t^ = t/mean(t)."""
     n = z.shape[0]
+    t = t / t.mean(axis=(1, 2), keepdims=True)
     q = softplus(z)
     m = q.mean(axis=(1, 2), keepdims=True)
     ph = q / m

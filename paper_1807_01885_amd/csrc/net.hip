@@ -229,60 +229,59 @@ __global__ void k_up_bwd(const float* __restrict__ dY, float* __restrict__ dX, i
 
 __device__ __forceinline__ float softplusf(float z) { return z > 20.f ? z : log1pf(expf(z)); }
 
-// Head: per sample (one block), q = softplus(z), p^ = q/mean q,
-// loss_n = sum (p^ - t)^2 / sum t^2; dz written into channel 0 of dY
-// (other channels zero).  loss partials per sample in lossv.
+// Head: per sample (one block), q = softplus(z), p^ = q / mean q, the
+// target normalised to unit mean t^ = t / mean t, loss_n = sum (p^ - t^)^2
+// / sum t^^2; dz (for the batch mean of loss_n) goes into channel 0 of dY,
+// the other channels are zero.  Fixed-order FP64 block reductions.
+__device__ __forceinline__ void block_sum3(double (*sh)[256], double& a, double& b, double& c) {
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  sh[2][threadIdx.x] = c;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < 3; k++) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  a = sh[0][0];
+  b = sh[1][0];
+  c = sh[2][0];
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(256)
 k_head_loss(const float* __restrict__ Z16, const float* __restrict__ t, float* __restrict__ dY, double* lossv,
             int HW, int n) {
   const int img = blockIdx.x;
   __shared__ double sh[3][256];
-  double sq = 0.0, stt = 0.0;
+  const float* ti = t + (size_t)img * HW;
+  double sq = 0.0, st = 0.0, stt = 0.0;
   for (int e = threadIdx.x; e < HW; e += 256) {
-    const float z = Z16[((size_t)img * HW + e) * C];
-    sq += softplusf(z);
-    const double tv = t[(size_t)img * HW + e];
+    sq += softplusf(Z16[((size_t)img * HW + e) * C]);
+    const double tv = ti[e];
+    st += tv;
     stt += tv * tv;
   }
-  sh[0][threadIdx.x] = sq;
-  sh[1][threadIdx.x] = stt;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
-      sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  const double m = sh[0][0] / HW, tt = sh[1][0];
-  __syncthreads();
-  double srr = 0.0, sdq = 0.0;
+  block_sum3(sh, sq, st, stt);
+  const double m = sq / HW, ts = HW / st, tt = stt * ts * ts;
+  double srr = 0.0, sdq = 0.0, unused = 0.0;
   for (int e = threadIdx.x; e < HW; e += 256) {
-    const float z = Z16[((size_t)img * HW + e) * C];
-    const double q = softplusf(z);
-    const double r = q / m - t[(size_t)img * HW + e];
+    const double q = softplusf(Z16[((size_t)img * HW + e) * C]);
+    const double r = q / m - ti[e] * ts;
     srr += r * r;
     sdq += (2.0 * r / tt / n) * q;
   }
-  sh[0][threadIdx.x] = srr;
-  sh[1][threadIdx.x] = sdq;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
-      sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  const double sdqt = sh[1][0];
-  if (threadIdx.x == 0) lossv[img] = sh[0][0] / tt;
+  block_sum3(sh, srr, sdq, unused);
+  if (threadIdx.x == 0) lossv[img] = srr / tt;
   for (int e = threadIdx.x; e < HW; e += 256) {
     const size_t o = ((size_t)img * HW + e) * C;
     const float z = Z16[o];
     const double q = softplusf(z);
-    const double r = q / m - t[(size_t)img * HW + e];
+    const double r = q / m - ti[e] * ts;
     const double dph = 2.0 * r / tt / n;
-    const double dq = dph / m - sdqt / (m * m * HW);
+    const double dq = dph / m - sdq / (m * m * HW);
     dY[o] = (float)(dq / (1.0 + exp(-(double)z)));
 #pragma unroll
     for (int c = 1; c < C; c++) dY[o + c] = 0.f;

@@ -117,3 +117,17 @@ def test_prolong_pins():
                                rtol=1e-12)
     zz = np.array([[-10.0, 5.0], [5.0, 5.0]]).repeat(8, 0).repeat(8, 1)
     assert np.all(nr.prolong(zz, 16, cut=0.01)[:8, :8] == 0.0)
+
+
+def test_loss_zero_at_match_and_scale_invariant():
+    """softplus(z) proportional to t gives zero loss and zero gradient;
+    scaling t by a constant leaves loss and gradient unchanged."""
+    rng = np.random.default_rng(5)
+    t = rng.uniform(0.1, 3.0, (2, 8, 8))
+    z = np.log(np.expm1(0.7 * t))
+    loss, dz = nr.loss_and_dz(z, t)
+    assert loss < 1e-28 and np.abs(dz).max() < 1e-14
+    z2 = rng.standard_normal((2, 8, 8))
+    l1, d1 = nr.loss_and_dz(z2, t)
+    l2, d2 = nr.loss_and_dz(z2, 123.0 * t)
+    assert abs(l1 - l2) < 1e-14 * l1 and np.allclose(d1, d2, rtol=1e-12, atol=0)
