@@ -70,10 +70,20 @@ typedef struct {
                       over the Brillouin zone [-pi/Delta, pi/Delta]^2;
                       CB_DC_ZERO: no DC component (Eq. 11 taken literally) */
   void* stream;    /* hipStream_t to enqueue on; NULL = the null stream */
-  int autotune;    /* 1: time the available FFT launch shapes once for this
-                      (N, precision) and keep the fastest (cached in
-                      tune_cache if set); 0 (default): built-in choice */
-  const char* tune_cache; /* path of the autotune cache file, or NULL */
+  int autotune;    /* 1: time every FFT launch-shape variant (a graph of
+                      ten convolutions each) at plan creation and keep the
+                      fastest for this (device, N, precision); 0 (default):
+                      variant 1, unless tune_cache holds an entry */
+  const char* tune_cache; /* text file of tuned choices, one line per
+                      (device architecture, N, precision): read first (an
+                      entry skips the timing), appended after tuning;
+                      NULL: no file */
+  int fft_variant; /* 0 (default): automatic as above; 1..6 force a
+                      launch shape (elements per thread in the row / column
+                      kernels, row-tile height): 1 (16, 16, 1x),
+                      2 (16, 8, 1x), 3 (8, 16, 1x), 4 (16, 16, 2x),
+                      5 (16, 32, 1x), 6 (8, 8, 2x).  All give the same
+                      transform up to rounding order. */
 } cb_plan_opts;
 
 /* Solve options; a NULL pointer selects every default. */
@@ -122,6 +132,8 @@ typedef struct {
   int validity_warning; /* 1 when dgamma > 0 and h < 5 Delta: Eq. 12 assumes
                         Delta << h (Sec. 2 after Eq. 12) */
   size_t workspace_bytes;
+  int fft_variant;   /* FFT launch-shape variant in use (1..6) */
+  double tune_us;    /* its timed convolution, microseconds (0: not timed) */
 } cb_plan_info;
 
 /*

@@ -278,4 +278,4 @@ def prolong(z, N, cut=0.0):
     lo = np.clip(i0, 0, G - 1)
     hi = np.clip(i0 + 1, 0, G - 1)
     rows = (1 - w)[:, None] * q[lo, :] + w[:, None] * q[hi, :]
-    return (1 - w)[None, :] * rows[:, lo] + w[None, :] * rows[:, hi]
+    return np.ascontiguousarray((1 - w)[None, :] * rows[:, lo] + w[None, :] * rows[:, hi])

@@ -17,7 +17,12 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcoatbem.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["plan.cpp", "fft.hip", "solver.hip", "batch.cpp", "net.hip"]
+# (source, object name, extra flags): the FFT file is compiled once per
+# launch-shape variant
+FFT_VARIANTS = 6
+SOURCES = ([("plan.cpp", "plan", []), ("fft_dispatch.cpp", "fft_dispatch", []),
+            ("solver.hip", "solver", []), ("batch.cpp", "batch", []), ("net.hip", "net", [])]
+           + [("fft.hip", f"fft_v{k}", [f"-DCB_FFT_VARIANT={k}"]) for k in range(FFT_VARIANTS)])
 ARCH = os.environ.get("COATBEM_ARCH", "gfx950")
 
 COMMON = [
@@ -33,9 +38,10 @@ def hipcc():
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def _compile(src):
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *COMMON]
+def _compile(entry):
+    src, name, extra = entry
+    obj = os.path.join(BUILD_DIR, name + ".o")
+    cmd = [hipcc(), *COMMON, *extra]
     if src.endswith(".cpp"):
         cmd += ["-x", "hip"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
@@ -47,7 +53,8 @@ def _compile(src):
 
 def build(verbose=True):
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    workers = min(len(SOURCES), max(1, os.cpu_count() or 1))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-lpthread", "-o", tmp]

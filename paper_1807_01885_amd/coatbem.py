@@ -40,7 +40,7 @@ CB_DC_ZERO = 1
 class cb_plan_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("dc_mode", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int),
-                ("tune_cache", ctypes.c_char_p)]
+                ("tune_cache", ctypes.c_char_p), ("fft_variant", ctypes.c_int)]
 
 
 class cb_solve_opts(ctypes.Structure):
@@ -71,7 +71,8 @@ class cb_plan_info(ctypes.Structure):
                 ("E1s", ctypes.c_double), ("E2s", ctypes.c_double),
                 ("sigma_c", ctypes.c_double), ("k00", ctypes.c_double),
                 ("dc", ctypes.c_double), ("validity_warning", ctypes.c_int),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("fft_variant", ctypes.c_int),
+                ("tune_us", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -162,10 +163,11 @@ def _stream_ptr(stream):
 
 
 def cb_plan_create(N, L, h, E1, nu1, E2, nu2, dgamma=0.0, precision="fp64",
-                   dc_mode="bz", stream=None, autotune=0):
+                   dc_mode="bz", stream=None, autotune=0, tune_cache=None, fft_variant=0):
     opts = cb_plan_opts(CB_FP64 if precision == "fp64" else CB_FP32,
                         CB_DC_BZ if dc_mode == "bz" else CB_DC_ZERO,
-                        _stream_ptr(stream), int(autotune), None)
+                        _stream_ptr(stream), int(autotune),
+                        None if tune_cache is None else os.fsencode(tune_cache), int(fft_variant))
     h_ = ctypes.c_void_p()
     _check(_lib.cb_plan_create(ctypes.byref(h_), int(N), float(L), float(h),
                                float(E1), float(nu1), float(E2), float(nu2),

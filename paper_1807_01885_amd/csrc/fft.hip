@@ -15,10 +15,26 @@
 // Intermediate layout ("row tiles"): S[rb][kx][rr], rb = row / RB,
 // rr = row % RB, kx in [0, N], complex.  K1/K3 read and write whole tiles
 // (contiguous), K2 reads RB-element segments of a column.
+//
+// This file is compiled once per launch-shape variant (CB_FFT_VARIANT =
+// 0 .. CB_FFT_VARIANTS-1): elements per thread in K1/K3 and in K2 and the
+// row-tile height differ, each variant lives in its own namespace, and the
+// plan picks one (built-in default or the autotuner's choice).
 #include "fft_core.h"
 #include "internal.h"
 
+#ifndef CB_FFT_VARIANT
+#define CB_FFT_VARIANT 0
+#endif
+#define CB_CAT2(a, b) a##b
+#define CB_CAT(a, b) CB_CAT2(a, b)
+
 namespace cb {
+namespace CB_CAT(fftv, CB_FFT_VARIANT) {
+
+constexpr int VE1 = kFftVariants[CB_FFT_VARIANT].e_rows;
+constexpr int VE2 = kFftVariants[CB_FFT_VARIANT].e_cols;
+constexpr int VRBM = kFftVariants[CB_FFT_VARIANT].tile_mul;
 
 constexpr int PS = 4;  // LDS padding shift
 
@@ -302,14 +318,14 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
 // ---------------------------------------------------------------------------
 template <int LOG2N> struct Shape {
   static constexpr int N = 1 << LOG2N, M = 2 * N;
-  static constexpr int E1 = N < 16 ? N : 16;
+  static constexpr int E1 = N < VE1 ? N : VE1;
   static constexpr int NT1 = N / E1;
-  static constexpr int E2 = 16;
+  static constexpr int E2 = VE2;
   static constexpr int NT2 = M / E2;
   static constexpr int CB = NT2 >= 64 ? 1 : 64 / NT2;
 };
 
-template <typename T> constexpr int row_tile() { return sizeof(T) == 4 ? 4 : 2; }
+template <typename T> constexpr int row_tile() { return (sizeof(T) == 4 ? 4 : 2) * VRBM; }
 
 template <typename T, int LOG2N>
 static size_t lds_rows(int G) {
@@ -324,13 +340,32 @@ static size_t lds_cols(int CB) {
   return sizeof(cx<T>) * (TW::NLO + TW::NHI + (size_t)CB * padded<PS>(M));
 }
 
+// row tiles per block of K1/K3: at least one wave of threads
+template <typename T, int LOG2N>
+constexpr int tiles_per_block() {
+  using SH = Shape<LOG2N>;
+  constexpr int RB = row_tile<T>();
+  constexpr int G0 = (SH::NT1 * RB >= 64) ? 1 : 64 / (SH::NT1 * RB);
+  return G0 > SH::N / RB ? SH::N / RB : G0;
+}
+
+// LDS bytes per block of the larger kernel; 0 if a block would exceed the
+// 1024-thread limit (the shape is then not launchable at this size)
+template <typename T, int LOG2N>
+static size_t lds_need() {
+  using SH = Shape<LOG2N>;
+  constexpr int G = tiles_per_block<T, LOG2N>();
+  if (G * row_tile<T>() * SH::NT1 > 1024 || SH::CB * SH::NT2 > 1024) return 0;
+  const size_t a = lds_rows<T, LOG2N>(G), b = lds_cols<T, LOG2N>(SH::CB);
+  return a > b ? a : b;
+}
+
 template <typename T, int LOG2N>
 static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T>* S, const T* Tq, const cx<T>* tw,
                              hipStream_t st) {
   using SH = Shape<LOG2N>;
   constexpr int N = SH::N, RB = row_tile<T>();
-  constexpr int G0 = (SH::NT1 * RB >= 64) ? 1 : 64 / (SH::NT1 * RB);
-  constexpr int G = G0 > N / RB ? N / RB : G0;
+  constexpr int G = tiles_per_block<T, LOG2N>();
   constexpr int NC = N + 1;
   const size_t lr = lds_rows<T, LOG2N>(G), lc = lds_cols<T, LOG2N>(SH::CB);
   auto k1 = k_rows_fwd<T, LOG2N, RB, SH::NT1, G>;
@@ -367,9 +402,11 @@ static hipError_t apply_dispatch(int stages, const int* skip, int log2n, const T
   }
 }
 
-hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages,
-                        const int* skip, const void* table, int prec) {
-  if (prec < 0) prec = P->precision;
+}  // namespace fftv<variant>
+
+hipError_t CB_CAT(launch_apply_v, CB_FFT_VARIANT)(const cb_plan_s* P, const void* p, void* u, hipStream_t st,
+                                                 int stages, const int* skip, const void* table, int prec) {
+  using namespace CB_CAT(fftv, CB_FFT_VARIANT);
   if (prec == 0) {
     if (!table) table = P->precision == 0 ? P->d_table : P->d_table64;
     return apply_dispatch<double>(stages, skip, P->log2n, (const double*)p, (double*)u, (cx<double>*)P->d_S,
@@ -380,11 +417,10 @@ hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t 
                                (const float*)table, nullptr, st);
 }
 
-size_t intermediate_elems(int N) { return (size_t)N * (N + 1); }
-
 // Set the dynamic-LDS attributes of every convolution kernel of this size
 // (both precisions) up front, so that no attribute call happens while a
 // stream is being captured.
+namespace CB_CAT(fftv, CB_FFT_VARIANT) {
 template <int LOG2N>
 static void prepare_n() {
   float* nf = nullptr;
@@ -392,7 +428,22 @@ static void prepare_n() {
   (void)apply_impl<float, LOG2N>(0, nullptr, nf, nf, nullptr, nullptr, nullptr, nullptr);
   (void)apply_impl<double, LOG2N>(0, nullptr, nd, nd, nullptr, nullptr, nullptr, nullptr);
 }
-void prepare_apply(int log2n) {
+}  // namespace fftv<variant>
+
+size_t CB_CAT(lds_bytes_v, CB_FFT_VARIANT)(int log2n, int prec) {
+  using namespace CB_CAT(fftv, CB_FFT_VARIANT);
+  switch (log2n) {
+#define CB_LDS_CASE(k) \
+  case k: return prec == 0 ? lds_need<double, k>() : lds_need<float, k>();
+    CB_LDS_CASE(4) CB_LDS_CASE(5) CB_LDS_CASE(6) CB_LDS_CASE(7)
+    CB_LDS_CASE(8) CB_LDS_CASE(9) CB_LDS_CASE(10) CB_LDS_CASE(11)
+#undef CB_LDS_CASE
+    default: return 0;
+  }
+}
+
+void CB_CAT(prepare_apply_v, CB_FFT_VARIANT)(int log2n) {
+  using namespace CB_CAT(fftv, CB_FFT_VARIANT);
   switch (log2n) {
     case 4: prepare_n<4>(); break;
     case 5: prepare_n<5>(); break;

@@ -27,6 +27,9 @@ struct SolverState {
   double bnorm;      // fixed-set CG: ||b||
   double nact;       // |Ic| of the current iteration
   double theta;      // activation threshold (residual level) of the iteration
+  double gnorm2;     // preconditioned method: sum over Ic of (g - mean)^2
+  double act_scale;  // step scale for activated cells: 1, or for the
+                     // preconditioned method (g . M^-1 g) / (g . g)
   // skip_u, done, zero are adjacent: a convolution kernel given &skip_u
   // returns if either of the first two is set, given &done if done is set
   int skip_u;        // 1: u was updated linearly, its recomputation is skipped
@@ -56,6 +59,18 @@ struct GraphEntry {
   unsigned long long used = 0;
 };
 constexpr int GRAPH_CACHE = 6;
+
+namespace cb {
+// FFT launch-shape variants: complex elements per thread in the row
+// kernels (K1/K3) and in the column kernel (K2), and the multiplier of the
+// row-tile height (4 rows FP32, 2 rows FP64).  Variant 0 is the default.
+struct FftVariant {
+  int e_rows, e_cols, tile_mul;
+};
+constexpr int CB_FFT_VARIANTS = 6;
+constexpr FftVariant kFftVariants[CB_FFT_VARIANTS] = {
+    {16, 16, 1}, {16, 8, 1}, {8, 16, 1}, {16, 16, 2}, {16, 32, 1}, {8, 8, 2}};
+}  // namespace cb
 
 struct cb_plan_s {
   int N = 0, M = 0, log2n = 0, precision = 0, dc_mode = 0;
@@ -90,15 +105,35 @@ struct cb_plan_s {
   GraphEntry graphs[GRAPH_CACHE];
   unsigned long long graph_clock = 0;
   int use_graphs = 1;
+  int variant[2] = {0, 0};  // FFT launch-shape variant of the FP64 / FP32 convolutions
+  double tune_us = 0.0;     // autotuned time of one convolution (0: not tuned)
 };
 
 namespace cb {
 // prec: -1 the plan's precision, 0 FP64, 1 FP32 (the table defaults to the
-// transfer table of that precision)
+// transfer table of that precision).  Runs the plan's FFT variant for prec.
 hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages = 7,
                         const int* skip = nullptr, const void* table = nullptr, int prec = -1);
-size_t intermediate_elems(int N);
+inline size_t intermediate_elems(int N) { return (size_t)N * (N + 1); }
+// dynamic-LDS attributes of every variant's kernels for this size
 void prepare_apply(int log2n);
+// one variant's entry points (fft.hip compiled once per variant)
+#define CB_DECLARE_FFT_VARIANT(k)                                                                         \
+  hipError_t launch_apply_v##k(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages,   \
+                               const int* skip, const void* table, int prec);                           \
+  void prepare_apply_v##k(int log2n);                                                                    \
+  size_t lds_bytes_v##k(int log2n, int prec);
+CB_DECLARE_FFT_VARIANT(0)
+CB_DECLARE_FFT_VARIANT(1)
+CB_DECLARE_FFT_VARIANT(2)
+CB_DECLARE_FFT_VARIANT(3)
+CB_DECLARE_FFT_VARIANT(4)
+CB_DECLARE_FFT_VARIANT(5)
+#undef CB_DECLARE_FFT_VARIANT
+// 1 if variant v fits the device's LDS per block for this size and precision
+bool fft_variant_fits(int v, int log2n, int prec, int device);
+// time every fitting variant for the plan's precision, or take it from the cache
+int autotune_fft(cb_plan_s* P, int autotune, const char* cache);
 }  // namespace cb
 
 // error reporting (thread-local message)

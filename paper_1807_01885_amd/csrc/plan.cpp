@@ -225,6 +225,9 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
     return cb_fail(CB_E_INVALID, "precision must be CB_FP64 or CB_FP32");
   if (opts.dc_mode != CB_DC_BZ && opts.dc_mode != CB_DC_ZERO)
     return cb_fail(CB_E_INVALID, "dc_mode must be CB_DC_BZ or CB_DC_ZERO");
+  if (opts.autotune != 0 && opts.autotune != 1) return cb_fail(CB_E_INVALID, "autotune must be 0 or 1");
+  if (opts.fft_variant < 0 || opts.fft_variant > cb::CB_FFT_VARIANTS)
+    return cb_fail(CB_E_INVALID, "fft_variant must be 0 (automatic) or 1.." + std::to_string(cb::CB_FFT_VARIANTS));
 
   auto* P = new (std::nothrow) cb_plan_s();
   if (!P) return cb_fail(CB_E_NOMEM, "host allocation failed");
@@ -337,6 +340,20 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
         hipEventCreateWithFlags(&P->ev_state[1], hipEventDisableTiming) != hipSuccess)
       rc = cb_fail(CB_E_DEVICE, "stream/event creation failed");
   }
+  if (rc == CB_OK) {
+    if (opts.fft_variant > 0) {
+      const int v = opts.fft_variant - 1;
+      // the FP64 refresh convolutions of FP32 plans use the same shape
+      // when it fits, else the default
+      if (!cb::fft_variant_fits(v, P->log2n, P->precision == CB_FP64 ? 0 : 1, P->device))
+        rc = cb_fail(CB_E_UNSUPPORTED, "fft_variant " + std::to_string(opts.fft_variant) +
+                                           " needs more LDS per block than the device has at this N");
+      P->variant[P->precision == CB_FP64 ? 0 : 1] = v;
+      if (P->precision == CB_FP32 && cb::fft_variant_fits(v, P->log2n, 0, P->device)) P->variant[0] = v;
+    } else {
+      rc = cb::autotune_fft(P, opts.autotune, opts.tune_cache);
+    }
+  }
   if (rc != CB_OK) {
     free_plan_memory(P);
     delete P;
@@ -378,6 +395,8 @@ extern "C" int cb_plan_get_info(cb_plan P, cb_plan_info* info) {
   I.dc = P->dc;
   I.validity_warning = P->validity_warning;
   I.workspace_bytes = P->workspace_bytes;
+  I.fft_variant = P->variant[P->precision == CB_FP64 ? 0 : 1] + 1;
+  I.tune_us = P->tune_us;
   *info = I;
   return CB_OK;
 }

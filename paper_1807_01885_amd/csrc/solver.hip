@@ -224,6 +224,7 @@ k_pk_gmask(const double* __restrict__ p, const double* __restrict__ g, TD* __res
   const double s = st->force ? gbar2[par] : st->d_in;
   const GapTotals gt = gap_totals(a, st);
   if (record_check(gt, st, gbar2, s, par)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->gnorm2 = gt.G;
   const double m = gt.m;
 #pragma unroll 4
   GRID_LOOP(i, n) gm[i] = p[i] > 0.0 ? (TD)(g[i] - m) : TD(0);
@@ -254,7 +255,7 @@ k_pk_zdot(const double* __restrict__ p, const double* __restrict__ g, const TD* 
 template <typename TD>
 __global__ void __launch_bounds__(RT)
 k_pk_dir_pc(const double* __restrict__ p, const TD* __restrict__ zp, TD* __restrict__ t,
-            const SolverState* __restrict__ st, double* part, int nb, int n, int par) {
+            SolverState* __restrict__ st, double* part, int nb, int n, int par) {
   if (st->done) return;
   const bool mx2[2] = {false, false}, mx3[3] = {false, false, false};
   double a[2], u3[3];
@@ -262,6 +263,13 @@ k_pk_dir_pc(const double* __restrict__ p, const TD* __restrict__ zp, TD* __restr
   fold<3>(region(part, R_UPD), nb, mx3, u3);
   const double nn = st->nact;
   const double zbar = (st->force && nn > 0.0) ? a[0] / nn : 0.0;
+  // A cell that becomes active takes the step -tau * act_scale * g: the
+  // direction t = M^-1 g is on a different scale from g (M^-1 damps the
+  // long waves by up to E2*/E1*), so -tau * g alone would overshoot there.
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const double G = st->gnorm2;
+    st->act_scale = (G > 0.0 && a[1] > 0.0) ? a[1] / G : 1.0;
+  }
   double beta = 0.0;
   if (u3[1] == 0.0) {
     double b[2];
@@ -330,7 +338,7 @@ k_pk_update(double* __restrict__ p, double* __restrict__ u, const double* __rest
     if (on && pn == 0.0) v[2] += 1.0;
     const double gi = g[i] - m;
     if (pn == 0.0 && gi < -theta) {
-      pn = -tau * gi;
+      pn = -tau * st->act_scale * gi;
       v[1] += 1.0;
     }
     p[i] = pn;
@@ -854,6 +862,7 @@ static SolverState base_state(const cb_plan_s* P, double tol, double d_in, bool 
   s.d_in = d_in;
   s.force = force ? 1 : 0;
   s.d = d_in;
+  s.act_scale = 1.0;
   return s;
 }
 

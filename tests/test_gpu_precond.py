@@ -44,3 +44,35 @@ def test_preconditioned_force_solve(lib, prec, shape, mat, F):
         assert abs(res["F"] - F) / F < (1e-12 if prec == "fp64" else 1e-6)
     assert out[1][0] < out[0][0]          # fewer iterations with the preconditioner
     assert out[-1][0] == out[1][0]        # automatic choice turns it on here
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("pc", [1, 0])
+def test_initial_guess_with_too_small_contact(lib, prec, pc):
+    """An initial guess whose support is smaller than the contact (the
+    oracle's pressure with its low-pressure rim removed) makes the solver
+    grow the contact set; activated cells take a step scaled to the
+    search direction, so the preconditioned solve converges to the same
+    pressure as the plain one and the oracle."""
+    print(f"grow contact pc={pc} {prec}", flush=True)
+    N, L = 128, 1.0
+    mat = Material(0.0023, 42.8, 0.31, 1.0, 0.30)
+    f = inputs.cone(N, L, 0.116)
+    F = 5.6e-3
+    op = Operator(N, L, mat)
+    ref = solve_pk(op, f, F, mode="force", tol=1e-10)
+    # keep the inner 70% of the contact radius, with a 20% ripple
+    a = np.sqrt((ref.p > 0).sum() / np.pi) * (L / N)
+    yy, xx = (np.indices((N, N)) - N // 2) * (L / N)
+    p0 = np.where(np.hypot(xx, yy) < 0.7 * a, ref.p, 0.0)
+    p0 = np.ascontiguousarray(p0 * (1.0 + 0.2 * np.cos(np.arange(N) * 0.3))[None, :])
+    assert (p0 > 0).sum() < 0.6 * (ref.p > 0).sum()
+    plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, 0.0, prec)
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
+    p = torch.tensor(p0, dtype=torch.float64, device="cuda")
+    tol = 1e-10 if prec == "fp64" else 1e-8
+    res = lib.cb_solve_force(plan, ft, F, p, tol=tol, precond=pc, init=1, max_iter=4000)
+    e_p = np.linalg.norm(p.cpu().numpy() - ref.p) / np.linalg.norm(ref.p)
+    print(f"  iters {res['iters']} (oracle cold {ref.iters}) e_p {e_p:.2e}", flush=True)
+    assert res["status"] == 0
+    assert e_p < (1e-7 if prec == "fp64" else 2e-4)
