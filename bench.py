@@ -3,25 +3,31 @@
 Workload (one "step"): the N = 1024 solve set -- 32 force-controlled
 contact problems drawn by the batched recipe (paraboloid / cone / flat
 punch / elliptic punch indenters, coating h/L log-uniform in [1e-3, 0.3],
-E1/E2 log-uniform in [0.01, 100], nu in [0.2, 0.45]), seed 1024, solved
-to relative residual 1e-6 by the FP32 path (FP32 fields and FFT
-convolution, FP64 reductions).  The same set solved by the plain FP64
-path (cold start, residual 1e-10) is timed alongside.
+E1/E2 log-uniform in [0.01, 100], nu in [0.2, 0.45]), seed 1024, each
+solved to relative residual 1e-8.  `value` is the full method: FP32
+direction convolutions with FP64 state and reductions, the learned warm
+start (network forward pass inside the step), all 32 solves concurrent
+through cb_solve_batch, FFT launch shapes from the shipped tune cache.
 
-Also measured live: cb_apply_K and its three kernels at N = 1024 (FP32
-and FP64) with HIP events on the plan stream; the roofline object uses
-the dominant kernel's algorithmic bytes per launch over its mean
-duration.  The CPU baseline times the FP64 oracle on the host for a
-bounded number of iterations of the first problem and scales by the
-iteration count that problem needs.
+Also timed on the same set and tolerance: the FP32 path from a cold start,
+and the plain FP64 solver (cold start, one solve after another).  Every
+path's pressures are checked against an FP64 solve to residual 1e-10.
+
+Measured live: cb_apply_K and its three kernels at N = 1024 (FP32 and
+FP64), graph-replayed with HIP events on the stream they run on; the
+roofline object uses the dominant kernel's algorithmic bytes per launch
+over its mean duration, and its HBM traffic from the committed
+FETCH_SIZE / WRITE_SIZE counter runs while the kernel source is unchanged.
+The CPU baseline times the FP64 oracle on the host for a bounded number of
+iterations of the first problem and scales by the iterations it needs.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -32,6 +38,25 @@ if ROOT not in sys.path:
 
 METRIC = "contact solves/sec at N=1024² (learned+FP32 vs plain FP64); cb_apply_K HBM GB/s"
 PEAK_HBM_GBPS = 8000.0
+TOL = 1e-8          # every timed path
+TOL_REF = 1e-10     # FP64 reference for the accuracy checks
+
+# HBM traffic of the column kernel (K2) at N = 1024, FP32, tuned launch
+# shape, from two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled
+# by what the same counters read for a 64 MiB device copy (FETCH x 2.0,
+# WRITE x 1.0); the summary and commands are in profiles/.  Valid while the
+# FFT sources hash to `src` and the plan uses `variant`.
+K2_TRAFFIC = {"kernel": "k2_cols", "N": 1024, "precision": "fp32", "variant": 3,
+              "src": "798b3a3f27ebb940:8f9410e6f82dcc1c",
+              "fetch_bytes": 6353.88 * 1024 * 2.0, "write_bytes": 8200.0 * 1024}
+
+
+def fft_src_hash():
+    out = []
+    for f in ("fft.hip", "fft_core.h"):
+        with open(os.path.join(ROOT, "paper_1807_01885_amd", "csrc", f), "rb") as fh:
+            out.append(hashlib.sha256(fh.read()).hexdigest()[:16])
+    return ":".join(out)
 
 
 def alg_bytes(N, s):
@@ -76,17 +101,8 @@ def time_apply(cb, plan, p, u, per_graph=50, replays=10):
     return out
 
 
-def solve_set(cb, plans, fs, ps, cases, tol, sequential=False):
-    """One step: every problem of the set, through the batched driver
-    (concurrent plan streams) or one after another."""
-    if sequential:
-        return [cb.cb_solve_force(pl, f, c.target, p, tol=tol) for pl, f, p, c in zip(plans, fs, ps, cases)]
-    return cb.cb_solve_batch(plans, fs, [c.target for c in cases], [1] * len(cases), ps, tol=tol)
-
-
 def cpu_baseline(case, iters_needed, budget_iters):
     """Oracle FP64 solve of `case` timed for budget_iters iterations, scaled."""
-    import numpy as np  # noqa: F401
     from oracle import operator as oop
     from oracle.solvers import solve_pk
     from oracle.transfer import Material
@@ -94,14 +110,15 @@ def cpu_baseline(case, iters_needed, budget_iters):
     op = oop.Operator(case.N, case.L, Material(case.h, case.E1, case.nu1, case.E2, case.nu2),
                       workers=workers)
     t0 = time.perf_counter()
-    r = solve_pk(op, case.f, case.target, mode="force", tol=1e-10, max_iter=budget_iters)
+    r = solve_pk(op, case.f, case.target, mode="force", tol=TOL, max_iter=budget_iters)
     dt = time.perf_counter() - t0
     per_iter = dt / max(r.iters, 1)
     est = per_iter * iters_needed
     return {"value": 1.0 / est, "unit": "solves/s", "cores": workers, "kind": "oracle",
             "sample": (f"FP64 oracle (numpy/scipy.fft, {workers} workers), first problem of the N=1024 "
                        f"set, {r.iters} iterations in {dt:.1f} s = {per_iter*1e3:.1f} ms/iteration, "
-                       f"scaled by the {iters_needed} iterations the FP64 solve of that problem needs")}
+                       f"scaled by the {iters_needed} iterations the plain FP64 solve of that problem "
+                       f"needs at residual {TOL:g}")}
 
 
 def main():
@@ -113,7 +130,6 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--dump", default=None, help="write per-problem results (JSON) here")
-    ap.add_argument("--sequential", action="store_true", help="solve the set one problem at a time")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -125,60 +141,82 @@ def main():
 
     from paper_1807_01885_amd import coatbem as cb
     from paper_1807_01885_amd import inputs
+    from paper_1807_01885_amd.tune import TUNE_CACHE
+    from paper_1807_01885_amd.warmstart import WarmStart
 
     torch.cuda.set_device(0)
     cases = inputs.headline_set(n=args.n_solves)
     N = cases[0].N
+    n = len(cases)
 
     def make(prec):
-        dt = torch.float32 if prec == "fp32" else torch.float64
-        plans = [cb.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, prec) for c in cases]
+        plans = [cb.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, prec, tune_cache=TUNE_CACHE)
+                 for c in cases]
         fs = [torch.tensor(c.f, dtype=torch.float64, device="cuda") for c in cases]
         ps = [torch.zeros(c.N, c.N, dtype=torch.float64, device="cuda") for c in cases]
         return plans, fs, ps
 
     plans32, fs32, ps32 = make("fp32")
     plans64, fs64, ps64 = make("fp64")
+    pc32 = [torch.zeros_like(p) for p in ps32]
+    ws = WarmStart()
+    targets = [c.target for c in cases]
     torch.cuda.synchronize()
 
-    # ---- FP32 path (timed steps) --------------------------------------------
-    tol32, tol64 = 1e-8, 1e-10
-    for _ in range(args.warmup):
-        solve_set(cb, plans32, fs32, ps32, cases, tol32, args.sequential)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res32 = solve_set(cb, plans32, fs32, ps32, cases, tol32, args.sequential)
-    torch.cuda.synchronize()
-    t32 = time.perf_counter() - t0
-    value = len(cases) * args.steps / t32
+    def step_learned():
+        for pl, f, p, c in zip(plans32, fs32, ps32, cases):
+            ws(pl, f, c.target, p)
+        return cb.cb_solve_batch(plans32, fs32, targets, [1] * n, ps32, tol=TOL, init=1)
 
-    # ---- plain FP64 path (one timed step) -------------------------------------
-    solve_set(cb, plans64[:2], fs64[:2], ps64[:2], cases[:2], tol64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res64 = solve_set(cb, plans64, fs64, ps64, cases, tol64, args.sequential)
-    torch.cuda.synchronize()
-    t64 = time.perf_counter() - t0
-    value64 = len(cases) / t64
+    def step_cold32():
+        return cb.cb_solve_batch(plans32, fs32, targets, [1] * n, pc32, tol=TOL)
 
-    # ---- accuracy of the FP32 path against the FP64 path ----------------------
-    ep, eF, agr = [], [], []
-    for a, b, ra, rb in zip(ps32, ps64, res32, res64):
-        ep.append((torch.linalg.norm(a - b) / torch.linalg.norm(b)).item())
-        eF.append(abs(ra["F"] - rb["F"]) / rb["F"])
-        sa, sb = a > 0, b > 0
-        uni = (sa | sb).sum().item()
-        agr.append(1.0 - (sa ^ sb).sum().item() / max(uni, 1))
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = fn()
+        torch.cuda.synchronize()
+        return res, time.perf_counter() - t0
+
+    # ---- the full method (value) ------------------------------------------------
+    res_l, t_l = timed(step_learned, args.steps, args.warmup)
+    value = n * args.steps / t_l
+    # ---- FP32 batched, cold start ----------------------------------------------
+    res_c, t_c = timed(step_cold32, args.steps, args.warmup)
+    value_c = n * args.steps / t_c
+    # ---- plain FP64: cold start, one solve after another --------------------------
+    def step_plain64():
+        return [cb.cb_solve_force(pl, f, c.target, p, tol=TOL) for pl, f, p, c in zip(plans64, fs64, ps64, cases)]
+    res_p, t_p = timed(step_plain64, 1, 1)
+    value_p = n / t_p
+    # ---- FP64 reference (residual 1e-10) for the accuracy checks ------------------
+    pref = [torch.zeros_like(p) for p in ps64]
+    res_r = cb.cb_solve_batch(plans64, fs64, targets, [1] * n, pref, tol=TOL_REF)
+    torch.cuda.synchronize()
+
+    def accuracy(ps, res):
+        ep, eF, agr = [], [], []
+        for a, b, ra, rb in zip(ps, pref, res, res_r):
+            ep.append((torch.linalg.norm(a - b) / torch.linalg.norm(b)).item())
+            eF.append(abs(ra["F"] - rb["F"]) / rb["F"])
+            sa, sb = a > 0, b > 0
+            uni = (sa | sb).sum().item()
+            agr.append(1.0 - (sa ^ sb).sum().item() / max(uni, 1))
+        return {"max_rel_L2_p": max(ep), "max_rel_F": max(eF), "min_set_agreement": min(agr)}
+
+    acc_l, acc_c, acc_p = accuracy(ps32, res_l), accuracy(pc32, res_c), accuracy(ps64, res_p)
+    it = lambda res: float(np.mean([r["iters"] for r in res]))  # noqa: E731
 
     # ---- apply_K roofline -------------------------------------------------------
-    dev = "cuda"
     rng = np.random.default_rng(0)
     pr = rng.standard_normal((N, N))
     timing = {}
     for prec, plans, s in (("fp32", plans32, 4), ("fp64", plans64, 8)):
         dt = torch.float32 if prec == "fp32" else torch.float64
-        p = torch.tensor(pr, dtype=dt, device=dev)
+        p = torch.tensor(pr, dtype=dt, device="cuda")
         u = torch.empty_like(p)
         ms = time_apply(cb, plans[0], p, u)
         ab = alg_bytes(N, s)
@@ -186,23 +224,29 @@ def main():
     t32k = timing["fp32"]
     dom = max(("k1_rows_fwd", "k2_cols", "k3_rows_inv"), key=lambda k: t32k[k]["ms"])
     ach = t32k[dom]["GBps"]
+    variant = cb.cb_plan_get_info(plans32[0])["fft_variant"]
+    traffic = None
+    if (dom == K2_TRAFFIC["kernel"] and N == K2_TRAFFIC["N"] and variant == K2_TRAFFIC["variant"]
+            and fft_src_hash() == K2_TRAFFIC["src"]):
+        traffic = K2_TRAFFIC["fetch_bytes"] + K2_TRAFFIC["write_bytes"]
     roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": ach / PEAK_HBM_GBPS, "traffic": None,
-            "bytes_per_launch": t32k[dom]["bytes"], "mean_launch_ms": t32k[dom]["ms"]}
+            "frac": ach / PEAK_HBM_GBPS, "traffic": traffic,
+            "bytes_per_launch": t32k[dom]["bytes"], "mean_launch_ms": t32k[dom]["ms"],
+            "fft_variant": variant}
 
     if args.dump:
         rows = []
-        for c, ra, rb, e1, e2, e3 in zip(cases, res32, res64, ep, eF, agr):
+        for c, a, b, d, r in zip(cases, res_l, res_c, res_p, res_r):
             rows.append(dict(shape=c.shape, h=c.h, E1=c.E1, nu1=c.nu1, nu2=c.nu2, F=c.target,
-                             it32=ra["iters"], it64=rb["iters"], st32=ra["status"], st64=rb["status"],
-                             res32=ra["resid"], res64=rb["resid"], ms32=ra["ms"], ms64=rb["ms"],
-                             area=rb["area"], d=rb["d"], ep=e1, eF=e2, agr=e3))
+                             it_learned=a["iters"], it_cold32=b["iters"], it_plain64=d["iters"],
+                             it_ref=r["iters"], ms_learned=a["ms"], ms_cold32=b["ms"], ms_plain64=d["ms"],
+                             area=r["area"], d=r["d"]))
         with open(args.dump, "w") as fh:
             json.dump(rows, fh, indent=1)
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(cases[0], res64[0]["iters"], args.cpu_iters)
+        cpu = cpu_baseline(cases[0], res_p[0]["iters"], args.cpu_iters)
 
     line = {
         "metric": METRIC,
@@ -211,24 +255,26 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * t32 / args.steps,
+        "ms_per_step": 1e3 * t_l / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"{len(cases)} force-controlled contact solves at N={N} (padded {2*N}^2 FFT), "
-                         "batched recipe seed 1024, FP32 direction convolutions + FP64 state/reductions, residual 1e-8, cold start, "
-                         "solved concurrently by cb_solve_batch"),
-            "N": N, "solves_per_step": len(cases), "tol": tol32,
+            "workload": (f"{n} force-controlled contact solves at N={N} (padded {2*N}^2 FFT), batched recipe "
+                         f"seed 1024, residual {TOL:g}: learned warm start (256^2 BF16 network) + FP32 direction "
+                         "convolutions with FP64 state/reductions, solved concurrently by cb_solve_batch"),
+            "N": N, "solves_per_step": n, "tol": TOL,
         },
         "roofline": roof,
         "cpu_baseline": cpu,
-        "plain_fp64": {"value": value64, "unit": "solves/s", "tol": tol64,
-                       "mean_iters": float(np.mean([r["iters"] for r in res64]))},
-        "fp32_mean_iters": float(np.mean([r["iters"] for r in res32])),
-        "fp32_vs_fp64": {"max_rel_L2_p": max(ep), "max_rel_F": max(eF), "min_set_agreement": min(agr)},
+        "accuracy_vs_fp64_1e-10": acc_l,
+        "mean_iters": it(res_l),
+        "fp32_cold_batched": {"value": value_c, "unit": "solves/s", "mean_iters": it(res_c), "accuracy": acc_c},
+        "plain_fp64": {"value": value_p, "unit": "solves/s", "mean_iters": it(res_p), "accuracy": acc_p,
+                       "how": "FP64 plans, cold start, one cb_solve_force after another"},
+        "speedup_vs_plain_fp64": value / value_p,
         "apply_K": {prec: {k: {"ms": round(v["ms"], 5), "GBps": round(v["GBps"], 1)} for k, v in t.items()}
                     for prec, t in timing.items()},
     }
