@@ -312,6 +312,13 @@ int cb_net_features(cb_net net, const double* f, int Nf, double L, double h,
 int cb_net_warmstart(cb_net net, cb_plan plan, const double* f, double F,
                      double cut, double* p_out);
 
+/* The same for n <= batch problems at once (one forward pass of n
+ * samples): plans[i], f[i] (plans[i]'s N x N), F_host[i], p_out[i].
+ * Synchronises the net's stream. */
+int cb_net_warmstart_batch(cb_net net, int n, const cb_plan* plans,
+                           const double* const* f, const double* F_host,
+                           double cut, double* const* p_out);
+
 /* Status text; cb_last_error: last error message of this thread. */
 const char* cb_status_string(int status);
 const char* cb_last_error(void);

@@ -110,6 +110,8 @@ _SIGS = {
     "cb_net_adam_step": (_i, [_vp, ctypes.c_float]),
     "cb_net_features": (_i, [_vp, _vp, _i, _d, _d, _d, _d, _d, _d, _d, _vp]),
     "cb_net_warmstart": (_i, [_vp, _vp, _vp, _d, _d, _vp]),
+    "cb_net_warmstart_batch": (_i, [_vp, _i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_d), _d,
+                                    ctypes.POINTER(_vp)]),
     "cb_status_string": (ctypes.c_char_p, [_i]),
     "cb_last_error": (ctypes.c_char_p, []),
     "cb_version": (_i, []),
@@ -379,3 +381,13 @@ def cb_net_warmstart(net: Net, plan: Plan, f, F, p_out, cut=0.0):
     _check(_lib.cb_net_warmstart(net.handle, plan.handle, _arr(plan, f, "f", torch.float64), float(F), float(cut),
                                  _arr(plan, p_out, "p_out", torch.float64)))
     return p_out
+
+
+def cb_net_warmstart_batch(net: Net, plans, fs, Fs, ps_out, cut=0.0):
+    n = len(plans)
+    hp = (_vp * n)(*[pl.handle for pl in plans])
+    hf = (_vp * n)(*[_arr(pl, f, "f", torch.float64).value for pl, f in zip(plans, fs)])
+    hpp = (_vp * n)(*[_arr(pl, p, "p_out", torch.float64).value for pl, p in zip(plans, ps_out)])
+    hF = (_d * n)(*[float(F) for F in Fs])
+    _check(_lib.cb_net_warmstart_batch(net.handle, n, hp, hf, hF, float(cut), hpp))
+    return ps_out

@@ -314,18 +314,32 @@ __global__ void k_weights_bf16(const float* __restrict__ prm, u16* __restrict__ 
 // ---------------------------------------------------------------------------
 // Warm-start input features and output prolongation
 // ---------------------------------------------------------------------------
-// min of f over N*N -> out[0] (one block, fixed order)
-__global__ void __launch_bounds__(256) k_fmin(const double* __restrict__ f, int n, double* out) {
+// Two-stage reductions for the warm start: RP blocks write one partial
+// each; the consumer folds the RP partials in a fixed order.
+constexpr int RP = 64;
+
+// partial minima of f over N*N
+__global__ void __launch_bounds__(256) k_fmin(const double* __restrict__ f, int n, double* part) {
   __shared__ double sh[256];
   double m = INFINITY;
-  for (int e = threadIdx.x; e < n; e += 256) m = fmin(m, f[e]);
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += RP * 256) m = fmin(m, f[e]);
   sh[threadIdx.x] = m;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sh[0];
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__device__ __forceinline__ double fold_min(const double* part) {
+  double m = part[0];
+  for (int b = 1; b < RP; b++) m = fmin(m, part[b]);
+  return m;
+}
+__device__ __forceinline__ double fold_sum(const double* part) {
+  double s = 0.0;
+  for (int b = 0; b < RP; b++) s += part[b];
+  return s;
 }
 
 struct Scalars {
@@ -339,7 +353,7 @@ struct Scalars {
 __global__ void k_features(const double* __restrict__ f, int N, int G, double L, const double* fminp, Scalars sc,
                            float* __restrict__ x) {
   const int tot = G * G;
-  const double f0 = fminp[0];
+  const double f0 = fold_min(fminp);
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
     const int y = e / G, xx = e % G;
     double g0;
@@ -364,18 +378,18 @@ __global__ void k_features(const double* __restrict__ f, int N, int G, double L,
   }
 }
 
-// mean of softplus(z) over the G x G head (one block, fixed order)
-__global__ void __launch_bounds__(256) k_qmean(const float* __restrict__ Z16, int G, double* out) {
+// partial sums of softplus(z) over the G x G head
+__global__ void __launch_bounds__(256) k_qmean(const float* __restrict__ Z16, int G, double* part) {
   __shared__ double sh[256];
   double s = 0.0;
-  for (int e = threadIdx.x; e < G * G; e += 256) s += softplusf(Z16[(size_t)e * C]);
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < G * G; e += RP * 256) s += softplusf(Z16[(size_t)e * C]);
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
     if (threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = sh[0] / ((double)G * G);
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
 // p[N x N] from the head output z (channel 0 of a G x G x 16 FP32 tensor):
@@ -391,7 +405,7 @@ __device__ __forceinline__ double qcut(const float* Z16, int G, int yy, int xx, 
 __global__ void k_prolong(const float* __restrict__ Z16, int G, int N, const double* meanp, double cut,
                           double* __restrict__ p) {
   const int tot = N * N;
-  const double im = 1.0 / meanp[0];
+  const double im = ((double)G * G) / fold_sum(meanp);
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
     const int y = e / N, x = e % N;
     double v;
@@ -503,8 +517,8 @@ extern "C" int cb_net_create(cb_net* out, int batch, int H, int W, void* stream)
   A((void**)&N->wpart, nw * LW * 4);
   A((void**)&N->bpart, nw * C * 4);
   A((void**)&N->lossv, batch * 8);
-  A((void**)&N->scratch, 64);
-  A((void**)&N->feat, (size_t)H * W * C * 4);
+  A((void**)&N->scratch, (size_t)2 * batch * RP * 8);
+  A((void**)&N->feat, px * C * 4);
   if (rc == CB_OK && hipHostMalloc((void**)&N->lossh, batch * 8, 0) != hipSuccess) rc = cb_fail(CB_E_NOMEM, "pinned");
   if (rc == CB_OK && (hipMemset(N->m1, 0, NPARAM * 4) != hipSuccess || hipMemset(N->m2, 0, NPARAM * 4) != hipSuccess ||
                       hipMemset(N->prm, 0, NPARAM * 4) != hipSuccess))
@@ -660,8 +674,9 @@ extern "C" int cb_net_adam_step(cb_net N, float lr) {
   return CB_OK;
 }
 
-extern "C" int cb_net_features(cb_net N, const double* f, int Nf, double L, double h, double E1, double nu1, double E2,
-                               double nu2, double F, float* x) {
+// features of one problem into x, its min f kept in scratch[slot]
+static int features_into(cb_net N, const double* f, int Nf, double L, double h, double E1, double nu1, double E2,
+                         double nu2, double F, float* x, int slot) {
   if (!N || !f || !x) return cb_fail(CB_E_INVALID, "null argument");
   if (N->H != N->W) return cb_fail(CB_E_INVALID, "square net grid required");
   const int G = N->H;
@@ -674,22 +689,44 @@ extern "C" int cb_net_features(cb_net N, const double* f, int Nf, double L, doub
   sc.s[3] = (float)(2.0 * nu2);
   sc.s[4] = (float)(std::log10(std::max(F, 1e-300) / (E2s * L * L)) / 4.0);
   sc.s[5] = 1.f;
-  hipLaunchKernelGGL(k_fmin, dim3(1), dim3(256), 0, N->stream, f, Nf * Nf, N->scratch);
-  hipLaunchKernelGGL(k_features, egrid((long long)G * G), dim3(256), 0, N->stream, f, Nf, G, L, (const double*)N->scratch,
-                     sc, x);
+  hipLaunchKernelGGL(k_fmin, dim3(RP), dim3(256), 0, N->stream, f, Nf * Nf, N->scratch + (size_t)slot * RP);
+  hipLaunchKernelGGL(k_features, egrid((long long)G * G), dim3(256), 0, N->stream, f, Nf, G, L,
+                     (const double*)(N->scratch + (size_t)slot * RP), sc, x);
   CB_HIP(hipGetLastError());
   return CB_OK;
 }
 
-extern "C" int cb_net_warmstart(cb_net N, cb_plan P, const double* f, double F, double cut, double* p_out) {
-  if (!N || !P || !f || !p_out) return cb_fail(CB_E_INVALID, "null argument");
+extern "C" int cb_net_features(cb_net N, const double* f, int Nf, double L, double h, double E1, double nu1, double E2,
+                               double nu2, double F, float* x) {
+  return features_into(N, f, Nf, L, h, E1, nu1, E2, nu2, F, x, 0);
+}
+
+extern "C" int cb_net_warmstart_batch(cb_net N, int n, const cb_plan* plans, const double* const* f,
+                                      const double* F_host, double cut, double* const* p_out) {
+  if (!N || !plans || !f || !F_host || !p_out) return cb_fail(CB_E_INVALID, "null argument");
+  if (n < 1 || n > N->batch) return cb_fail(CB_E_INVALID, "batch size out of range");
   if (!(cut >= 0.0)) return cb_fail(CB_E_INVALID, "cut must be >= 0");
-  if (int rc = cb_net_features(N, f, P->N, P->L, P->h, P->E1, P->nu1, P->E2, P->nu2, F, N->feat)) return rc;
-  if (int rc = cb_net_forward(N, 1, N->feat, nullptr)) return rc;
-  hipLaunchKernelGGL(k_qmean, dim3(1), dim3(256), 0, N->stream, N->head, N->H, N->scratch + 1);
-  hipLaunchKernelGGL(k_prolong, egrid((long long)P->N * P->N), dim3(256), 0, N->stream, N->head, N->H, P->N,
-                     (const double*)(N->scratch + 1), cut, p_out);
+  const size_t hwc = (size_t)N->H * N->W * C;
+  for (int i = 0; i < n; i++) {
+    const cb_plan P = plans[i];
+    if (!P || !f[i] || !p_out[i]) return cb_fail(CB_E_INVALID, "null plan or array in the batch");
+    if (int rc = features_into(N, f[i], P->N, P->L, P->h, P->E1, P->nu1, P->E2, P->nu2, F_host[i], N->feat + i * hwc,
+                               i))
+      return rc;
+  }
+  if (int rc = cb_net_forward(N, n, N->feat, nullptr)) return rc;
+  for (int i = 0; i < n; i++) {
+    const cb_plan P = plans[i];
+    double* mean = N->scratch + (size_t)(N->batch + i) * RP;
+    hipLaunchKernelGGL(k_qmean, dim3(RP), dim3(256), 0, N->stream, N->head + i * hwc, N->H, mean);
+    hipLaunchKernelGGL(k_prolong, egrid((long long)P->N * P->N), dim3(256), 0, N->stream, N->head + i * hwc, N->H,
+                       P->N, (const double*)mean, cut, p_out[i]);
+  }
   CB_HIP(hipGetLastError());
   CB_HIP(hipStreamSynchronize(N->stream));
   return CB_OK;
+}
+
+extern "C" int cb_net_warmstart(cb_net N, cb_plan P, const double* f, double F, double cut, double* p_out) {
+  return cb_net_warmstart_batch(N, 1, &P, &f, &F, cut, &p_out);
 }

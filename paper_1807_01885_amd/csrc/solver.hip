@@ -191,15 +191,15 @@ k_pk_dir(const double* __restrict__ p, const double* __restrict__ g, TD* __restr
          double* gbar2, double* part, int nb, int n, int par) {
   if (st->done) return;
   const bool mx7[7] = {false, false, false, false, false, true, true};
-  const bool mx3[3] = {false, false, false};
-  double a[7], u3[3];
+  const bool mx4[4] = {false, false, false, false};
+  double a[7], u4[4];
   fold<7>(region(part, R_GAP0 + par), nb, mx7, a);
-  fold<3>(region(part, R_UPD), nb, mx3, u3);
+  fold<4>(region(part, R_UPD), nb, mx4, u4);
   const double s = st->force ? gbar2[par] : st->d_in;
   const GapTotals gt = gap_totals(a, st);
   if (record_check(gt, st, gbar2, s, par)) return;
   double beta = 0.0;
-  if (u3[1] == 0.0) {  // no restart requested by the previous update
+  if (u4[3] == 0.0) {  // no restart requested by the previous update
     double b[7];
     fold<7>(region(part, R_GAP0 + (par ^ 1)), nb, mx7, b);
     const double nb2 = b[2];
@@ -257,10 +257,10 @@ __global__ void __launch_bounds__(RT)
 k_pk_dir_pc(const double* __restrict__ p, const TD* __restrict__ zp, TD* __restrict__ t,
             SolverState* __restrict__ st, double* part, int nb, int n, int par) {
   if (st->done) return;
-  const bool mx2[2] = {false, false}, mx3[3] = {false, false, false};
-  double a[2], u3[3];
+  const bool mx2[2] = {false, false}, mx4[4] = {false, false, false, false};
+  double a[2], u4[4];
   fold<2>(region(part, R_PZ0 + par), nb, mx2, a);
-  fold<3>(region(part, R_UPD), nb, mx3, u3);
+  fold<4>(region(part, R_UPD), nb, mx4, u4);
   const double nn = st->nact;
   const double zbar = (st->force && nn > 0.0) ? a[0] / nn : 0.0;
   // A cell that becomes active takes the step -tau * act_scale * g: the
@@ -271,7 +271,7 @@ k_pk_dir_pc(const double* __restrict__ p, const TD* __restrict__ zp, TD* __restr
     st->act_scale = (G > 0.0 && a[1] > 0.0) ? a[1] / G : 1.0;
   }
   double beta = 0.0;
-  if (u3[1] == 0.0) {
+  if (u4[3] == 0.0) {
     double b[2];
     fold<2>(region(part, R_PZ0 + (par ^ 1)), nb, mx2, b);
     beta = b[1] > 0.0 ? a[1] / b[1] : 0.0;
@@ -306,17 +306,20 @@ k_pk_step(const double* __restrict__ p, const double* __restrict__ g, const TD* 
 // tau; p <- max(p - tau t, 0) on Ic; p = 0 and g < -theta -> p = -tau g
 // (activation, restarts the conjugate directions); u <- u - tau K t (exact
 // while no cell is clipped or activated); partials: sum p, activations,
-// clipped cells.  theta = current relative residual x rms of (d - f) on
-// Ic: a cell whose penetration is below the residual level of the contact
-// set is not activated yet (Polonsky-Keer activate at any g < 0, which
-// makes edge cells cycle between clipping and activation, each cycle a
-// restart); the stopping test still requires g >= -tol x rms everywhere,
-// so the converged solution is the same.
+// clipped cells, activations that restart.  theta = current relative
+// residual x rms of (d - f) on Ic: a cell whose penetration is below the
+// residual level of the contact set is not activated yet (Polonsky-Keer
+// activate at any g < 0, which makes edge cells cycle between clipping and
+// activation, each cycle a restart); the stopping test still requires
+// g >= -tol x rms everywhere, so the converged solution is the same.
+// With `clip` (preconditioned method), a cell clipped in this or the
+// previous iteration that re-enters does not restart the directions: such
+// bounces at the contact edge otherwise restart nearly every iteration.
 template <typename TD>
 __global__ void __launch_bounds__(RT)
 k_pk_update(double* __restrict__ p, double* __restrict__ u, const double* __restrict__ g,
             const TD* __restrict__ t, const TD* __restrict__ r, const SolverState* __restrict__ st, double* part,
-            int nb, int n) {
+            unsigned char* __restrict__ clip, int nb, int n) {
   if (st->done) return;
   const bool mx4[4] = {false, false, false, false};
   double a[4];
@@ -327,26 +330,29 @@ k_pk_update(double* __restrict__ p, double* __restrict__ u, const double* __rest
   const double tau = rt > 0.0 ? a[0] / rt : 1.0 / st->k00;
   const double m = st->gdev;
   const double theta = st->theta;
-  double v[3] = {0.0, 0.0, 0.0};
-  const bool mx[3] = {false, false, false};
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const bool mx[4] = {false, false, false, false};
 #pragma unroll 4
   GRID_LOOP(i, n) {
     double pi = p[i];
     const bool on = pi > 0.0;
     if (on) pi -= tau * (double)t[i];
     double pn = pi > 0.0 ? pi : 0.0;
-    if (on && pn == 0.0) v[2] += 1.0;
+    const bool clipped = on && pn == 0.0;
+    if (clipped) v[2] += 1.0;
     const double gi = g[i] - m;
     if (pn == 0.0 && gi < -theta) {
       pn = -tau * st->act_scale * gi;
       v[1] += 1.0;
+      if (!clip || !(clipped || clip[i])) v[3] += 1.0;
     }
+    if (clip) clip[i] = clipped ? 1 : 0;
     p[i] = pn;
     u[i] -= tau * (double)r[i];
     v[0] += pn;
   }
-  block_allreduce<3>(v, mx);
-  write_partials<3>(region(part, R_UPD), v);
+  block_allreduce<4>(v, mx);
+  write_partials<4>(region(part, R_UPD), v);
 }
 
 // force control: p, u *= F / (dA sum p); block 0 decides whether u must be
@@ -355,9 +361,9 @@ __global__ void __launch_bounds__(RT)
 k_pk_post(double* __restrict__ p, double* __restrict__ u, SolverState* st, const double* part, int nb, int n,
           int refresh) {
   if (st->done) return;
-  const bool mx3[3] = {false, false, false};
-  double a[3];
-  fold<3>(region(part, R_UPD), nb, mx3, a);
+  const bool mx4[4] = {false, false, false, false};
+  double a[4];
+  fold<4>(region(part, R_UPD), nb, mx4, a);
   if (blockIdx.x == 0 && threadIdx.x == 0)
     st->skip_u = (refresh || a[1] > 0.0 || a[2] > 0.0) ? 0 : 1;
   if (!st->force || !(a[0] > 0.0)) return;
@@ -369,21 +375,22 @@ k_pk_post(double* __restrict__ p, double* __restrict__ u, SolverState* st, const
   }
 }
 
-// sum p -> R_UPD with the restart flag set (first iteration: no beta)
+// sum p -> R_UPD with the restart flags set (first iteration: no beta)
 __global__ void __launch_bounds__(RT) k_pk_seed(const double* __restrict__ p, double* part, int n) {
-  double v[3] = {0.0, blockIdx.x == 0 && threadIdx.x == 0 ? 1.0 : 0.0, 0.0};
-  const bool mx[3] = {false, false, false};
+  const double one = blockIdx.x == 0 && threadIdx.x == 0 ? 1.0 : 0.0;
+  double v[4] = {0.0, one, 0.0, one};
+  const bool mx[4] = {false, false, false, false};
   GRID_LOOP(i, n) v[0] += p[i];
-  block_allreduce<3>(v, mx);
-  write_partials<3>(region(part, R_UPD), v);
+  block_allreduce<4>(v, mx);
+  write_partials<4>(region(part, R_UPD), v);
 }
 
 // force control start: p *= F / (dA sum p)
 __global__ void __launch_bounds__(RT) k_pk_scale0(double* __restrict__ p, const SolverState* st, const double* part,
                                                   int nb, int n) {
-  const bool mx3[3] = {false, false, false};
-  double a[3];
-  fold<3>(region(part, R_UPD), nb, mx3, a);
+  const bool mx4[4] = {false, false, false, false};
+  double a[4];
+  fold<4>(region(part, R_UPD), nb, mx4, a);
   if (!(a[0] > 0.0)) return;
   const double sc = st->Ftarget / (st->dA * a[0]);
   GRID_LOOP(i, n) p[i] *= sc;
@@ -731,7 +738,8 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
     }
     if (hipError_t e = apply_dir(c, t, r, skip_done)) return e;
     hipLaunchKernelGGL(k_pk_step<TD>, grid, blk, 0, c.st, p, g, t, r, st, part, c.n);
-    hipLaunchKernelGGL(k_pk_update<TD>, grid, blk, 0, c.st, p, u, g, t, r, st, part, c.nb, c.n);
+    hipLaunchKernelGGL(k_pk_update<TD>, grid, blk, 0, c.st, p, u, g, t, r, st, part, pc ? P->d_det : nullptr,
+                       c.nb, c.n);
     hipLaunchKernelGGL(k_pk_post, force ? grid : dim3(1), blk, 0, c.st, p, u, st, part, c.nb, c.n,
                        i == chunk - 1 ? 1 : 0);
     if (hipError_t e = apply64(c, p, u, skip_u)) return e;
@@ -903,6 +911,7 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
   CB_HIP(hipMemsetAsync(P->d_t, 0, (size_t)c.n * 8, c.st));
   CB_HIP(hipMemsetAsync(P->d_r, 0, (size_t)c.n * 8, c.st));
   CB_HIP(hipMemsetAsync(P->d_pold, 0, (size_t)c.n * 8, c.st));
+  hipLaunchKernelGGL(k_zero_bytes, grid, blk, 0, c.st, P->d_det, c.n);  // clip flags of the preconditioned method
   hipLaunchKernelGGL(k_pk_seed, grid, blk, 0, c.st, (const double*)p, P->d_part, c.n);
   if (force) hipLaunchKernelGGL(k_pk_scale0, grid, blk, 0, c.st, p, P->d_state, P->d_part, c.nb, c.n);
   CB_HIP(apply64(c, p, (double*)P->d_u, nullptr));

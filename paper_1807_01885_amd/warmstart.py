@@ -164,17 +164,21 @@ def load(path=WEIGHTS):
 class WarmStart:
     """Trained network bound to a stream: ws(plan, f, F, p_out) fills p_out."""
 
-    def __init__(self, path=WEIGHTS, cut=None, stream=None, params=None):
+    def __init__(self, path=WEIGHTS, cut=None, stream=None, params=None, batch=1):
         meta = {}
         if params is None:
             params, meta = load(path)
         self.meta = meta
         self.cut = float(meta.get("cut", 0.1) if cut is None else cut)
-        self.net = cb.cb_net_create(1, G, G, stream=stream)
+        self.net = cb.cb_net_create(batch, G, G, stream=stream)
         cb.cb_net_set_params(self.net, torch.tensor(params, device="cuda"))
 
     def __call__(self, plan, f, F, p_out):
         return cb.cb_net_warmstart(self.net, plan, f, F, p_out, cut=self.cut)
+
+    def batch(self, plans, fs, Fs, ps_out):
+        """Warm starts of up to `batch` problems with one forward pass."""
+        return cb.cb_net_warmstart_batch(self.net, plans, fs, Fs, ps_out, cut=self.cut)
 
 
 def compare(ws, problems, tol=TOL, precision="fp32", log=None):

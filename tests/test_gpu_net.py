@@ -226,3 +226,26 @@ def test_net_errors(lib):
         lib.cb_net_warmstart(lib.cb_net_create(1, 64, 32), plan, f, 1.0, torch.empty_like(f))
     with pytest.raises(lib.CoatbemError):  # negative cut
         lib.cb_net_warmstart(lib.cb_net_create(1, 32, 32), plan, f, 1.0, torch.empty_like(f), cut=-1.0)
+
+
+def test_warmstart_batch_equals_single(lib):
+    """One forward pass over mixed-size problems gives, bit for bit, what
+    one call per problem gives."""
+    params = _params(8)
+    L = 1.0
+    specs = [(128, 0.02, 10.0, 1.5e-3), (512, 0.005, 40.0, 4e-3), (256, 0.1, 0.3, 1e-3)]
+    net1 = _net(lib, params, 1, 256, 256)
+    netb = _net(lib, params, len(specs), 256, 256)
+    plans, fs, Fs, single = [], [], [], []
+    for N, h, E1, F in specs:
+        plan = lib.cb_plan_create(N, L, h, E1, 0.3, 1.0, 0.3, 0.0, "fp32")
+        f = torch.tensor(inputs.cone(N, L, 0.1), dtype=torch.float64, device="cuda")
+        p = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        lib.cb_net_warmstart(net1, plan, f, F, p, cut=0.1)
+        plans.append(plan), fs.append(f), Fs.append(F), single.append(p)
+    outs = [torch.full_like(p, -1.0) for p in single]
+    lib.cb_net_warmstart_batch(netb, plans, fs, Fs, outs, cut=0.1)
+    for a, b in zip(outs, single):
+        assert torch.equal(a, b)
+    with pytest.raises(lib.CoatbemError):
+        lib.cb_net_warmstart_batch(net1, plans, fs, Fs, outs, cut=0.1)   # n > batch
