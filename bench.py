@@ -130,6 +130,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--dump", default=None, help="write per-problem results (JSON) here")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="only launch K2 (N=1024, FP32, tuned shape) 10 times and a 64 MiB device copy 5 times, "
+                         "for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -145,6 +148,20 @@ def main():
     from paper_1807_01885_amd.warmstart import WarmStart
 
     torch.cuda.set_device(0)
+    if args.pmc_probe:
+        plan = cb.cb_plan_create(1024, 1.0, 0.05, 20.0, 0.3, 1.0, 0.25, 0.0, "fp32", tune_cache=TUNE_CACHE)
+        p = torch.randn(1024, 1024, dtype=torch.float32, device="cuda")
+        u = torch.empty_like(p)
+        cb.cb_apply_K(plan, p, u)
+        for _ in range(10):
+            cb.cb_apply_K_stages(plan, p, u, 2)
+        a = torch.ones(64 * 2**20 // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": "done", "fft_variant": cb.cb_plan_get_info(plan)["fft_variant"]}))
+        return
     cases = inputs.headline_set(n=args.n_solves)
     N = cases[0].N
     n = len(cases)

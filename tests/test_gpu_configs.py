@@ -1,0 +1,154 @@
+"""The two full-size workloads the per-step parity tests do not reach.
+
+N = 2048 (flat punch and rough indenter on a soft coating, padded 4096^2)
+and the N = 512 adhesive approach/retraction sweeps (200 steps each) are
+too large for an oracle solve in a test, so they are checked through
+properties every correct solution has, evaluated with the FP64 oracle's
+operator on the GPU's pressure:
+  - the contact conditions (Sec. 2): on the contact set the gap
+    u + f - d vanishes to the solve tolerance, off it there is no
+    penetration, and p = 0 off the set (non-adhesive: p >= 0; adhesive:
+    no boundary cell below -sigma_c, Eq. 12);
+  - FP32 against FP64 paths: pressure relative L2 <= 1e-4, force <= 1e-5,
+    contact sets agreeing on >= 99.9 % of their union.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.operator import Operator
+from oracle.transfer import Material, critical_stress
+from paper_1807_01885_amd import inputs
+
+pytestmark = pytest.mark.gpu
+TOL = {"fp64": 1e-10, "fp32": 1e-8}
+
+
+def _agreement(a, b):
+    u = (a | b).sum()
+    return 1.0 if u == 0 else 1.0 - (a ^ b).sum() / u
+
+
+def _gap(op, p, f, d):
+    return op.apply(p) + f - d
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_c3_n2048_contact_conditions_and_fp32(lib, which):
+    c = inputs.flat_and_rough_c3(N=2048, seeds=(0,))[which]
+    print(f"C3 {c.shape} N={c.N}", flush=True)
+    op = Operator(c.N, c.L, Material(c.h, c.E1, c.nu1, c.E2, c.nu2))
+    ft = torch.tensor(c.f, dtype=torch.float64, device="cuda")
+    out = {}
+    for prec in ("fp64", "fp32"):
+        plan = lib.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, prec)
+        p = torch.zeros_like(ft)
+        res = lib.cb_solve_indent(plan, ft, c.target, p, tol=TOL[prec])
+        pn = p.cpu().numpy()
+        g = _gap(op, pn, c.f, c.target)
+        S = pn > 0
+        rel = np.linalg.norm(g[S]) / np.linalg.norm((c.target - c.f)[S])
+        scale = np.linalg.norm((c.target - c.f)[S]) / np.sqrt(S.sum())
+        pen = max(0.0, -g[~S].min()) / scale
+        print(f"  {prec}: iters {res['iters']} {res['ms']:.0f} ms F {res['F']:.6e} area {res['area']:.4f} "
+              f"gap on S {rel:.1e} penetration off S {pen:.1e}", flush=True)
+        assert res["status"] == 0 and pn.min() >= 0.0
+        assert rel < 10 * TOL[prec] + 1e-12
+        assert pen < 10 * TOL[prec] + 1e-12
+        out[prec] = (pn, res)
+    (a, ra), (b, rb) = out["fp32"], out["fp64"]
+    e_p = np.linalg.norm(a - b) / np.linalg.norm(b)
+    e_F = abs(ra["F"] - rb["F"]) / rb["F"]
+    agr = _agreement(a > 0, b > 0)
+    print(f"  fp32 vs fp64: p {e_p:.1e} F {e_F:.1e} sets {agr:.6f}", flush=True)
+    assert e_p < 1e-4 and e_F < 1e-5 and agr >= 0.999
+
+
+ATTACH = {"fp64": 1e-12, "fp32": 1e-9}   # default attach tolerance / L
+
+
+def _adhesive_conditions(op, p, S, f, d, sigma_c, prec):
+    """Relative gap on S, penetration off S beyond the attach tolerance
+    (relative), max |p| off S, and max(-p)/sigma_c on the boundary of S."""
+    g = _gap(op, p, f, d)
+    scale = np.abs(d - f[S]).max() if S.any() else 1.0
+    on = np.abs(g[S]).max() / scale if S.any() else 0.0
+    pen = max(0.0, -g[~S].min() - ATTACH[prec] * op.L) / scale
+    off = np.abs(p[~S]).max() if (~S).any() else 0.0
+    # boundary of S: in S with a 4-neighbour outside S or on the grid edge
+    pad = np.pad(S, 1, constant_values=False)
+    inner = pad[:-2, 1:-1] & pad[2:, 1:-1] & pad[1:-1, :-2] & pad[1:-1, 2:]
+    bnd = S & ~inner
+    low = (-p[bnd]).max() / sigma_c if bnd.any() else 0.0
+    return on, pen, off, low
+
+
+def test_c2_adhesive_sweep_n512(lib):
+    """One of the six sweeps (h = 0.1, E1/E2 = 10) in segments of 40 steps
+    (the state carries over), FP32 and FP64, contact conditions checked
+    after each segment; F(d) and pull-off force of FP32 against FP64."""
+    c = inputs.adhesive_sweep_c2()[3]
+    steps = c.meta["d_steps"]
+    mat = Material(c.h, c.E1, c.nu1, c.E2, c.nu2)
+    op = Operator(c.N, c.L, mat)
+    sc = critical_stress(mat, c.dgamma, c.L / c.N)
+    ft = torch.tensor(c.f, dtype=torch.float64, device="cuda")
+    curves = {}
+    for prec in ("fp64", "fp32"):
+        print(f"C2 sweep h={c.h} E1={c.E1} {prec}", flush=True)
+        plan = lib.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, c.dgamma, prec)
+        p = torch.zeros_like(ft)
+        mask = torch.zeros(c.N, c.N, dtype=torch.uint8, device="cuda")
+        res = []
+        for s in range(0, len(steps), 40):
+            seg = steps[s:s + 40]
+            r = lib.cb_sweep(plan, ft, seg, p, mask, tol=TOL[prec])
+            res += r
+            S = mask.cpu().numpy().astype(bool)
+            on, pen, off, low = _adhesive_conditions(op, p.cpu().numpy(), S, c.f, seg[-1], sc, prec)
+            print(f"  step {s + len(seg):3d} d={seg[-1]:+.3e} F {r[-1]['F']:+.4e} area {r[-1]['area']:.4f} "
+                  f"gap on S {on:.1e} pen {pen:.1e} p off S {off:.1e} min boundary p/sigma_c {-low:.3f} "
+                  f"{sum(x['ms'] for x in r):.0f} ms", flush=True)
+            tolc = 100 * TOL[prec]
+            assert on < tolc and pen < tolc and off == 0.0 and low <= 1.0 + 1e-9
+        assert all(x["status"] == 0 for x in res)
+        curves[prec] = res
+    F64 = np.array([r["F"] for r in curves["fp64"]])
+    F32 = np.array([r["F"] for r in curves["fp32"]])
+    A64 = np.array([r["area"] for r in curves["fp64"]])
+    A32 = np.array([r["area"] for r in curves["fp32"]])
+    span = np.abs(F64).max()
+    cell = (c.L / c.N) ** 2
+    print(f"  pull-off fp64 {F64.min():+.6e} fp32 {F32.min():+.6e}; max |dF|/span {np.abs(F32 - F64).max() / span:.1e}",
+          flush=True)
+    assert np.abs(F32 - F64).max() <= 1e-3 * span
+    assert np.all(np.abs(A32 - A64) <= 0.01 * np.maximum(A64, 0) + 2 * cell)
+    assert abs(F32.min() - F64.min()) <= 1e-3 * abs(F64.min())
+    # approach: area never shrinks; retraction: area never grows
+    n_app = 80
+    assert np.all(np.diff(A64[:n_app]) >= -1e-15) and np.all(np.diff(A64[n_app:]) <= 1e-15)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 4, 5])
+def test_c2_other_sweeps_fp32(lib, k):
+    """The remaining sweeps of the set, FP32, contact conditions at the
+    end of approach and at the end of retraction."""
+    c = inputs.adhesive_sweep_c2()[k]
+    steps = c.meta["d_steps"]
+    mat = Material(c.h, c.E1, c.nu1, c.E2, c.nu2)
+    op = Operator(c.N, c.L, mat)
+    sc = critical_stress(mat, c.dgamma, c.L / c.N)
+    print(f"C2 sweep h={c.h} E1={c.E1} fp32", flush=True)
+    plan = lib.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, c.dgamma, "fp32")
+    ft = torch.tensor(c.f, dtype=torch.float64, device="cuda")
+    p = torch.zeros_like(ft)
+    mask = torch.zeros(c.N, c.N, dtype=torch.uint8, device="cuda")
+    for seg in (steps[:80], steps[80:]):
+        r = lib.cb_sweep(plan, ft, seg, p, mask, tol=TOL["fp32"])
+        assert all(x["status"] == 0 for x in r)
+        S = mask.cpu().numpy().astype(bool)
+        on, pen, off, low = _adhesive_conditions(op, p.cpu().numpy(), S, c.f, seg[-1], sc, "fp32")
+        A = np.array([x["area"] for x in r])
+        print(f"  d={seg[-1]:+.3e} F {r[-1]['F']:+.4e} min F {min(x['F'] for x in r):+.4e} area {A[-1]:.4f} "
+              f"gap on S {on:.1e} pen {pen:.1e} {sum(x['ms'] for x in r):.0f} ms", flush=True)
+        assert on < 1e-6 and pen < 1e-6 and off == 0.0 and low <= 1.0 + 1e-9
