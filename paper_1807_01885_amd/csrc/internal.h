@@ -30,6 +30,8 @@ struct SolverState {
   double gnorm2;     // preconditioned method: sum over Ic of (g - mean)^2
   double act_scale;  // step scale for activated cells: 1, or for the
                      // preconditioned method (g . M^-1 g) / (g . g)
+  double pscale;     // force control: load rescale of p and u decided at the
+                     // end of an iteration, applied by the next gap kernel
   // skip_u, done, zero are adjacent: a convolution kernel given &skip_u
   // returns if either of the first two is set, given &done if done is set
   int skip_u;        // 1: u was updated linearly, its recomputation is skipped

@@ -111,20 +111,28 @@ __device__ __forceinline__ const double* region(const double* part, int r) { ret
 // S1 = sum g', S2 = sum g'^2, n, A1 = sum (s - f), A2 = sum (s - f)^2;
 // over the rest: max(-g'); and a non-finite flag.
 __global__ void __launch_bounds__(RT)
-k_pk_gap(const double* __restrict__ p, const double* __restrict__ u, const double* __restrict__ f,
+k_pk_gap(double* __restrict__ p, double* __restrict__ u, const double* __restrict__ f,
          double* __restrict__ g, const SolverState* __restrict__ st, const double* __restrict__ gbar2,
          double* part, int n, int par) {
   if (st->done) return;
   const double s = st->force ? gbar2[par] : st->d_in;
+  const double sc = st->pscale;  // pending load rescale of the previous iteration
   double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, 0.0};
   const bool mx[7] = {false, false, false, false, false, true, true};
 #pragma unroll 4
   GRID_LOOP(i, n) {
     const double fi = f[i];
-    const double x = u[i] + fi - s;
+    double ui = u[i], pi = p[i];
+    if (sc != 1.0) {
+      ui *= sc;
+      pi *= sc;
+      u[i] = ui;
+      p[i] = pi;
+    }
+    const double x = ui + fi - s;
     g[i] = x;
     if (!isfinite(x)) v[6] = 1.0;
-    if (p[i] > 0.0) {
+    if (pi > 0.0) {
       const double a = s - fi;
       v[0] += x;
       v[1] += x * x;
@@ -355,20 +363,26 @@ k_pk_update(double* __restrict__ p, double* __restrict__ u, const double* __rest
   write_partials<4>(region(part, R_UPD), v);
 }
 
-// force control: p, u *= F / (dA sum p); block 0 decides whether u must be
-// recomputed from p (a cell changed state, or a refresh is due)
-__global__ void __launch_bounds__(RT)
-k_pk_post(double* __restrict__ p, double* __restrict__ u, SolverState* st, const double* part, int nb, int n,
-          int refresh) {
+// One block: whether u must be recomputed from p (a cell changed state, or
+// a refresh is due), and under force control the rescale F / (dA sum p)
+// of p and u, which the next gap kernel applies as it reads them (u
+// recomputed from the unscaled p scales the same way, K being linear).
+__global__ void __launch_bounds__(RT) k_pk_post(SolverState* st, const double* part, int nb, int refresh) {
   if (st->done) return;
   const bool mx4[4] = {false, false, false, false};
   double a[4];
   fold<4>(region(part, R_UPD), nb, mx4, a);
-  if (blockIdx.x == 0 && threadIdx.x == 0)
+  if (threadIdx.x == 0) {
     st->skip_u = (refresh || a[1] > 0.0 || a[2] > 0.0) ? 0 : 1;
-  if (!st->force || !(a[0] > 0.0)) return;
-  const double sc = st->Ftarget / (st->dA * a[0]);
-#pragma unroll 4
+    st->pscale = (st->force && a[0] > 0.0) ? st->Ftarget / (st->dA * a[0]) : 1.0;
+  }
+}
+
+// the rescale still pending when the iterations stop without converging
+__global__ void __launch_bounds__(RT) k_pk_pending_scale(double* __restrict__ p, double* __restrict__ u,
+                                                         const SolverState* st, int n) {
+  const double sc = st->pscale;
+  if (sc == 1.0) return;
   GRID_LOOP(i, n) {
     p[i] *= sc;
     u[i] *= sc;
@@ -740,8 +754,7 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
     hipLaunchKernelGGL(k_pk_step<TD>, grid, blk, 0, c.st, p, g, t, r, st, part, c.n);
     hipLaunchKernelGGL(k_pk_update<TD>, grid, blk, 0, c.st, p, u, g, t, r, st, part, pc ? P->d_det : nullptr,
                        c.nb, c.n);
-    hipLaunchKernelGGL(k_pk_post, force ? grid : dim3(1), blk, 0, c.st, p, u, st, part, c.nb, c.n,
-                       i == chunk - 1 ? 1 : 0);
+    hipLaunchKernelGGL(k_pk_post, dim3(1), blk, 0, c.st, st, (const double*)part, c.nb, i == chunk - 1 ? 1 : 0);
     if (hipError_t e = apply64(c, p, u, skip_u)) return e;
   }
   return hipGetLastError();
@@ -871,6 +884,7 @@ static SolverState base_state(const cb_plan_s* P, double tol, double d_in, bool 
   s.force = force ? 1 : 0;
   s.d = d_in;
   s.act_scale = 1.0;
+  s.pscale = 1.0;
   return s;
 }
 
@@ -920,6 +934,7 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
   auto enq = [&]() { return pk_enqueue_chunk<TD>(c, p, f, force, pc, op.chunk); };
   if (int rc = run_chunks(P, (force ? 1 : 0) + (pc ? 4 : 0), p, f, nullptr, op.chunk, op.max_iter, enq, &s)) return rc;
   const int status = s.nonfinite ? CB_E_NONFINITE : (s.done ? CB_OK : CB_E_NOCONV);
+  if (!s.done) hipLaunchKernelGGL(k_pk_pending_scale, grid, blk, 0, c.st, p, (double*)P->d_u, P->d_state, c.n);
   hipLaunchKernelGGL(k_stats, grid, blk, 0, c.st, (const double*)p, (const double*)P->d_u,
                      (const unsigned char*)nullptr, P->d_part, c.n);
   hipLaunchKernelGGL(k_fold_misc<4>, dim3(1), blk, 0, c.st, P->d_part, c.nb, 8);
