@@ -110,9 +110,10 @@ __device__ __forceinline__ const double* region(const double* part, int r) { ret
 // gbar[par], the previous mean); partials over Ic = {p > 0}:
 // S1 = sum g', S2 = sum g'^2, n, A1 = sum (s - f), A2 = sum (s - f)^2;
 // over the rest: max(-g'); and a non-finite flag.
+template <typename TD>
 __global__ void __launch_bounds__(RT)
 k_pk_gap(double* __restrict__ p, double* __restrict__ u, const double* __restrict__ f,
-         double* __restrict__ g, const SolverState* __restrict__ st, const double* __restrict__ gbar2,
+         TD* __restrict__ g, const SolverState* __restrict__ st, const double* __restrict__ gbar2,
          double* part, int n, int par) {
   if (st->done) return;
   const double s = st->force ? gbar2[par] : st->d_in;
@@ -130,7 +131,7 @@ k_pk_gap(double* __restrict__ p, double* __restrict__ u, const double* __restric
       p[i] = pi;
     }
     const double x = ui + fi - s;
-    g[i] = x;
+    g[i] = (TD)x;
     if (!isfinite(x)) v[6] = 1.0;
     if (pi > 0.0) {
       const double a = s - fi;
@@ -195,7 +196,7 @@ __device__ __forceinline__ bool record_check(const GapTotals& gt, SolverState* s
 // convergence check, conjugate coefficient, t = Ic ? g + beta t : 0
 template <typename TD>
 __global__ void __launch_bounds__(RT)
-k_pk_dir(const double* __restrict__ p, const double* __restrict__ g, TD* __restrict__ t, SolverState* st,
+k_pk_dir(const double* __restrict__ p, const TD* __restrict__ g, TD* __restrict__ t, SolverState* st,
          double* gbar2, double* part, int nb, int n, int par) {
   if (st->done) return;
   const bool mx7[7] = {false, false, false, false, false, true, true};
@@ -217,13 +218,13 @@ k_pk_dir(const double* __restrict__ p, const double* __restrict__ g, TD* __restr
   }
   const double m = gt.m;
 #pragma unroll 4
-  GRID_LOOP(i, n) t[i] = p[i] > 0.0 ? (TD)((g[i] - m) + beta * (double)t[i]) : TD(0);
+  GRID_LOOP(i, n) t[i] = p[i] > 0.0 ? (TD)(((double)g[i] - m) + beta * (double)t[i]) : TD(0);
 }
 
 // preconditioned: convergence check and gm = Ic ? g : 0
 template <typename TD>
 __global__ void __launch_bounds__(RT)
-k_pk_gmask(const double* __restrict__ p, const double* __restrict__ g, TD* __restrict__ gm, SolverState* st,
+k_pk_gmask(const double* __restrict__ p, const TD* __restrict__ g, TD* __restrict__ gm, SolverState* st,
            double* gbar2, double* part, int nb, int n, int par) {
   if (st->done) return;
   const bool mx7[7] = {false, false, false, false, false, true, true};
@@ -235,13 +236,13 @@ k_pk_gmask(const double* __restrict__ p, const double* __restrict__ g, TD* __res
   if (blockIdx.x == 0 && threadIdx.x == 0) st->gnorm2 = gt.G;
   const double m = gt.m;
 #pragma unroll 4
-  GRID_LOOP(i, n) gm[i] = p[i] > 0.0 ? (TD)(g[i] - m) : TD(0);
+  GRID_LOOP(i, n) gm[i] = p[i] > 0.0 ? (TD)((double)g[i] - m) : TD(0);
 }
 
 // preconditioned: partials over Ic of sum z', sum g z' (z' = M^-1 gm)
 template <typename TD>
 __global__ void __launch_bounds__(RT)
-k_pk_zdot(const double* __restrict__ p, const double* __restrict__ g, const TD* __restrict__ zp,
+k_pk_zdot(const double* __restrict__ p, const TD* __restrict__ g, const TD* __restrict__ zp,
           const SolverState* __restrict__ st, double* part, int n, int par) {
   if (st->done) return;
   const double m = st->gdev;
@@ -252,7 +253,7 @@ k_pk_zdot(const double* __restrict__ p, const double* __restrict__ g, const TD* 
     if (p[i] > 0.0) {
       const double z = (double)zp[i];
       v[0] += z;
-      v[1] += (g[i] - m) * z;
+      v[1] += ((double)g[i] - m) * z;
     }
   }
   block_allreduce<2>(v, mx);
@@ -291,7 +292,7 @@ k_pk_dir_pc(const double* __restrict__ p, const TD* __restrict__ zp, TD* __restr
 // partials over Ic: sum g t, sum r t, sum r, sum t (g = g' - gdev)
 template <typename TD>
 __global__ void __launch_bounds__(RT)
-k_pk_step(const double* __restrict__ p, const double* __restrict__ g, const TD* __restrict__ t,
+k_pk_step(const double* __restrict__ p, const TD* __restrict__ g, const TD* __restrict__ t,
           const TD* __restrict__ r, const SolverState* __restrict__ st, double* part, int n) {
   if (st->done) return;
   const double m = st->gdev;
@@ -301,7 +302,7 @@ k_pk_step(const double* __restrict__ p, const double* __restrict__ g, const TD* 
   GRID_LOOP(i, n) {
     if (p[i] > 0.0) {
       const double ti = (double)t[i], ri = (double)r[i];
-      v[0] += (g[i] - m) * ti;
+      v[0] += ((double)g[i] - m) * ti;
       v[1] += ri * ti;
       v[2] += ri;
       v[3] += ti;
@@ -325,7 +326,7 @@ k_pk_step(const double* __restrict__ p, const double* __restrict__ g, const TD* 
 // bounces at the contact edge otherwise restart nearly every iteration.
 template <typename TD>
 __global__ void __launch_bounds__(RT)
-k_pk_update(double* __restrict__ p, double* __restrict__ u, const double* __restrict__ g,
+k_pk_update(double* __restrict__ p, double* __restrict__ u, const TD* __restrict__ g,
             const TD* __restrict__ t, const TD* __restrict__ r, const SolverState* __restrict__ st, double* part,
             unsigned char* __restrict__ clip, int nb, int n) {
   if (st->done) return;
@@ -348,7 +349,7 @@ k_pk_update(double* __restrict__ p, double* __restrict__ u, const double* __rest
     double pn = pi > 0.0 ? pi : 0.0;
     const bool clipped = on && pn == 0.0;
     if (clipped) v[2] += 1.0;
-    const double gi = g[i] - m;
+    const double gi = (double)g[i] - m;
     if (pn == 0.0 && gi < -theta) {
       pn = -tau * st->act_scale * gi;
       v[1] += 1.0;
@@ -728,7 +729,7 @@ template <typename TD>
 static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, bool force, bool pc, int chunk) {
   cb_plan_s* P = c.P;
   double* u = (double*)P->d_u;
-  double* g = (double*)P->d_g;
+  TD* g = (TD*)P->d_g;  // the gap in the direction type (FP32 plans: FP32)
   TD* t = (TD*)P->d_t;
   TD* r = (TD*)P->d_r;
   TD* gm = (TD*)P->d_pold;
@@ -740,7 +741,7 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
   const int* skip_u = &st->skip_u;    // {skip_u, done}
   for (int i = 0; i < chunk; i++) {
     const int par = i & 1;
-    hipLaunchKernelGGL(k_pk_gap, grid, blk, 0, c.st, p, u, f, g, st, gb, part, c.n, par);
+    hipLaunchKernelGGL(k_pk_gap<TD>, grid, blk, 0, c.st, p, u, f, g, st, gb, part, c.n, par);
     if (pc) {
       hipLaunchKernelGGL(k_pk_gmask<TD>, grid, blk, 0, c.st, p, g, gm, st, gb, part, c.nb, c.n, par);
       // z' = M^-1 gm (into r, free until K t is formed)
