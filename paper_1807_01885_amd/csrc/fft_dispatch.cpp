@@ -80,15 +80,16 @@ static void cache_append(const char* path, const std::string& arch, int N, int p
   if (out) out << arch << ' ' << N << ' ' << prec << ' ' << v << ' ' << us << '\n';
 }
 
-// mean time of one convolution with the plan's current variant, microseconds
-static int time_variant(cb_plan_s* P, hipEvent_t e0, hipEvent_t e1, double* us) {
+// mean time of one convolution of precision prec (0 FP64, 1 FP32) with the
+// plan's current variant for it, microseconds
+static int time_variant(cb_plan_s* P, int prec, hipEvent_t e0, hipEvent_t e1, double* us) {
   constexpr int REPS = 10, REPLAYS = 3;
   hipStream_t st = P->istream;
   hipGraph_t g = nullptr;
   hipGraphExec_t ex = nullptr;
   CB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int r = 0; r < REPS && e == hipSuccess; r++) e = launch_apply(P, P->d_u, P->d_t, st);
+  for (int r = 0; r < REPS && e == hipSuccess; r++) e = launch_apply(P, P->d_u, P->d_t, st, 7, nullptr, nullptr, prec);
   const hipError_t ee = hipStreamEndCapture(st, &g);
   if (e != hipSuccess || ee != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
@@ -110,19 +111,16 @@ static int time_variant(cb_plan_s* P, hipEvent_t e0, hipEvent_t e1, double* us) 
   return CB_OK;
 }
 
-int autotune_fft(cb_plan_s* P, int autotune, const char* cache) {
-  const int prec = P->precision == CB_FP64 ? 0 : 1;
-  if (!autotune && !cache) return CB_OK;
-  hipDeviceProp_t prop;
-  CB_HIP(hipGetDeviceProperties(&prop, P->device));
-  const std::string arch = prop.gcnArchName;
+// variant for one precision: from the cache, else timed (autotune = 1)
+static int tune_one(cb_plan_s* P, int prec, int autotune, const char* cache, const std::string& arch, double* us_out) {
+  *us_out = 0.0;
   if (cache) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     int v = 0;
     double us = 0.0;
     if (cache_lookup(cache, arch, P->N, prec, &v, &us) && fft_variant_fits(v, P->log2n, prec, P->device)) {
       P->variant[prec] = v;
-      P->tune_us = us;
+      *us_out = us;
       return CB_OK;
     }
   }
@@ -141,7 +139,7 @@ int autotune_fft(cb_plan_s* P, int autotune, const char* cache) {
     if (!fft_variant_fits(v, P->log2n, prec, P->device)) continue;
     P->variant[prec] = v;
     double us = 0.0;
-    rc = time_variant(P, e0, e1, &us);
+    rc = time_variant(P, prec, e0, e1, &us);
     if (rc == CB_OK && us < best) {
       best = us;
       bestv = v;
@@ -151,11 +149,27 @@ int autotune_fft(cb_plan_s* P, int autotune, const char* cache) {
   (void)hipEventDestroy(e1);
   P->variant[prec] = bestv;
   if (rc != CB_OK) return rc;
-  P->tune_us = best;
+  *us_out = best;
   if (cache) {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     cache_append(cache, arch, P->N, prec, bestv, best);
   }
+  return CB_OK;
+}
+
+// The plan's precision, and for FP32 plans also the FP64 convolutions that
+// refresh u = K p in the solvers.
+int autotune_fft(cb_plan_s* P, int autotune, const char* cache) {
+  if (!autotune && !cache) return CB_OK;
+  hipDeviceProp_t prop;
+  CB_HIP(hipGetDeviceProperties(&prop, P->device));
+  const std::string arch = prop.gcnArchName;
+  const int prec = P->precision == CB_FP64 ? 0 : 1;
+  double us = 0.0, us64 = 0.0;
+  if (int rc = tune_one(P, prec, autotune, cache, arch, &us)) return rc;
+  P->tune_us = us;
+  if (prec == 1)
+    if (int rc = tune_one(P, 0, autotune, cache, arch, &us64)) return rc;
   return CB_OK;
 }
 

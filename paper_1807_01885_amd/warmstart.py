@@ -102,7 +102,7 @@ def _features(net, ds, idx, x):
 
 
 def evaluate_loss(net, ds, batch):
-    x = torch.empty((batch, G, G, C), dtype=torch.float32, device="cuda")
+    x = torch.empty((batch, net.H, net.W, C), dtype=torch.float32, device="cuda")
     tot, cnt = 0.0, 0
     for s in range(0, len(ds), batch):
         idx = list(range(s, min(s + batch, len(ds))))
@@ -115,12 +115,11 @@ def evaluate_loss(net, ds, batch):
 
 def train(ds, steps=4000, batch=16, lr=2e-3, seed=0, val=None, log=print, log_every=200):
     """Adam with linear warm-up and cosine decay; returns (params, history)."""
-    if ds.N != G:
-        raise ValueError(f"training data must be on the {G} x {G} grid")
-    net = cb.cb_net_create(batch, G, G)
+    g = ds.N  # the network is trained on the grid of its data
+    net = cb.cb_net_create(batch, g, g)
     cb.cb_net_set_params(net, torch.tensor(init_params(seed), device="cuda"))
     rng = np.random.default_rng(seed)
-    x = torch.empty((batch, G, G, C), dtype=torch.float32, device="cuda")
+    x = torch.empty((batch, g, g, C), dtype=torch.float32, device="cuda")
     hist = []
     run = 0.0
     t0 = time.time()
@@ -164,13 +163,14 @@ def load(path=WEIGHTS):
 class WarmStart:
     """Trained network bound to a stream: ws(plan, f, F, p_out) fills p_out."""
 
-    def __init__(self, path=WEIGHTS, cut=None, stream=None, params=None, batch=1):
+    def __init__(self, path=WEIGHTS, cut=None, stream=None, params=None, batch=1, grid=None):
         meta = {}
         if params is None:
             params, meta = load(path)
         self.meta = meta
         self.cut = float(meta.get("cut", 0.1) if cut is None else cut)
-        self.net = cb.cb_net_create(batch, G, G, stream=stream)
+        self.grid = int(meta.get("grid", G) if grid is None else grid)
+        self.net = cb.cb_net_create(batch, self.grid, self.grid, stream=stream)
         cb.cb_net_set_params(self.net, torch.tensor(params, device="cuda"))
 
     def __call__(self, plan, f, F, p_out):
@@ -204,10 +204,10 @@ def compare(ws, problems, tol=TOL, precision="fp32", log=None):
     return rows
 
 
-def _choose_cut(params, problems, cuts, log):
+def _choose_cut(params, grid, problems, cuts, log):
     best = None
     for cut in cuts:
-        rows = compare(WarmStart(cut=cut, params=params), problems)
+        rows = compare(WarmStart(cut=cut, params=params, grid=grid), problems)
         m = float(np.mean([r["warm"] for r in rows]))
         log(f"  cut {cut:g}: mean warm iterations {m:.2f} (cold {np.mean([r['cold'] for r in rows]):.2f})")
         if best is None or m < best[1]:
@@ -226,6 +226,7 @@ def main(argv=None):
     tr.add_argument("--lr", type=float, default=2e-3)
     tr.add_argument("--seed", type=int, default=0)
     tr.add_argument("--out", default=os.path.dirname(WEIGHTS))
+    tr.add_argument("--grid", type=int, default=G, help="network grid = grid of the training solves")
     ev = sub.add_parser("evaluate")
     ev.add_argument("--weights", default=WEIGHTS)
     ev.add_argument("--n", type=int, default=32)
@@ -237,16 +238,16 @@ def main(argv=None):
         print(s, flush=True)
 
     if a.cmd == "train":
-        log(f"generating {a.n_train} training and {a.n_val} validation solves at N={G}")
-        ds = generate(cases(a.n_train, TRAIN_SEED), log=log)
-        val = generate(cases(a.n_val, VAL_SEED), log=log)
+        log(f"generating {a.n_train} training and {a.n_val} validation solves at N={a.grid}")
+        ds = generate(cases(a.n_train, TRAIN_SEED, a.grid), log=log)
+        val = generate(cases(a.n_val, VAL_SEED, a.grid), log=log)
         log(f"training {a.steps} steps, batch {a.batch}")
         params, hist = train(ds, a.steps, a.batch, a.lr, a.seed, val=val, log=log)
-        cut = _choose_cut(params, cases(48, VAL_SEED + 7), (0.03, 0.1, 0.2, 0.35), log)
-        meta = {"grid": G, "cut": cut, "n_train": len(ds), "n_val": len(val), "steps": a.steps,
+        cut = _choose_cut(params, a.grid, cases(48, VAL_SEED + 7, a.grid), (0.03, 0.1, 0.2, 0.35), log)
+        meta = {"grid": a.grid, "cut": cut, "n_train": len(ds), "n_val": len(val), "steps": a.steps,
                 "batch": a.batch, "lr": a.lr, "seed": a.seed, "train_seed": TRAIN_SEED, "val_seed": VAL_SEED,
                 "tol": TOL, "final": hist[-1], "cold_iters_mean": float(np.mean(ds.iters))}
-        path = os.path.join(a.out, os.path.basename(WEIGHTS))
+        path = os.path.join(a.out, f"warmstart_g{a.grid}.npy")
         save(params, path, meta)
         log(f"saved {path} (cut {cut})")
     else:
