@@ -48,7 +48,12 @@ TOL_REF = 1e-10     # FP64 reference for the accuracy checks
 # FFT sources hash to `src` and the plan uses `variant`.
 K2_TRAFFIC = {"kernel": "k2_cols", "N": 1024, "precision": "fp32", "variant": 3,
               "src": "798b3a3f27ebb940:8f9410e6f82dcc1c",
-              "fetch_bytes": 6353.88 * 1024 * 2.0, "write_bytes": 8200.0 * 1024}
+              "fetch_bytes": 6353.88 * 1024 * 2.0, "write_bytes": 8200.0 * 1024,
+              # SQ_INSTS_VALU per launch (same probe, same conditions)
+              "valu_wave_insts": 3923700.0}
+# wave64 VALU instructions the chip issues per second without packed FP32:
+# 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per instruction on a 16-lane SIMD
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
 
 
 def fft_src_hash():
@@ -246,13 +251,17 @@ def main():
     ach = t32k[dom]["GBps"]
     variant = cb.cb_plan_get_info(plans32[0])["fft_variant"]
     traffic = None
+    issue = None
     if (dom == K2_TRAFFIC["kernel"] and N == K2_TRAFFIC["N"] and variant == K2_TRAFFIC["variant"]
             and fft_src_hash() == K2_TRAFFIC["src"]):
         traffic = K2_TRAFFIC["fetch_bytes"] + K2_TRAFFIC["write_bytes"]
+        floor_ms = 1e3 * K2_TRAFFIC["valu_wave_insts"] / VALU_ISSUE_PER_S
+        issue = {"valu_wave_insts": K2_TRAFFIC["valu_wave_insts"], "issue_floor_ms": floor_ms,
+                 "frac_of_valu_issue": floor_ms / t32k[dom]["ms"]}
     roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
             "frac": ach / PEAK_HBM_GBPS, "traffic": traffic,
             "bytes_per_launch": t32k[dom]["bytes"], "mean_launch_ms": t32k[dom]["ms"],
-            "fft_variant": variant}
+            "fft_variant": variant, "valu_issue": issue}
 
     if args.dump:
         rows = []
