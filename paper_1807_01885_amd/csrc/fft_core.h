@@ -128,17 +128,41 @@ __host__ __device__ constexpr int last_radix_from(int L, int E, int Ls0) {
 __host__ __device__ constexpr int last_radix(int L, int E) { return last_radix_from(L, E, 1); }
 
 // Twiddle then DFT of one butterfly of a Stockham pass (stride Ls, radix R,
-// twiddle-table length LT, line length L; j = butterfly index).
+// twiddle-table length LT, line length L; j = butterfly index).  The R - 1
+// twiddles w^i, w = exp(-2 pi i k scale / LT), come from table lookups of
+// w, w^4 and (R = 16) w^8 and products of at most two further factors, so
+// that each is within a few roundings of exact while most lookups (two LDS
+// reads, index arithmetic and a product each) are saved.
 template <typename T, int L, int LT, int R, int Ls, int DIR>
 __device__ __forceinline__ void butterfly(cx<T>* a, int j, const Tw<T, LT>& tw) {
   if constexpr (Ls > 1) {
     const int k = j & (Ls - 1);
     constexpr int scale = LT / (Ls * R);
+    cx<T> w[R];
+    if constexpr (R <= 4) {
+#pragma unroll
+      for (int i = 1; i < R; i++) w[i] = tw.get(i * k * scale);
+    } else {
+      const int e = k * scale;
+      w[1] = tw.get(e);
+      w[4] = tw.get(4 * e);
+      w[2] = cmul(w[1], w[1]);
+      w[3] = cmul(w[2], w[1]);
+#pragma unroll
+      for (int i = 5; i < 8; i++) w[i] = cmul(w[4], w[i - 4]);
+      if constexpr (R == 16) {
+        w[8] = tw.get(8 * e);
+        w[12] = cmul(w[8], w[4]);
+#pragma unroll
+        for (int i = 9; i < 12; i++) w[i] = cmul(w[8], w[i - 8]);
+#pragma unroll
+        for (int i = 13; i < 16; i++) w[i] = cmul(w[12], w[i - 12]);
+      }
+    }
 #pragma unroll
     for (int i = 1; i < R; i++) {
-      cx<T> w = tw.get(i * k * scale);
-      if constexpr (DIR < 0) w.y = -w.y;
-      a[i] = cmul(a[i], w);
+      if constexpr (DIR < 0) w[i].y = -w[i].y;
+      a[i] = cmul(a[i], w[i]);
     }
   }
   dft<T, R, DIR>(a);
