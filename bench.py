@@ -106,6 +106,40 @@ def time_apply(cb, plan, p, u, per_graph=50, replays=10):
     return out
 
 
+def apply_roofline(cb, plan32, plan64, N):
+    """Live timing of cb_apply_K and its kernels (both precisions) and the
+    roofline object of the dominant FP32 kernel."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(0)
+    pr = rng.standard_normal((N, N))
+    timing = {}
+    for prec, plan, s in (("fp32", plan32, 4), ("fp64", plan64, 8)):
+        dt = torch.float32 if prec == "fp32" else torch.float64
+        p = torch.tensor(pr, dtype=dt, device="cuda")
+        u = torch.empty_like(p)
+        ms = time_apply(cb, plan, p, u)
+        ab = alg_bytes(N, s)
+        timing[prec] = {k: {"ms": ms[k], "GBps": ab[k] / (ms[k] * 1e-3) / 1e9, "bytes": ab[k]} for k in ms}
+    t32k = timing["fp32"]
+    dom = max(("k1_rows_fwd", "k2_cols", "k3_rows_inv"), key=lambda k: t32k[k]["ms"])
+    ach = t32k[dom]["GBps"]
+    variant = cb.cb_plan_get_info(plan32)["fft_variant"]
+    traffic = None
+    issue = None
+    if (dom == K2_TRAFFIC["kernel"] and N == K2_TRAFFIC["N"] and variant == K2_TRAFFIC["variant"]
+            and fft_src_hash() == K2_TRAFFIC["src"]):
+        traffic = K2_TRAFFIC["fetch_bytes"] + K2_TRAFFIC["write_bytes"]
+        floor_ms = 1e3 * K2_TRAFFIC["valu_wave_insts"] / VALU_ISSUE_PER_S
+        issue = {"valu_wave_insts": K2_TRAFFIC["valu_wave_insts"], "issue_floor_ms": floor_ms,
+                 "frac_of_valu_issue": floor_ms / t32k[dom]["ms"]}
+    roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBPS, "traffic": traffic,
+            "bytes_per_launch": t32k[dom]["bytes"], "mean_launch_ms": t32k[dom]["ms"],
+            "fft_variant": variant, "valu_issue": issue}
+    return timing, roof
+
+
 def cpu_baseline(case, iters_needed, budget_iters):
     """Oracle FP64 solve of `case` timed for budget_iters iterations, scaled."""
     from oracle import operator as oop
@@ -135,6 +169,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--dump", default=None, help="write per-problem results (JSON) here")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the live apply_K timing and roofline object (for rocprofv3 --kernel-trace --stats)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch K2 (N=1024, FP32, tuned shape) 10 times and a 64 MiB device copy 5 times, "
                          "for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
@@ -170,6 +206,16 @@ def main():
     cases = inputs.headline_set(n=args.n_solves)
     N = cases[0].N
     n = len(cases)
+    if args.roofline_only:
+        c = cases[0]
+        p32, p64 = (cb.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, prec, tune_cache=TUNE_CACHE)
+                    for prec in ("fp32", "fp64"))
+        timing, roof = apply_roofline(cb, p32, p64, N)
+        print(json.dumps({"roofline": roof, "apply_K": {prec: {k: {"ms": round(v["ms"], 5),
+                                                                   "GBps": round(v["GBps"], 1)}
+                                                               for k, v in t.items()}
+                                                        for prec, t in timing.items()}}))
+        return
 
     def make(prec):
         plans = [cb.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, prec, tune_cache=TUNE_CACHE)
@@ -235,33 +281,7 @@ def main():
     acc_l, acc_c, acc_p = accuracy(ps32, res_l), accuracy(pc32, res_c), accuracy(ps64, res_p)
     it = lambda res: float(np.mean([r["iters"] for r in res]))  # noqa: E731
 
-    # ---- apply_K roofline -------------------------------------------------------
-    rng = np.random.default_rng(0)
-    pr = rng.standard_normal((N, N))
-    timing = {}
-    for prec, plans, s in (("fp32", plans32, 4), ("fp64", plans64, 8)):
-        dt = torch.float32 if prec == "fp32" else torch.float64
-        p = torch.tensor(pr, dtype=dt, device="cuda")
-        u = torch.empty_like(p)
-        ms = time_apply(cb, plans[0], p, u)
-        ab = alg_bytes(N, s)
-        timing[prec] = {k: {"ms": ms[k], "GBps": ab[k] / (ms[k] * 1e-3) / 1e9, "bytes": ab[k]} for k in ms}
-    t32k = timing["fp32"]
-    dom = max(("k1_rows_fwd", "k2_cols", "k3_rows_inv"), key=lambda k: t32k[k]["ms"])
-    ach = t32k[dom]["GBps"]
-    variant = cb.cb_plan_get_info(plans32[0])["fft_variant"]
-    traffic = None
-    issue = None
-    if (dom == K2_TRAFFIC["kernel"] and N == K2_TRAFFIC["N"] and variant == K2_TRAFFIC["variant"]
-            and fft_src_hash() == K2_TRAFFIC["src"]):
-        traffic = K2_TRAFFIC["fetch_bytes"] + K2_TRAFFIC["write_bytes"]
-        floor_ms = 1e3 * K2_TRAFFIC["valu_wave_insts"] / VALU_ISSUE_PER_S
-        issue = {"valu_wave_insts": K2_TRAFFIC["valu_wave_insts"], "issue_floor_ms": floor_ms,
-                 "frac_of_valu_issue": floor_ms / t32k[dom]["ms"]}
-    roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-            "frac": ach / PEAK_HBM_GBPS, "traffic": traffic,
-            "bytes_per_launch": t32k[dom]["bytes"], "mean_launch_ms": t32k[dom]["ms"],
-            "fft_variant": variant, "valu_issue": issue}
+    timing, roof = apply_roofline(cb, plans32[0], plans64[0], N)
 
     if args.dump:
         rows = []
