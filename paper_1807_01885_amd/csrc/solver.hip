@@ -105,6 +105,13 @@ __device__ __forceinline__ const double* region(const double* part, int r) { ret
 // Constrained CG (non-adhesive), one iteration =
 //   gap -> dir -> K t -> step -> update -> post [-> K p]
 // (preconditioned: gap -> gmask -> M^-1 gm -> zdot -> dir_pc -> K t -> ...)
+// The contact set Ic = {p > 0} is kept as a byte mask `act`, written by the
+// update, so that only the update reads p.  Under force control the stored
+// p and u lag the true ones by the factor st->pscale decided at the end of
+// the previous iteration: the gap and update kernels apply it as they read
+// (u recomputed from the stored p scales the same way, K being linear), the
+// update writes true values, and the solve applies the last factor at its
+// end.
 // ---------------------------------------------------------------------------
 // stored gap g' = u + f - s (s = d, or under force control the shift
 // gbar[par], the previous mean); partials over Ic = {p > 0}:
@@ -112,28 +119,21 @@ __device__ __forceinline__ const double* region(const double* part, int r) { ret
 // over the rest: max(-g'); and a non-finite flag.
 template <typename TD>
 __global__ void __launch_bounds__(RT)
-k_pk_gap(double* __restrict__ p, double* __restrict__ u, const double* __restrict__ f,
+k_pk_gap(const unsigned char* __restrict__ act, const double* __restrict__ u, const double* __restrict__ f,
          TD* __restrict__ g, const SolverState* __restrict__ st, const double* __restrict__ gbar2,
          double* part, int n, int par) {
   if (st->done) return;
   const double s = st->force ? gbar2[par] : st->d_in;
-  const double sc = st->pscale;  // pending load rescale of the previous iteration
+  const double sc = st->pscale;  // pending load factor of the stored u
   double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, 0.0};
   const bool mx[7] = {false, false, false, false, false, true, true};
 #pragma unroll 4
   GRID_LOOP(i, n) {
     const double fi = f[i];
-    double ui = u[i], pi = p[i];
-    if (sc != 1.0) {
-      ui *= sc;
-      pi *= sc;
-      u[i] = ui;
-      p[i] = pi;
-    }
-    const double x = ui + fi - s;
+    const double x = u[i] * sc + fi - s;
     g[i] = (TD)x;
     if (!isfinite(x)) v[6] = 1.0;
-    if (pi > 0.0) {
+    if (act[i]) {
       const double a = s - fi;
       v[0] += x;
       v[1] += x * x;
@@ -196,7 +196,7 @@ __device__ __forceinline__ bool record_check(const GapTotals& gt, SolverState* s
 // convergence check, conjugate coefficient, t = Ic ? g + beta t : 0
 template <typename TD>
 __global__ void __launch_bounds__(RT)
-k_pk_dir(const double* __restrict__ p, const TD* __restrict__ g, TD* __restrict__ t, SolverState* st,
+k_pk_dir(const unsigned char* __restrict__ act, const TD* __restrict__ g, TD* __restrict__ t, SolverState* st,
          double* gbar2, double* part, int nb, int n, int par) {
   if (st->done) return;
   const bool mx7[7] = {false, false, false, false, false, true, true};
@@ -218,13 +218,13 @@ k_pk_dir(const double* __restrict__ p, const TD* __restrict__ g, TD* __restrict_
   }
   const double m = gt.m;
 #pragma unroll 4
-  GRID_LOOP(i, n) t[i] = p[i] > 0.0 ? (TD)(((double)g[i] - m) + beta * (double)t[i]) : TD(0);
+  GRID_LOOP(i, n) t[i] = act[i] ? (TD)(((double)g[i] - m) + beta * (double)t[i]) : TD(0);
 }
 
 // preconditioned: convergence check and gm = Ic ? g : 0
 template <typename TD>
 __global__ void __launch_bounds__(RT)
-k_pk_gmask(const double* __restrict__ p, const TD* __restrict__ g, TD* __restrict__ gm, SolverState* st,
+k_pk_gmask(const unsigned char* __restrict__ act, const TD* __restrict__ g, TD* __restrict__ gm, SolverState* st,
            double* gbar2, double* part, int nb, int n, int par) {
   if (st->done) return;
   const bool mx7[7] = {false, false, false, false, false, true, true};
@@ -236,13 +236,13 @@ k_pk_gmask(const double* __restrict__ p, const TD* __restrict__ g, TD* __restric
   if (blockIdx.x == 0 && threadIdx.x == 0) st->gnorm2 = gt.G;
   const double m = gt.m;
 #pragma unroll 4
-  GRID_LOOP(i, n) gm[i] = p[i] > 0.0 ? (TD)((double)g[i] - m) : TD(0);
+  GRID_LOOP(i, n) gm[i] = act[i] ? (TD)((double)g[i] - m) : TD(0);
 }
 
 // preconditioned: partials over Ic of sum z', sum g z' (z' = M^-1 gm)
 template <typename TD>
 __global__ void __launch_bounds__(RT)
-k_pk_zdot(const double* __restrict__ p, const TD* __restrict__ g, const TD* __restrict__ zp,
+k_pk_zdot(const unsigned char* __restrict__ act, const TD* __restrict__ g, const TD* __restrict__ zp,
           const SolverState* __restrict__ st, double* part, int n, int par) {
   if (st->done) return;
   const double m = st->gdev;
@@ -250,7 +250,7 @@ k_pk_zdot(const double* __restrict__ p, const TD* __restrict__ g, const TD* __re
   const bool mx[2] = {false, false};
 #pragma unroll 4
   GRID_LOOP(i, n) {
-    if (p[i] > 0.0) {
+    if (act[i]) {
       const double z = (double)zp[i];
       v[0] += z;
       v[1] += ((double)g[i] - m) * z;
@@ -263,7 +263,7 @@ k_pk_zdot(const double* __restrict__ p, const TD* __restrict__ g, const TD* __re
 // preconditioned: t = Ic ? (z' - mean) + beta t : 0, beta = (g.z)/(g.z)_prev
 template <typename TD>
 __global__ void __launch_bounds__(RT)
-k_pk_dir_pc(const double* __restrict__ p, const TD* __restrict__ zp, TD* __restrict__ t,
+k_pk_dir_pc(const unsigned char* __restrict__ act, const TD* __restrict__ zp, TD* __restrict__ t,
             SolverState* __restrict__ st, double* part, int nb, int n, int par) {
   if (st->done) return;
   const bool mx2[2] = {false, false}, mx4[4] = {false, false, false, false};
@@ -286,13 +286,13 @@ k_pk_dir_pc(const double* __restrict__ p, const TD* __restrict__ zp, TD* __restr
     beta = b[1] > 0.0 ? a[1] / b[1] : 0.0;
   }
 #pragma unroll 4
-  GRID_LOOP(i, n) t[i] = p[i] > 0.0 ? (TD)(((double)zp[i] - zbar) + beta * (double)t[i]) : TD(0);
+  GRID_LOOP(i, n) t[i] = act[i] ? (TD)(((double)zp[i] - zbar) + beta * (double)t[i]) : TD(0);
 }
 
 // partials over Ic: sum g t, sum r t, sum r, sum t (g = g' - gdev)
 template <typename TD>
 __global__ void __launch_bounds__(RT)
-k_pk_step(const double* __restrict__ p, const TD* __restrict__ g, const TD* __restrict__ t,
+k_pk_step(const unsigned char* __restrict__ act, const TD* __restrict__ g, const TD* __restrict__ t,
           const TD* __restrict__ r, const SolverState* __restrict__ st, double* part, int n) {
   if (st->done) return;
   const double m = st->gdev;
@@ -300,7 +300,7 @@ k_pk_step(const double* __restrict__ p, const TD* __restrict__ g, const TD* __re
   const bool mx[4] = {false, false, false, false};
 #pragma unroll 4
   GRID_LOOP(i, n) {
-    if (p[i] > 0.0) {
+    if (act[i]) {
       const double ti = (double)t[i], ri = (double)r[i];
       v[0] += ((double)g[i] - m) * ti;
       v[1] += ri * ti;
@@ -328,7 +328,7 @@ template <typename TD>
 __global__ void __launch_bounds__(RT)
 k_pk_update(double* __restrict__ p, double* __restrict__ u, const TD* __restrict__ g,
             const TD* __restrict__ t, const TD* __restrict__ r, const SolverState* __restrict__ st, double* part,
-            unsigned char* __restrict__ clip, int nb, int n) {
+            unsigned char* __restrict__ act, unsigned char* __restrict__ clip, int nb, int n) {
   if (st->done) return;
   const bool mx4[4] = {false, false, false, false};
   double a[4];
@@ -339,11 +339,12 @@ k_pk_update(double* __restrict__ p, double* __restrict__ u, const TD* __restrict
   const double tau = rt > 0.0 ? a[0] / rt : 1.0 / st->k00;
   const double m = st->gdev;
   const double theta = st->theta;
+  const double sc = st->pscale;  // pending load factor of the stored p and u
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const bool mx[4] = {false, false, false, false};
 #pragma unroll 4
   GRID_LOOP(i, n) {
-    double pi = p[i];
+    double pi = p[i] * sc;
     const bool on = pi > 0.0;
     if (on) pi -= tau * (double)t[i];
     double pn = pi > 0.0 ? pi : 0.0;
@@ -357,7 +358,8 @@ k_pk_update(double* __restrict__ p, double* __restrict__ u, const TD* __restrict
     }
     if (clip) clip[i] = clipped ? 1 : 0;
     p[i] = pn;
-    u[i] -= tau * (double)r[i];
+    act[i] = pn > 0.0 ? 1 : 0;
+    u[i] = u[i] * sc - tau * (double)r[i];
     v[0] += pn;
   }
   block_allreduce<4>(v, mx);
@@ -379,7 +381,7 @@ __global__ void __launch_bounds__(RT) k_pk_post(SolverState* st, const double* p
   }
 }
 
-// the rescale still pending when the iterations stop without converging
+// the load factor still pending on the stored p and u when the iterations stop
 __global__ void __launch_bounds__(RT) k_pk_pending_scale(double* __restrict__ p, double* __restrict__ u,
                                                          const SolverState* st, int n) {
   const double sc = st->pscale;
@@ -730,6 +732,7 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
   cb_plan_s* P = c.P;
   double* u = (double*)P->d_u;
   TD* g = (TD*)P->d_g;  // the gap in the direction type (FP32 plans: FP32)
+  unsigned char* act = P->d_mask2;  // contact set {p > 0}
   TD* t = (TD*)P->d_t;
   TD* r = (TD*)P->d_r;
   TD* gm = (TD*)P->d_pold;
@@ -741,20 +744,26 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
   const int* skip_u = &st->skip_u;    // {skip_u, done}
   for (int i = 0; i < chunk; i++) {
     const int par = i & 1;
-    hipLaunchKernelGGL(k_pk_gap<TD>, grid, blk, 0, c.st, p, u, f, g, st, gb, part, c.n, par);
+    hipLaunchKernelGGL(k_pk_gap<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const double*)u, f, g, st, gb,
+                       part, c.n, par);
     if (pc) {
-      hipLaunchKernelGGL(k_pk_gmask<TD>, grid, blk, 0, c.st, p, g, gm, st, gb, part, c.nb, c.n, par);
+      hipLaunchKernelGGL(k_pk_gmask<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)g, gm, st, gb, part,
+                         c.nb, c.n, par);
       // z' = M^-1 gm (into r, free until K t is formed)
       if (hipError_t e = apply_dir(c, gm, r, skip_done, P->d_ptable)) return e;
-      hipLaunchKernelGGL(k_pk_zdot<TD>, grid, blk, 0, c.st, p, g, r, st, part, c.n, par);
-      hipLaunchKernelGGL(k_pk_dir_pc<TD>, grid, blk, 0, c.st, p, r, t, st, part, c.nb, c.n, par);
+      hipLaunchKernelGGL(k_pk_zdot<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)g, (const TD*)r, st,
+                         part, c.n, par);
+      hipLaunchKernelGGL(k_pk_dir_pc<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)r, t, st, part,
+                         c.nb, c.n, par);
     } else {
-      hipLaunchKernelGGL(k_pk_dir<TD>, grid, blk, 0, c.st, p, g, t, st, gb, part, c.nb, c.n, par);
+      hipLaunchKernelGGL(k_pk_dir<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)g, t, st, gb, part,
+                         c.nb, c.n, par);
     }
     if (hipError_t e = apply_dir(c, t, r, skip_done)) return e;
-    hipLaunchKernelGGL(k_pk_step<TD>, grid, blk, 0, c.st, p, g, t, r, st, part, c.n);
-    hipLaunchKernelGGL(k_pk_update<TD>, grid, blk, 0, c.st, p, u, g, t, r, st, part, pc ? P->d_det : nullptr,
-                       c.nb, c.n);
+    hipLaunchKernelGGL(k_pk_step<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)g, (const TD*)t,
+                       (const TD*)r, st, part, c.n);
+    hipLaunchKernelGGL(k_pk_update<TD>, grid, blk, 0, c.st, p, u, (const TD*)g, (const TD*)t, (const TD*)r, st, part,
+                       act, pc ? P->d_det : nullptr, c.nb, c.n);
     hipLaunchKernelGGL(k_pk_post, dim3(1), blk, 0, c.st, st, (const double*)part, c.nb, i == chunk - 1 ? 1 : 0);
     if (hipError_t e = apply64(c, p, u, skip_u)) return e;
   }
@@ -929,13 +938,14 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
   hipLaunchKernelGGL(k_zero_bytes, grid, blk, 0, c.st, P->d_det, c.n);  // clip flags of the preconditioned method
   hipLaunchKernelGGL(k_pk_seed, grid, blk, 0, c.st, (const double*)p, P->d_part, c.n);
   if (force) hipLaunchKernelGGL(k_pk_scale0, grid, blk, 0, c.st, p, P->d_state, P->d_part, c.nb, c.n);
+  hipLaunchKernelGGL(k_mask_from_p, grid, blk, 0, c.st, (const double*)p, P->d_mask2, c.n);
   CB_HIP(apply64(c, p, (double*)P->d_u, nullptr));
   SolverState s;
   const bool pc = op.precond < 0 ? P->precond_auto != 0 : op.precond > 0;
   auto enq = [&]() { return pk_enqueue_chunk<TD>(c, p, f, force, pc, op.chunk); };
   if (int rc = run_chunks(P, (force ? 1 : 0) + (pc ? 4 : 0), p, f, nullptr, op.chunk, op.max_iter, enq, &s)) return rc;
   const int status = s.nonfinite ? CB_E_NONFINITE : (s.done ? CB_OK : CB_E_NOCONV);
-  if (!s.done) hipLaunchKernelGGL(k_pk_pending_scale, grid, blk, 0, c.st, p, (double*)P->d_u, P->d_state, c.n);
+  hipLaunchKernelGGL(k_pk_pending_scale, grid, blk, 0, c.st, p, (double*)P->d_u, P->d_state, c.n);
   hipLaunchKernelGGL(k_stats, grid, blk, 0, c.st, (const double*)p, (const double*)P->d_u,
                      (const unsigned char*)nullptr, P->d_part, c.n);
   hipLaunchKernelGGL(k_fold_misc<4>, dim3(1), blk, 0, c.st, P->d_part, c.nb, 8);
