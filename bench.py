@@ -168,6 +168,7 @@ def main():
     ap.add_argument("--n-solves", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--c4", type=int, default=64, help="problems of the uneven batched recipe leg (0: skip)")
     ap.add_argument("--dump", default=None, help="write per-problem results (JSON) here")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the live apply_K timing and roofline object (for rocprofv3 --kernel-trace --stats)")
@@ -293,6 +294,28 @@ def main():
         with open(args.dump, "w") as fh:
             json.dump(rows, fh, indent=1)
 
+    # ---- the batched recipe: uneven grids, half adhesive (one timed pass) -------
+    c4 = None
+    if args.c4 > 0:
+        cs = inputs.batch_c4(n=args.c4, seed=4)
+        pl4 = [cb.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, c.dgamma, "fp32", tune_cache=TUNE_CACHE)
+               for c in cs]
+        f4 = [torch.tensor(c.f, dtype=torch.float64, device="cuda") for c in cs]
+        p4 = [torch.zeros_like(f) for f in f4]
+        m4 = [1 if c.mode == "force" else 0 for c in cs]
+        t4 = [c.target for c in cs]
+        r4, dt4 = timed(lambda: cb.cb_solve_batch(pl4, f4, t4, m4, p4, tol=TOL, raise_on_error=False), 1, 1)
+        groups = {}
+        for c, r in zip(cs, r4):
+            key = f"N{c.N}_{'adhesive' if c.dgamma > 0 else 'plain'}"
+            groups.setdefault(key, []).append(r["iters"])
+        c4 = {"value": len(cs) / dt4, "unit": "solves/s", "solves": len(cs),
+              "failed": sum(r["status"] != 0 for r in r4),
+              "mean_iters": {k: round(float(np.mean(v)), 1) for k, v in sorted(groups.items())},
+              "how": "batched recipe seed 4 (N in {128,256,512,1024}, half adhesive single solves), FP32 plans, "
+                     "cold start, one cb_solve_batch"}
+        del pl4, f4, p4
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(cases[0], res_p[0]["iters"], args.cpu_iters)
@@ -325,6 +348,7 @@ def main():
         "plain_fp64": {"value": value_p, "unit": "solves/s", "mean_iters": it(res_p), "accuracy": acc_p,
                        "how": "FP64 plans, cold start, one cb_solve_force after another"},
         "speedup_vs_plain_fp64": value / value_p,
+        "batched_recipe": c4,
         "apply_K": {prec: {k: {"ms": round(v["ms"], 5), "GBps": round(v["GBps"], 1)} for k, v in t.items()}
                     for prec, t in timing.items()},
     }
