@@ -177,7 +177,7 @@ def main():
                          "for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(independent solves would shard by problem across GPUs)", file=sys.stderr)
         sys.exit(2)
 

@@ -7,7 +7,7 @@ Paper passages followed
     (Fig. 2), K of size N^2 x N^2.
   * Eq. 2 and Eq. 11 (Sec. 2): K p evaluated as IFFT[ K^ . FFT(p) ].
 
-Reading adopted (listed in the design doc): the pressure grid is zero-padded to
+Reading adopted: the pressure grid is zero-padded to
 M = 2N in both directions so that the periodic convolution of Eq. 11
 equals the non-periodic sum of Eq. 1 over the N x N patch; forward FFT
 unnormalised, inverse 1/M^2 (numpy conventions).

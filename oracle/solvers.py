@@ -19,7 +19,7 @@ Paper passages followed
     and the check repeated until no boundary element exceeds sigma_c;
     then the next displacement step.
 
-Readings adopted where the paper is silent (listed in the design doc):
+Readings adopted where the paper is silent:
   * sign conventions: f >= 0 is the indenter profile, d the rigid
     approach (positive into the body), p > 0 compressive, u the surface
     displacement into the body, F = Delta^2 sum p;

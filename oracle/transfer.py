@@ -11,7 +11,7 @@ Paper passages followed
     summed).
   * Eq. 11 (Sec. 2): k = sqrt(kx^2 + ky^2); no value is defined at k = 0.
 
-Reading adopted where the paper is silent (listed in the design doc):
+Reading adopted where the paper is silent:
   * DC term: chosen so that the discrete frequency sum of the transfer
     function equals its integral over the Brillouin zone
     [-pi/Delta, pi/Delta]^2 (see `dc_bz`).  For the homogeneous case this

@@ -6,7 +6,7 @@ Metrics (both sides on the same seeded inputs):
 Bars: FP64 path 1e-8 / 1e-10 / identical sets (the LCP solution is unique
 and both sides converge to 1e-10); FP32 path (FP32 search-direction
 convolutions, FP64 state and reductions, residual 1e-8) 1e-4 / 1e-5 /
->= 0.999 (the spec bar; observed errors are far smaller).
+>= 0.999 (the accuracy bar of the FP32 path; observed errors are far smaller).
 """
 import math
 
