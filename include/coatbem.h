@@ -100,9 +100,12 @@ typedef struct {
   int precond;       /* non-adhesive solves: -1 (default) automatic, 0 plain
                         conjugate gradients, 1 gradients preconditioned by the
                         Fourier multiplier 1/C(kh) = 2/(E1* k K^(k)), which
-                        removes the layer's stiffness contrast; automatic turns
-                        it on for coatings >= 3x stiffer than the substrate
-                        with h <= L/16.  The converged pressure is the same. */
+                        removes the layer's stiffness contrast, 2 by 1/K^(k),
+                        the inverse of the operator's symbol.  Automatic: 2
+                        from the caller's guess (init = 1); from a cold start
+                        1 for coatings >= 3x stiffer than the substrate with
+                        h <= L/16, else 0.  The converged pressure is the
+                        same; other values: CB_E_INVALID. */
 } cb_solve_opts;
 
 /* Per-solve (or per-step) outcome, filled on the host. */

@@ -85,8 +85,9 @@ struct cb_plan_s {
   // device memory owned by the plan
   void* d_table = nullptr;       // (N+1)^2, 1/M^2 folded, plan type
   void* d_table64 = nullptr;     // FP64 copy for FP32 plans (exact refreshes)
-  void* d_ptable = nullptr;      // preconditioner symbol (N+1)^2, 1/M^2 folded
-  int precond_auto = 0;          // 1: constrained CG preconditioned by default
+  void* d_ptable = nullptr;      // preconditioner symbol 1/C(kh), (N+1)^2, 1/M^2 folded
+  void* d_pinv = nullptr;        // preconditioner symbol 1/K^(k), same layout
+  int precond_auto = 0;          // automatic preconditioner of a cold start: 0 none, 1 layer
   void* d_S = nullptr;           // N x (N+1) complex intermediate
   // solver workspace (plan type unless noted)
   void* d_u = nullptr;

@@ -207,7 +207,7 @@ static void free_plan_memory(cb_plan_s* P) {
   for (auto& e : P->ev_state)
     if (e) (void)hipEventDestroy(e);
   if (P->istream) (void)hipStreamDestroy(P->istream);
-  void* ptrs[] = {P->d_table, P->d_table64, P->d_ptable, P->d_S, P->d_u, P->d_t, P->d_r, P->d_g,
+  void* ptrs[] = {P->d_table, P->d_table64, P->d_ptable, P->d_pinv, P->d_S, P->d_u, P->d_t, P->d_r, P->d_g,
                   P->d_pold, P->d_mask, P->d_mask2, P->d_det, P->d_part, P->d_state};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -274,8 +274,14 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
         pdev[(size_t)a * NC + b] = inv / shape(k * h, cf);
       }
   }
-  // automatic use: a coating at least 3x stiffer than the substrate and
-  // thin relative to the domain
+  // Second symbol: the inverse of the operator itself, 1 / K^(k) (with the
+  // same 1/M^2), which undoes the 1/k decay of the half-space kernel as well
+  // as the layer's stiffness contrast.
+  std::vector<double> qdev((size_t)NC * NC);
+  for (size_t e = 0; e < qdev.size(); e++) qdev[e] = inv / P->table64[e];
+  // automatic choice from a cold start: the layer multiplier for a coating
+  // at least 3x stiffer than the substrate and thin relative to the domain,
+  // else none (from a caller's guess the solver takes the inverse symbol)
   P->precond_auto = (P->E1s >= 3.0 * P->E2s && h <= L / 16.0) ? 1 : 0;
 
   const size_t n2 = (size_t)N * N;
@@ -296,6 +302,7 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
   }
   alloc(&P->d_table, (size_t)NC * NC * es);
   alloc(&P->d_ptable, (size_t)NC * NC * es);
+  alloc(&P->d_pinv, (size_t)NC * NC * es);
   // the intermediate and the solver arrays are sized for FP64 in both
   // precisions: solves keep their state (p, u, f, gap) in FP64 and FP32
   // plans refresh u with an FP64 convolution
@@ -320,12 +327,15 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
     if (P->precision == CB_FP64) {
       e1 = hipMemcpy(P->d_table, tdev.data(), tdev.size() * 8, hipMemcpyHostToDevice);
       e2 = hipMemcpy(P->d_ptable, pdev.data(), pdev.size() * 8, hipMemcpyHostToDevice);
+      if (e2 == hipSuccess) e2 = hipMemcpy(P->d_pinv, qdev.data(), qdev.size() * 8, hipMemcpyHostToDevice);
     } else {
       std::vector<float> tf(tdev.begin(), tdev.end()), pf(pdev.begin(), pdev.end());
       e1 = hipMemcpy(P->d_table, tf.data(), tf.size() * 4, hipMemcpyHostToDevice);
       if (e1 == hipSuccess)
         e1 = hipMemcpy(P->d_table64, tdev.data(), tdev.size() * 8, hipMemcpyHostToDevice);
       e2 = hipMemcpy(P->d_ptable, pf.data(), pf.size() * 4, hipMemcpyHostToDevice);
+      std::vector<float> qf(qdev.begin(), qdev.end());
+      if (e2 == hipSuccess) e2 = hipMemcpy(P->d_pinv, qf.data(), qf.size() * 4, hipMemcpyHostToDevice);
     }
     const hipError_t e3 = hipMemset(P->d_part, 0, part_doubles * sizeof(double));
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
