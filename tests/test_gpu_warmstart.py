@@ -15,11 +15,11 @@ Measured and asserted:
     relative L2 error of the initial pressure <= 0.3 on the native grid
     (<= 0.6 at N = 1024, where the bilinear interpolation of the 256^2
     output blurs the punch edges) against >= 0.9 for the uniform start;
-  - iteration counts are reported; the mean may not exceed the cold mean
-    by more than 5 %.  Constrained CG needs iterations for the error at
-    the contact edge, which a smooth guess does not remove, so the gain in
-    iterations is small (a few % at N = 256) even though the guess halves
-    or better the starting error.
+  - the warm-started solves need far fewer iterations: a caller's guess
+    switches the automatic preconditioner to the inverse of the operator's
+    symbol, which converges fastest once the contact set is nearly right;
+    measured 36.3 -> 18.5 mean iterations at N = 256 and 57.1 -> 14.0 at
+    N = 1024; the bar is 0.8 of the cold mean.
 """
 import numpy as np
 import pytest
@@ -59,4 +59,4 @@ def test_trained_network_on_held_out_problems(lib, N, n, e0_bar):
     print(f"  mean iterations cold {mc:.2f} warm {mw:.2f} (gain {1 - mw / mc:+.1%}); mean p0 error "
           f"net {np.mean(e0_net):.3f} uniform {np.mean(e0_uni):.3f}", flush=True)
     assert np.mean(e0_net) <= e0_bar and np.mean(e0_uni) >= 0.9
-    assert mw <= 1.05 * mc
+    assert mw <= 0.8 * mc
