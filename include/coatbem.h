@@ -104,8 +104,10 @@ typedef struct {
                         the inverse of the operator's symbol.  Automatic: 2
                         from the caller's guess (init = 1); from a cold start
                         1 for coatings >= 3x stiffer than the substrate with
-                        h <= L/16, else 0.  The converged pressure is the
-                        same; other values: CB_E_INVALID. */
+                        h <= L/16, else 0.  Adhesive solves (CG on the
+                        contact set): the same symbols, automatic 2.  The
+                        converged pressure is the same; other values:
+                        CB_E_INVALID. */
 } cb_solve_opts;
 
 /* Per-solve (or per-step) outcome, filled on the host. */

@@ -45,7 +45,7 @@ struct SolverState {
 // Partial-sum regions (doubles) in the plan's reduction buffer: each holds
 // an 8-double header and up to RED_BLOCKS_MAX x 8 block partials.
 enum {
-  R_GAP0 = 0, R_GAP1, R_STEP, R_UPD, R_RR0, R_RR1, R_ZQ, R_INIT, R_MISC, R_PZ0, R_PZ1, R_NUM
+  R_GAP0 = 0, R_GAP1, R_STEP, R_UPD, R_RR0, R_RR1, R_ZQ, R_INIT, R_MISC, R_PZ0, R_PZ1, R_RY0, R_RY1, R_NUM
 };
 constexpr int RED_BLOCKS_MAX = 256;
 constexpr int REG_STRIDE = 8 + 8 * RED_BLOCKS_MAX;
@@ -87,6 +87,7 @@ struct cb_plan_s {
   void* d_table64 = nullptr;     // FP64 copy for FP32 plans (exact refreshes)
   void* d_ptable = nullptr;      // preconditioner symbol 1/C(kh), (N+1)^2, 1/M^2 folded
   void* d_pinv = nullptr;        // preconditioner symbol 1/K^(k), same layout
+  void* d_y = nullptr;           // preconditioned residual of the fixed-set CG (8 B per cell)
   int precond_auto = 0;          // automatic preconditioner of a cold start: 0 none, 1 layer
   void* d_S = nullptr;           // N x (N+1) complex intermediate
   // solver workspace (plan type unless noted)

@@ -207,7 +207,7 @@ static void free_plan_memory(cb_plan_s* P) {
   for (auto& e : P->ev_state)
     if (e) (void)hipEventDestroy(e);
   if (P->istream) (void)hipStreamDestroy(P->istream);
-  void* ptrs[] = {P->d_table, P->d_table64, P->d_ptable, P->d_pinv, P->d_S, P->d_u, P->d_t, P->d_r, P->d_g,
+  void* ptrs[] = {P->d_table, P->d_table64, P->d_ptable, P->d_pinv, P->d_y, P->d_S, P->d_u, P->d_t, P->d_r, P->d_g,
                   P->d_pold, P->d_mask, P->d_mask2, P->d_det, P->d_part, P->d_state};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -312,6 +312,7 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
   alloc(&P->d_r, n2 * 8);
   alloc(&P->d_g, n2 * 8);
   alloc(&P->d_pold, n2 * 8);
+  alloc(&P->d_y, n2 * 8);
   if (P->precision == CB_FP32) alloc(&P->d_table64, (size_t)NC * NC * 8);
   alloc((void**)&P->d_mask, n2);
   alloc((void**)&P->d_mask2, n2);

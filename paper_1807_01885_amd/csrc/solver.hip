@@ -525,6 +525,103 @@ k_mcg_dir(TD* __restrict__ z, const double* __restrict__ r, const unsigned char*
   GRID_LOOP(i, n) z[i] = S[i] ? (TD)(r[i] + beta * (double)z[i]) : TD(0);
 }
 
+// Preconditioned fixed-set CG (z = P_S M^-1 P_S r, M^-1 a Fourier multiplier),
+// one iteration = K z -> zq -> upd_pc -> M^-1 rt -> ry -> dir_pc.
+// start: y = M^-1 r given, rho = r.y over S -> R_RY1, z = S ? y : 0
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_mcg_pc0(const double* __restrict__ r, const TD* __restrict__ y, TD* __restrict__ z,
+          const unsigned char* __restrict__ S, const SolverState* __restrict__ st, double* part, int n) {
+  if (st->done) return;
+  double v[1] = {0.0};
+  const bool mx[1] = {false};
+#pragma unroll 4
+  GRID_LOOP(i, n) {
+    const double yi = (double)y[i];
+    if (S[i]) v[0] += r[i] * yi;
+    z[i] = S[i] ? (TD)yi : TD(0);
+  }
+  block_allreduce<1>(v, mx);
+  write_partials<1>(region(part, R_RY1), v);
+}
+
+// alpha = rho / z.q; x += alpha z, r -= alpha q on S; partials |r|^2 (and a
+// non-finite flag) -> R_RR[par]; rt = S ? r : 0 in the direction type
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_mcg_upd_pc(double* __restrict__ x, double* __restrict__ r, TD* __restrict__ rt, const TD* __restrict__ z,
+             const TD* __restrict__ q, const unsigned char* __restrict__ S, SolverState* st, double* part, int nb,
+             int n, int par) {
+  if (st->done) return;
+  const bool mx1[1] = {false};
+  double zq[1], rho[1];
+  fold<1>(region(part, R_ZQ), nb, mx1, zq);
+  fold<1>(region(part, R_RY0 + (par ^ 1)), nb, mx1, rho);
+  if (!(zq[0] > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) { st->breakdown = 1; st->done = 1; }
+    return;
+  }
+  const double al = rho[0] / zq[0];
+  double v[2] = {0.0, 0.0};
+  const bool mx2[2] = {false, true};
+#pragma unroll 4
+  GRID_LOOP(i, n) {
+    double ri = 0.0;
+    if (S[i]) {
+      x[i] += al * (double)z[i];
+      ri = r[i] - al * (double)q[i];
+      r[i] = ri;
+      v[0] += ri * ri;
+      if (!isfinite(ri)) v[1] = 1.0;
+    }
+    rt[i] = (TD)ri;
+  }
+  block_allreduce<2>(v, mx2);
+  write_partials<2>(region(part, R_RR0 + par), v);
+}
+
+// convergence check on |r|; partials r.y over S -> R_RY[par]
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_mcg_ry(const double* __restrict__ r, const TD* __restrict__ y, const unsigned char* __restrict__ S,
+         SolverState* st, double* part, int nb, int n, int par) {
+  if (st->done) return;
+  const bool mx2[2] = {false, true};
+  double a[2];
+  fold<2>(region(part, R_RR0 + par), nb, mx2, a);
+  const double bn = st->bnorm;
+  const double resid = bn > 0.0 ? sqrt(a[0]) / bn : 0.0;
+  const bool stop = a[1] > 0.0 || resid <= st->tol;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->iters += 1;
+    st->resid = resid;
+    if (a[1] > 0.0) st->nonfinite = 1;
+    if (stop) st->done = 1;
+  }
+  if (stop) return;
+  double v[1] = {0.0};
+  const bool mx[1] = {false};
+#pragma unroll 4
+  GRID_LOOP(i, n) if (S[i]) v[0] += r[i] * (double)y[i];
+  block_allreduce<1>(v, mx);
+  write_partials<1>(region(part, R_RY0 + par), v);
+}
+
+// z = S ? y + beta z : 0, beta = rho_new / rho_old
+template <typename TD>
+__global__ void __launch_bounds__(RT)
+k_mcg_dir_pc(TD* __restrict__ z, const TD* __restrict__ y, const unsigned char* __restrict__ S,
+             const SolverState* __restrict__ st, double* part, int nb, int n, int par) {
+  if (st->done) return;
+  const bool mx1[1] = {false};
+  double a[1], b[1];
+  fold<1>(region(part, R_RY0 + par), nb, mx1, a);
+  fold<1>(region(part, R_RY0 + (par ^ 1)), nb, mx1, b);
+  const double beta = b[0] > 0.0 ? a[0] / b[0] : 0.0;
+#pragma unroll 4
+  GRID_LOOP(i, n) z[i] = S[i] ? (TD)((double)y[i] + beta * (double)z[i]) : TD(0);
+}
+
 // ---------------------------------------------------------------------------
 // small kernels: initial guesses, masks, statistics
 // ---------------------------------------------------------------------------
@@ -776,7 +873,8 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
 }
 
 template <typename TD>
-static hipError_t mcg_enqueue_chunk(const Ctx& c, double* x, const unsigned char* S, int chunk) {
+// pk: 0 plain CG, 1 / 2 preconditioned by 1/C(kh) / 1/K^
+static hipError_t mcg_enqueue_chunk(const Ctx& c, double* x, const unsigned char* S, int chunk, int pk) {
   cb_plan_s* P = c.P;
   double* r = (double*)P->d_g;
   TD* z = (TD*)P->d_t;
@@ -784,6 +882,23 @@ static hipError_t mcg_enqueue_chunk(const Ctx& c, double* x, const unsigned char
   SolverState* st = P->d_state;
   double* part = P->d_part;
   const dim3 grid(c.nb), blk(RT);
+  if (pk > 0) {
+    TD* rt = (TD*)P->d_pold;
+    TD* y = (TD*)P->d_y;
+    const void* ptab = pk == 2 ? P->d_pinv : P->d_ptable;
+    for (int i = 0; i < chunk; i++) {
+      const int par = i & 1;
+      if (hipError_t e = apply_dir(c, z, q, &st->done)) return e;
+      hipLaunchKernelGGL(k_mcg_zq<TD>, grid, blk, 0, c.st, (const TD*)z, (const TD*)q, S, st, part, c.n);
+      hipLaunchKernelGGL(k_mcg_upd_pc<TD>, grid, blk, 0, c.st, x, r, rt, (const TD*)z, (const TD*)q, S, st, part,
+                         c.nb, c.n, par);
+      if (hipError_t e = apply_dir(c, rt, y, &st->done, ptab)) return e;
+      hipLaunchKernelGGL(k_mcg_ry<TD>, grid, blk, 0, c.st, (const double*)r, (const TD*)y, S, st, part, c.nb, c.n,
+                         par);
+      hipLaunchKernelGGL(k_mcg_dir_pc<TD>, grid, blk, 0, c.st, z, (const TD*)y, S, st, part, c.nb, c.n, par);
+    }
+    return hipGetLastError();
+  }
   for (int i = 0; i < chunk; i++) {
     const int par = i & 1;
     if (hipError_t e = apply_dir(c, z, q, &st->done)) return e;
@@ -986,7 +1101,7 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
 // restarts).
 template <typename TD>
 static int set_solve(const Ctx& c, const double* f, double d, const unsigned char* S, double* x, double tol,
-                     int max_iter, int chunk, int& iters, double& resid) {
+                     int max_iter, int chunk, int pk, int& iters, double& resid) {
   cb_plan_s* P = c.P;
   double* u = (double*)P->d_u;
   double* r = (double*)P->d_g;
@@ -1004,8 +1119,13 @@ static int set_solve(const Ctx& c, const double* f, double d, const unsigned cha
     if (s.nonfinite) return CB_E_NONFINITE;
     resid = s.resid;
     if (s.done || attempt == 2 || budget <= 0) return (s.done || attempt == 2) ? CB_OK : CB_E_NOCONV;
-    auto enq = [&]() { return mcg_enqueue_chunk<TD>(c, x, S, chunk); };
-    if (int rc = run_chunks(P, 2, x, S, f, chunk, budget, enq, &s)) return rc;
+    if (pk > 0) {  // y = M^-1 r (z holds r in the direction type), z = y on S
+      CB_HIP(apply_dir(c, z, P->d_y, nullptr, pk == 2 ? P->d_pinv : P->d_ptable));
+      hipLaunchKernelGGL(k_mcg_pc0<TD>, grid, blk, 0, c.st, (const double*)r, (const TD*)P->d_y, z, S, P->d_state,
+                         P->d_part, c.n);
+    }
+    auto enq = [&]() { return mcg_enqueue_chunk<TD>(c, x, S, chunk, pk); };
+    if (int rc = run_chunks(P, 2 + 16 * pk, x, S, f, chunk, budget, enq, &s)) return rc;
     iters += s.iters;
     budget -= s.iters;
     if (s.nonfinite) return CB_E_NONFINITE;
@@ -1031,7 +1151,10 @@ static int adhesive_step(const Ctx& c, const double* f, double d, double* p, uns
   }
   while (rounds < op.max_rounds) {
     rounds++;
-    const int rc = set_solve<TD>(c, f, d, S, p, op.tol, op.max_iter, op.chunk, iters, resid);
+    // fixed-set CG: automatic = preconditioned by the inverse symbol (on a
+    // fixed set it needs 3-7x fewer iterations than plain CG)
+    const int pk = op.precond >= 0 ? op.precond : 2;
+    const int rc = set_solve<TD>(c, f, d, S, p, op.tol, op.max_iter, op.chunk, pk, iters, resid);
     if (rc != CB_OK) { status = rc; break; }
     CB_HIP(apply64(c, p, u, nullptr));
     hipLaunchKernelGGL(k_detach_attach, grid, blk, 0, c.st, f, (const double*)u, p, (const unsigned char*)S, Salt,
@@ -1067,6 +1190,7 @@ static int adhesive_indent(cb_plan_s* P, const double* f, double d, double* p, u
   Ctx c = make_ctx(P);
   const Opts op = fill_opts(P, o);
   *res = cb_result{};
+  if (op.precond < -1 || op.precond > 2) return cb_fail(CB_E_INVALID, "precond must be -1, 0, 1 or 2");
   if (int rc = enter(P)) return rc;
   unsigned char* S = P->d_mask;
   unsigned char* Salt = P->d_mask2;
@@ -1084,6 +1208,7 @@ static int sweep_impl(cb_plan_s* P, const double* f, const double* dsteps, int n
                       unsigned char* mask, const cb_solve_opts* o, cb_result* out) {
   Ctx c = make_ctx(P);
   const Opts op = fill_opts(P, o);
+  if (op.precond < -1 || op.precond > 2) return cb_fail(CB_E_INVALID, "precond must be -1, 0, 1 or 2");
   if (int rc = enter(P)) return rc;
   unsigned char* S = mask;
   unsigned char* Salt = P->d_mask;
