@@ -101,13 +101,15 @@ typedef struct {
                         conjugate gradients, 1 gradients preconditioned by the
                         Fourier multiplier 1/C(kh) = 2/(E1* k K^(k)), which
                         removes the layer's stiffness contrast, 2 by 1/K^(k),
-                        the inverse of the operator's symbol.  Automatic: 2
-                        from the caller's guess (init = 1); from a cold start
+                        the inverse of the operator's symbol, 3 two-phase:
                         1 for coatings >= 3x stiffer than the substrate with
-                        h <= L/16, else 0.  Adhesive solves (CG on the
-                        contact set): the same symbols, automatic 2.  The
-                        converged pressure is the same; other values:
-                        CB_E_INVALID. */
+                        h <= L/16, else 0, until an iteration leaves the
+                        contact set unchanged, then 2.  Automatic: 3, but 2
+                        from a caller's guess (init = 1) unless the coating
+                        is stiff and thin as above.
+                        Adhesive solves (CG on the contact set): 0, 1 or 2,
+                        automatic 2.  The converged pressure is the same;
+                        other values: CB_E_INVALID. */
 } cb_solve_opts;
 
 /* Per-solve (or per-step) outcome, filled on the host. */
@@ -313,7 +315,10 @@ int cb_net_features(cb_net net, const double* f, int Nf, double L, double h,
  * pass, q normalised to unit mean with values below `cut` set to zero,
  * interpolated (bilinear, cell-centred) or averaged onto the plan's
  * N x N grid into p_out (double).  Pass p_out to cb_solve_force with
- * opts.init = 1.  Synchronises the net's stream. */
+ * opts.init = 1.  Plans of coatings >= 3x stiffer than the substrate with
+ * h <= L/16 get the uniform unit pressure instead (the cold start): there
+ * the network's guess measured slower than a cold start.  Synchronises the
+ * net's stream. */
 int cb_net_warmstart(cb_net net, cb_plan plan, const double* f, double F,
                      double cut, double* p_out);
 

@@ -40,6 +40,12 @@ struct SolverState {
   int iters;         // iterations performed
   int nonfinite;     // 1 if a NaN/Inf was met
   int breakdown;     // fixed-set CG: non-positive curvature met
+  int phase;         // two-phase constrained CG: 0 before, 1 after the switch
+                     // to the inverse-symbol preconditioner
+  int quiet;         // consecutive iterations without a change of the contact set
+  int switch_it;     // iteration count at the switch
+  int pskip[4];      // FFT skip pairs of the two direction blocks:
+                     // {phase-0 block idle, 0, phase-1 block idle, 0}
 };
 
 // Partial-sum regions (doubles) in the plan's reduction buffer: each holds

@@ -674,6 +674,11 @@ extern "C" int cb_net_adam_step(cb_net N, float lr) {
   return CB_OK;
 }
 
+__global__ void k_fill1(double* __restrict__ p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 1.0;
+}
+
 // features of one problem into x, its min f kept in scratch[slot]
 static int features_into(cb_net N, const double* f, int Nf, double L, double h, double E1, double nu1, double E2,
                          double nu2, double F, float* x, int slot) {
@@ -717,6 +722,13 @@ extern "C" int cb_net_warmstart_batch(cb_net N, int n, const cb_plan* plans, con
   if (int rc = cb_net_forward(N, n, N->feat, nullptr)) return rc;
   for (int i = 0; i < n; i++) {
     const cb_plan P = plans[i];
+    if (P->precond_auto == 1) {
+      // stiff thin coating: the uniform start (the network's guess measured
+      // slower than a cold start on these)
+      hipLaunchKernelGGL(k_fill1, egrid((long long)P->N * P->N), dim3(256), 0, N->stream, p_out[i],
+                         (long long)P->N * P->N);
+      continue;
+    }
     double* mean = N->scratch + (size_t)(N->batch + i) * RP;
     hipLaunchKernelGGL(k_qmean, dim3(RP), dim3(256), 0, N->stream, N->head + i * hwc, N->H, mean);
     hipLaunchKernelGGL(k_prolong, egrid((long long)P->N * P->N), dim3(256), 0, N->stream, N->head + i * hwc, N->H,

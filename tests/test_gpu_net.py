@@ -192,23 +192,30 @@ def test_features(lib, Nf):
 @pytest.mark.parametrize("N", [512, 256, 128])
 def test_warmstart_prolongation(lib, N):
     """The initial pressure equals the reference network's output carried
-    through the reference interpolation (to the BF16 forward's accuracy)."""
+    through the reference interpolation (to the BF16 forward's accuracy);
+    a stiff thin coating (E1* >= 3 E2*, h <= L/16) gets the uniform unit
+    pressure instead."""
     print(f"warm start N={N}", flush=True)
     L = 1.0
     params = _params(7)
     f = inputs.paraboloid(N, L, 1.0)
-    plan = lib.cb_plan_create(N, L, 0.02, 10.0, 0.3, 1.0, 0.3, 0.0, "fp32")
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
     net = _net(lib, params, 1, 256, 256)
     F = 1.5e-3
+    h = 0.1   # thicker than L/16: the network's guess is used
+    plan = lib.cb_plan_create(N, L, h, 10.0, 0.3, 1.0, 0.3, 0.0, "fp32")
     p = torch.empty((N, N), dtype=torch.float64, device="cuda")
-    lib.cb_net_warmstart(net, plan, torch.tensor(f, dtype=torch.float64, device="cuda"), F, p, cut=0.0)
-    x = nr.features(f, 256, L, 0.02, 10.0, 0.3, 1.0, 0.3, F)
+    lib.cb_net_warmstart(net, plan, ft, F, p, cut=0.0)
+    x = nr.features(f, 256, L, h, 10.0, 0.3, 1.0, 0.3, F)
     ref = nr.prolong(nr.forward(params, x[None])[0], N)
     e = _rel(p.cpu().numpy(), ref)
     print(f"  p0 rel {e:.2e}", flush=True)
     assert e < 2e-2
-    lib.cb_net_warmstart(net, plan, torch.tensor(f, dtype=torch.float64, device="cuda"), F, p, cut=1e30)
+    lib.cb_net_warmstart(net, plan, ft, F, p, cut=1e30)
     assert torch.count_nonzero(p).item() == 0
+    thin = lib.cb_plan_create(N, L, 0.02, 10.0, 0.3, 1.0, 0.3, 0.0, "fp32")
+    lib.cb_net_warmstart(net, thin, ft, F, p, cut=0.0)
+    assert torch.all(p == 1.0).item()
 
 
 def test_net_errors(lib):

@@ -2,7 +2,10 @@
 where the layer-removing Fourier preconditioner is used) against the FP64
 oracle's plain constrained CG.  The converged pressure is the unique
 solution of the complementarity problem, so both must agree to the
-solve tolerance; the preconditioned path must also need fewer iterations."""
+solve tolerance; the preconditioned path must also need fewer iterations.
+precond = 3 (the automatic choice of a cold start) runs the plain or
+layer-preconditioned iteration until the contact set has not changed for
+three iterations, then switches to the inverse of the operator's symbol."""
 import numpy as np
 import pytest
 import torch
@@ -33,7 +36,7 @@ def test_preconditioned_force_solve(lib, prec, shape, mat, F):
     ft = torch.tensor(f, dtype=torch.float64, device="cuda")
     tol = 1e-10 if prec == "fp64" else 1e-8
     out = {}
-    for pc in (1, 0, -1):
+    for pc in (1, 0, 3, -1):
         p = torch.zeros_like(ft)
         res = lib.cb_solve_force(plan, ft, F, p, tol=tol, precond=pc)
         e_p = np.linalg.norm(p.double().cpu().numpy() - ref.p) / np.linalg.norm(ref.p)
@@ -43,11 +46,11 @@ def test_preconditioned_force_solve(lib, prec, shape, mat, F):
         assert e_p < (1e-7 if prec == "fp64" else 2e-4)
         assert abs(res["F"] - F) / F < (1e-12 if prec == "fp64" else 1e-6)
     assert out[1][0] < out[0][0]          # fewer iterations with the preconditioner
-    assert out[-1][0] == out[1][0]        # automatic choice turns it on here
+    assert out[-1][0] == out[3][0]        # automatic choice: two-phase
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("pc", [1, 0])
+@pytest.mark.parametrize("pc", [1, 0, 3])
 def test_initial_guess_with_too_small_contact(lib, prec, pc):
     """An initial guess whose support is smaller than the contact (the
     oracle's pressure with its low-pressure rim removed) makes the solver
@@ -88,7 +91,7 @@ def test_inverse_symbol_preconditioner(lib, prec, shape, mat, F):
     """precond = 2 (the inverse of the operator's symbol, the automatic
     choice from a caller's guess): same pressure as the oracle's plain
     method, fewer iterations than the plain GPU method; a cold start on
-    these coatings defaults to the plain method."""
+    these coatings starts with the plain method (two-phase)."""
     print(f"inverse precond {shape} {prec}", flush=True)
     N, L = 128, 1.0
     f = {"paraboloid": inputs.paraboloid(N, L, 1.0), "flat": inputs.flat_punch(N, L, 0.11),
@@ -98,7 +101,7 @@ def test_inverse_symbol_preconditioner(lib, prec, shape, mat, F):
     ft = torch.tensor(f, dtype=torch.float64, device="cuda")
     tol = 1e-10 if prec == "fp64" else 1e-8
     it = {}
-    for pc in (2, 0, -1):
+    for pc in (2, 0, 3, -1):
         p = torch.zeros_like(ft)
         res = lib.cb_solve_force(plan, ft, F, p, tol=tol, precond=pc)
         e_p = np.linalg.norm(p.cpu().numpy() - ref.p) / np.linalg.norm(ref.p)
@@ -106,6 +109,6 @@ def test_inverse_symbol_preconditioner(lib, prec, shape, mat, F):
         assert res["status"] == 0
         assert e_p < (1e-7 if prec == "fp64" else 2e-4)
         it[pc] = res["iters"]
-    assert it[2] < it[0] and it[-1] == it[0]
+    assert it[2] < it[0] and it[-1] == it[3]
     with pytest.raises(lib.CoatbemError):
-        lib.cb_solve_force(plan, ft, F, torch.zeros_like(ft), precond=3)
+        lib.cb_solve_force(plan, ft, F, torch.zeros_like(ft), precond=4)
