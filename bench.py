@@ -175,6 +175,9 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch K2 (N=1024, FP32, tuned shape) 10 times and a 64 MiB device copy 5 times, "
                          "for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
+    ap.add_argument("--profile-solves", action="store_true",
+                    help="only the FP32 solves of the set, cold then from the learned guess, one after another "
+                         "on one host thread (for rocprofv3 --kernel-trace --stats)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -207,6 +210,21 @@ def main():
     cases = inputs.headline_set(n=args.n_solves)
     N = cases[0].N
     n = len(cases)
+    if args.profile_solves:
+        ws = WarmStart()
+        its = []
+        for c in cases:
+            plan = cb.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, "fp32", tune_cache=TUNE_CACHE)
+            f = torch.tensor(c.f, dtype=torch.float64, device="cuda")
+            p = torch.zeros(c.N, c.N, dtype=torch.float64, device="cuda")
+            cold = cb.cb_solve_force(plan, f, c.target, p, tol=TOL)["iters"]
+            ws(plan, f, c.target, p)
+            warm = cb.cb_solve_force(plan, f, c.target, p, tol=TOL, init=1)["iters"]
+            its.append((cold, warm))
+            print(f"solve {len(its)}/{n}: iterations cold {cold} warm {warm}", flush=True)
+        print(json.dumps({"profile_solves": "done", "mean_iters_cold": float(np.mean([a for a, _ in its])),
+                          "mean_iters_warm": float(np.mean([b for _, b in its]))}))
+        return
     if args.roofline_only:
         c = cases[0]
         p32, p64 = (cb.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, prec, tune_cache=TUNE_CACHE)
