@@ -200,6 +200,18 @@ int cb_apply_K(cb_plan plan, const void* p, void* u);
 int cb_apply_K_stages(cb_plan plan, const void* p, void* u, int stage_mask);
 
 /*
+ * cb_apply_precond -- y = M^-1 x, the solver's Fourier preconditioner (not
+ *   part of the paper): the N-periodic convolution (real 2-D FFT of length
+ *   N per axis, no zero padding) with the symbol s(k), k = (2 pi / L) |(a, b)|:
+ *   which = 1: s = 1 / C(k h), C = E1* k K^(k) / 2 (the layer's stiffness
+ *   contrast removed); which = 2: s = 1 / K^(k) (the operator's inverse
+ *   symbol; at k = 0 the inverse of the padded table's DC value).  x, y:
+ *   device N*N of the plan type; y must not alias x.  Asynchronous on the
+ *   plan stream.  Other `which`: CB_E_INVALID.
+ */
+int cb_apply_precond(cb_plan plan, int which, const void* x, void* y);
+
+/*
  * cb_solve_indent -- non-adhesive (dgamma = 0) or adhesive (dgamma > 0)
  *   contact at prescribed rigid approach d.
  *   Non-adhesive: the complementarity problem p >= 0, g >= 0, p g = 0 by

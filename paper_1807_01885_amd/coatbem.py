@@ -91,6 +91,7 @@ _SIGS = {
     "cb_transfer_table": (_i, [_i, _d, _d, _d, _d, _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "cb_apply_K": (_i, [_vp, _vp, _vp]),
     "cb_apply_K_stages": (_i, [_vp, _vp, _vp, _i]),
+    "cb_apply_precond": (_i, [_vp, _i, _vp, _vp]),
     "cb_solve_indent": (_i, [_vp, _vp, _d, _vp, _vp, ctypes.POINTER(cb_solve_opts),
                              ctypes.POINTER(cb_result)]),
     "cb_solve_force": (_i, [_vp, _vp, _d, _vp, _vp, ctypes.POINTER(cb_solve_opts),
@@ -233,6 +234,11 @@ def _opts(tol=0.0, max_iter=0, chunk=0, init=0, attach_tol=-1.0, max_rounds=0, p
 def cb_apply_K(plan: Plan, p, u):
     _check(_lib.cb_apply_K(plan.handle, _arr(plan, p, "p"), _arr(plan, u, "u")))
     return u
+
+
+def cb_apply_precond(plan: Plan, which, x, y):
+    _check(_lib.cb_apply_precond(plan.handle, int(which), _arr(plan, x, "x"), _arr(plan, y, "y")))
+    return y
 
 
 def cb_apply_K_stages(plan: Plan, p, u, stage_mask):

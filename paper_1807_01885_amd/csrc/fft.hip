@@ -12,6 +12,10 @@
 //   K3  rows, inverse real FFT (Hermitian half spectrum -> first N of M
 //       real outputs).
 //
+// The same three kernels with PAD = false give the N-periodic convolution
+// (real transforms of length N, no zero padding, N/2 + 1 half-spectrum
+// columns): the solver's Fourier preconditioners are applied that way.
+//
 // Intermediate layout ("row tiles"): S[rb][kx][rr], rb = row / RB,
 // rr = row % RB, kx in [0, N], complex.  K1/K3 read and write whole tiles
 // (contiguous), K2 reads RB-element segments of a column.
@@ -41,13 +45,14 @@ constexpr int PS = 4;  // LDS padding shift
 // ---------------------------------------------------------------------------
 // K1: forward row transform
 // ---------------------------------------------------------------------------
-template <typename T, int LOG2N, int RB, int NT1, int G>
+template <typename T, int LOG2N, bool PAD, int RB, int NT1, int G>
 __global__ void __launch_bounds__(G * RB * NT1)
 k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restrict__ tw_g,
            const int* __restrict__ skip) {
   if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
-  constexpr int N = 1 << LOG2N, M = 2 * N, L = N, NC = N + 1;
+  // real transform length M, packed complex line L = M / 2
+  constexpr int N = 1 << LOG2N, M = PAD ? 2 * N : N, L = M / 2, NC = L + 1;
   constexpr int ROWS = G * RB, NTH = ROWS * NT1, E = L / NT1;
   constexpr int LP = padded<PS>(L);
   using TW = Tw<T, M>;
@@ -60,8 +65,9 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
   const int row0 = blockIdx.x * ROWS;
   C* line = buf + lrow * LP;
 
-  // first pass (Ls = 1): packed inputs z[n], n < N/2, from global; the
-  // loads are issued before the twiddle tables are built
+  // first pass (Ls = 1): packed inputs z[n], n < N/2, from global (with
+  // padding the upper half of the line is zero); the loads are issued
+  // before the twiddle tables are built
   {
     constexpr int R = pick_radix(L, E, 1);
     constexpr int NB = L / (R * NT1);
@@ -71,7 +77,7 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
     for (int b = 0; b < NB; b++) {
       const int j = t + b * NT1;
 #pragma unroll
-      for (int i = 0; i < R; i++) a[b][i] = (i < R / 2) ? z[j + i * (L / R)] : C{T(0), T(0)};
+      for (int i = 0; i < R; i++) a[b][i] = (!PAD || i < R / 2) ? z[j + i * (L / R)] : C{T(0), T(0)};
     }
     TW::compute(tws, tid, NTH);
 #pragma unroll
@@ -87,8 +93,8 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
   MidPasses<T, L, M, NT1, 1, PS, pick_radix(L, E, 1), L>::run(line, t, tw);
 
   // split into the half spectrum of the length-M real transform:
-  // X[k] = (Z[k] + conj Z[N-k])/2 - i/2 W^k (Z[k] - conj Z[N-k]),
-  // W = exp(-2 pi i / M), k in [0, N]; items in tile order (k major, rr minor)
+  // X[k] = (Z[k] + conj Z[L-k])/2 - i/2 W^k (Z[k] - conj Z[L-k]),
+  // W = exp(-2 pi i / M), k in [0, L]; items in tile order (k major, rr minor)
   constexpr int ITEMS = G * NC * RB;
   C* out = S + (size_t)blockIdx.x * ITEMS;
 #pragma unroll
@@ -100,8 +106,8 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
       const int k = qq / RB;
       const int rr = qq - k * RB;
       const C* ln = buf + (g * RB + rr) * LP;
-      const C zk = ln[padi<PS>(k & (N - 1))];
-      const C zn = cconj(ln[padi<PS>((N - k) & (N - 1))]);
+      const C zk = ln[padi<PS>(k & (L - 1))];
+      const C zn = cconj(ln[padi<PS>((L - k) & (L - 1))]);
       const C e = cscale(cadd(zk, zn), T(0.5));
       const C o = cscale(csub(zk, zn), T(0.5));  // times -i below
       const C w = tw.get(k);
@@ -114,13 +120,13 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
 // ---------------------------------------------------------------------------
 // K2: column transform, transfer multiply, inverse column transform
 // ---------------------------------------------------------------------------
-template <typename T, int LOG2N, int RB, int NT2, int CB>
+template <typename T, int LOG2N, bool PAD, int RB, int NT2, int CB>
 __global__ void __launch_bounds__(CB * NT2)
 k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict__ tw_g,
        const int* __restrict__ skip) {
   if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
-  constexpr int N = 1 << LOG2N, M = 2 * N, L = M, NC = N + 1;
+  constexpr int N = 1 << LOG2N, M = PAD ? 2 * N : N, L = M, NC = M / 2 + 1;
   constexpr int NTH = CB * NT2, E = L / NT2;
   constexpr int LP = padded<PS>(L);
   constexpr int NBLK = (NC + CB - 1) / CB;
@@ -149,7 +155,7 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
 #pragma unroll
       for (int i = 0; i < R0; i++) {
         const int n = j + i * (L / R0);
-        a[b][i] = (i < R0 / 2 && active)
+        a[b][i] = ((!PAD || i < R0 / 2) && active)
                       ? S[(size_t)(n / RB) * (NC * RB) + kx * RB + (n % RB)]
                       : C{T(0), T(0)};
       }
@@ -184,7 +190,7 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
 #pragma unroll
       for (int i = 0; i < RL; i++) {
         const int ky = j + i * (L / RL);
-        const int kq = ky <= N ? ky : M - ky;
+        const int kq = ky <= M / 2 ? ky : M - ky;
         a[b][i] = cscale(a[b][i], trow[kq]);
       }
       dft<T, RL, -1>(a[b]);
@@ -212,7 +218,7 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
       butterfly<T, L, M, RIL, L / RIL, -1>(a[b], j, tw);
       if (active) {
 #pragma unroll
-        for (int i = 0; i < RIL / 2; i++) {
+        for (int i = 0; i < (PAD ? RIL / 2 : RIL); i++) {
           const int n = j + i * (L / RIL);  // < N
           S[(size_t)(n / RB) * (NC * RB) + kx * RB + (n % RB)] = a[b][i];
         }
@@ -224,13 +230,13 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
 // ---------------------------------------------------------------------------
 // K3: inverse row transform (half spectrum -> first N real outputs)
 // ---------------------------------------------------------------------------
-template <typename T, int LOG2N, int RB, int NT1, int G>
+template <typename T, int LOG2N, bool PAD, int RB, int NT1, int G>
 __global__ void __launch_bounds__(G * RB * NT1)
 k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restrict__ tw_g,
            const int* __restrict__ skip) {
   if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
-  constexpr int N = 1 << LOG2N, M = 2 * N, L = N, NC = N + 1;
+  constexpr int N = 1 << LOG2N, M = PAD ? 2 * N : N, L = M / 2, NC = L + 1;
   constexpr int ROWS = G * RB, NTH = ROWS * NT1, E = L / NT1;
   constexpr int LP = padded<PS>(L + 1);
   using TW = Tw<T, M>;
@@ -264,8 +270,8 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
     }
   }
   __syncthreads();
-  // Z[k] = (X[k] + conj X[N-k]) + i W^-k (X[k] - conj X[N-k]), pairs (k, N-k)
-  constexpr int PAIRS = N / 2 + 1;
+  // Z[k] = (X[k] + conj X[L-k]) + i W^-k (X[k] - conj X[L-k]), pairs (k, L-k)
+  constexpr int PAIRS = L / 2 + 1;
 #pragma unroll
   for (int it = 0; it < (ROWS * PAIRS + NTH - 1) / NTH; it++) {
     const int q = tid + it * NTH;
@@ -274,18 +280,18 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
     const int k = q - lr * PAIRS;
     C* ln = buf + lr * LP;
     const C xk = ln[padi<PS>(k)];
-    const C xn = ln[padi<PS>(N - k)];
+    const C xn = ln[padi<PS>(L - k)];
     {
       const C s = cadd(xk, cconj(xn));
       const C dd = csub(xk, cconj(xn));
       const C w = cconj(tw.get(k));
       ln[padi<PS>(k)] = cadd(s, mul_mi<-1>(cmul(w, dd)));
     }
-    if (k != 0 && k != N / 2) {
+    if (k != 0 && k != L / 2) {
       const C s = cadd(xn, cconj(xk));
       const C dd = csub(xn, cconj(xk));
-      const C w = cconj(tw.get(N - k));
-      ln[padi<PS>(N - k)] = cadd(s, mul_mi<-1>(cmul(w, dd)));
+      const C w = cconj(tw.get(L - k));
+      ln[padi<PS>(L - k)] = cadd(s, mul_mi<-1>(cmul(w, dd)));
     }
   }
   __syncthreads();
@@ -308,7 +314,7 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
       const int j = t + b * NT1;
       butterfly<T, L, M, RL, L / RL, -1>(a[b], j, tw);
 #pragma unroll
-      for (int i = 0; i < RL / 2; i++) zo[j + i * (L / RL)] = a[b][i];
+      for (int i = 0; i < (PAD ? RL / 2 : RL); i++) zo[j + i * (L / RL)] = a[b][i];
     }
   }
 }
@@ -316,41 +322,44 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
 // ---------------------------------------------------------------------------
 // launch shapes and dispatch
 // ---------------------------------------------------------------------------
-template <int LOG2N> struct Shape {
-  static constexpr int N = 1 << LOG2N, M = 2 * N;
-  static constexpr int E1 = N < VE1 ? N : VE1;
-  static constexpr int NT1 = N / E1;
-  static constexpr int E2 = VE2;
+// PAD: the 2N-padded convolution of the operator; else the N-periodic one
+template <int LOG2N, bool PAD = true> struct Shape {
+  static constexpr int N = 1 << LOG2N, M = PAD ? 2 * N : N, L1 = M / 2;
+  static constexpr int E1 = L1 < VE1 ? L1 : VE1;
+  static constexpr int NT1 = L1 / E1;
+  // the column kernel takes at least two passes (first and last differ)
+  static constexpr int E2 = (PAD || VE2 <= M / 2) ? VE2 : M / 2;
   static constexpr int NT2 = M / E2;
   static constexpr int CB = NT2 >= 64 ? 1 : 64 / NT2;
 };
 
 template <typename T> constexpr int row_tile() { return (sizeof(T) == 4 ? 4 : 2) * VRBM; }
 
-template <typename T, int LOG2N>
+template <typename T, int LOG2N, bool PAD = true>
 static size_t lds_rows(int G) {
-  constexpr int N = 1 << LOG2N, M = 2 * N;
-  using TW = Tw<T, M>;
-  return sizeof(cx<T>) * (TW::NLO + TW::NHI + (size_t)G * row_tile<T>() * padded<PS>(N + 1));
+  using SH = Shape<LOG2N, PAD>;
+  using TW = Tw<T, SH::M>;
+  return sizeof(cx<T>) * (TW::NLO + TW::NHI + (size_t)G * row_tile<T>() * padded<PS>(SH::L1 + 1));
 }
-template <typename T, int LOG2N>
+template <typename T, int LOG2N, bool PAD = true>
 static size_t lds_cols(int CB) {
-  constexpr int N = 1 << LOG2N, M = 2 * N;
-  using TW = Tw<T, M>;
-  return sizeof(cx<T>) * (TW::NLO + TW::NHI + (size_t)CB * padded<PS>(M));
+  using SH = Shape<LOG2N, PAD>;
+  using TW = Tw<T, SH::M>;
+  return sizeof(cx<T>) * (TW::NLO + TW::NHI + (size_t)CB * padded<PS>(SH::M));
 }
 
 // row tiles per block of K1/K3: at least one wave of threads
-template <typename T, int LOG2N>
+template <typename T, int LOG2N, bool PAD = true>
 constexpr int tiles_per_block() {
-  using SH = Shape<LOG2N>;
+  using SH = Shape<LOG2N, PAD>;
   constexpr int RB = row_tile<T>();
   constexpr int G0 = (SH::NT1 * RB >= 64) ? 1 : 64 / (SH::NT1 * RB);
   return G0 > SH::N / RB ? SH::N / RB : G0;
 }
 
 // LDS bytes per block of the larger kernel; 0 if a block would exceed the
-// 1024-thread limit (the shape is then not launchable at this size)
+// 1024-thread limit (the shape is then not launchable at this size).  The
+// periodic kernels of a size need no more threads or LDS than the padded.
 template <typename T, int LOG2N>
 static size_t lds_need() {
   using SH = Shape<LOG2N>;
@@ -360,17 +369,17 @@ static size_t lds_need() {
   return a > b ? a : b;
 }
 
-template <typename T, int LOG2N>
+template <typename T, int LOG2N, bool PAD>
 static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T>* S, const T* Tq, const cx<T>* tw,
                              hipStream_t st) {
-  using SH = Shape<LOG2N>;
+  using SH = Shape<LOG2N, PAD>;
   constexpr int N = SH::N, RB = row_tile<T>();
-  constexpr int G = tiles_per_block<T, LOG2N>();
-  constexpr int NC = N + 1;
-  const size_t lr = lds_rows<T, LOG2N>(G), lc = lds_cols<T, LOG2N>(SH::CB);
-  auto k1 = k_rows_fwd<T, LOG2N, RB, SH::NT1, G>;
-  auto k2 = k_cols<T, LOG2N, RB, SH::NT2, SH::CB>;
-  auto k3 = k_rows_inv<T, LOG2N, RB, SH::NT1, G>;
+  constexpr int G = tiles_per_block<T, LOG2N, PAD>();
+  constexpr int NC = SH::M / 2 + 1;
+  const size_t lr = lds_rows<T, LOG2N, PAD>(G), lc = lds_cols<T, LOG2N, PAD>(SH::CB);
+  auto k1 = k_rows_fwd<T, LOG2N, PAD, RB, SH::NT1, G>;
+  auto k2 = k_cols<T, LOG2N, PAD, RB, SH::NT2, SH::CB>;
+  auto k3 = k_rows_inv<T, LOG2N, PAD, RB, SH::NT1, G>;
   static bool attr = false;
   if (!attr) {
     hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
@@ -386,20 +395,27 @@ static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool PAD>
 static hipError_t apply_dispatch(int stages, const int* skip, int log2n, const T* p, T* u, cx<T>* S, const T* Tq,
                                  const cx<T>* tw, hipStream_t st) {
   switch (log2n) {
-    case 4: return apply_impl<T, 4>(stages, skip, p, u, S, Tq, tw, st);
-    case 5: return apply_impl<T, 5>(stages, skip, p, u, S, Tq, tw, st);
-    case 6: return apply_impl<T, 6>(stages, skip, p, u, S, Tq, tw, st);
-    case 7: return apply_impl<T, 7>(stages, skip, p, u, S, Tq, tw, st);
-    case 8: return apply_impl<T, 8>(stages, skip, p, u, S, Tq, tw, st);
-    case 9: return apply_impl<T, 9>(stages, skip, p, u, S, Tq, tw, st);
-    case 10: return apply_impl<T, 10>(stages, skip, p, u, S, Tq, tw, st);
-    case 11: return apply_impl<T, 11>(stages, skip, p, u, S, Tq, tw, st);
+    case 4: return apply_impl<T, 4, PAD>(stages, skip, p, u, S, Tq, tw, st);
+    case 5: return apply_impl<T, 5, PAD>(stages, skip, p, u, S, Tq, tw, st);
+    case 6: return apply_impl<T, 6, PAD>(stages, skip, p, u, S, Tq, tw, st);
+    case 7: return apply_impl<T, 7, PAD>(stages, skip, p, u, S, Tq, tw, st);
+    case 8: return apply_impl<T, 8, PAD>(stages, skip, p, u, S, Tq, tw, st);
+    case 9: return apply_impl<T, 9, PAD>(stages, skip, p, u, S, Tq, tw, st);
+    case 10: return apply_impl<T, 10, PAD>(stages, skip, p, u, S, Tq, tw, st);
+    case 11: return apply_impl<T, 11, PAD>(stages, skip, p, u, S, Tq, tw, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename T>
+static hipError_t apply_any(bool periodic, int stages, const int* skip, int log2n, const T* p, T* u, cx<T>* S,
+                            const T* Tq, hipStream_t st) {
+  return periodic ? apply_dispatch<T, false>(stages, skip, log2n, p, u, S, Tq, nullptr, st)
+                  : apply_dispatch<T, true>(stages, skip, log2n, p, u, S, Tq, nullptr, st);
 }
 
 }  // namespace fftv<variant>
@@ -407,14 +423,18 @@ static hipError_t apply_dispatch(int stages, const int* skip, int log2n, const T
 hipError_t CB_CAT(launch_apply_v, CB_FFT_VARIANT)(const cb_plan_s* P, const void* p, void* u, hipStream_t st,
                                                  int stages, const int* skip, const void* table, int prec) {
   using namespace CB_CAT(fftv, CB_FFT_VARIANT);
+  // stages bit 3: the N-periodic convolution (its table must be given)
+  const bool periodic = (stages & 8) != 0;
+  stages &= 7;
+  if (periodic && !table) return hipErrorInvalidValue;
   if (prec == 0) {
     if (!table) table = P->precision == 0 ? P->d_table : P->d_table64;
-    return apply_dispatch<double>(stages, skip, P->log2n, (const double*)p, (double*)u, (cx<double>*)P->d_S,
-                                  (const double*)table, nullptr, st);
+    return apply_any<double>(periodic, stages, skip, P->log2n, (const double*)p, (double*)u, (cx<double>*)P->d_S,
+                             (const double*)table, st);
   }
   if (!table) table = P->d_table;
-  return apply_dispatch<float>(stages, skip, P->log2n, (const float*)p, (float*)u, (cx<float>*)P->d_S,
-                               (const float*)table, nullptr, st);
+  return apply_any<float>(periodic, stages, skip, P->log2n, (const float*)p, (float*)u, (cx<float>*)P->d_S,
+                          (const float*)table, st);
 }
 
 // Set the dynamic-LDS attributes of every convolution kernel of this size
@@ -425,8 +445,10 @@ template <int LOG2N>
 static void prepare_n() {
   float* nf = nullptr;
   double* nd = nullptr;
-  (void)apply_impl<float, LOG2N>(0, nullptr, nf, nf, nullptr, nullptr, nullptr, nullptr);
-  (void)apply_impl<double, LOG2N>(0, nullptr, nd, nd, nullptr, nullptr, nullptr, nullptr);
+  (void)apply_impl<float, LOG2N, true>(0, nullptr, nf, nf, nullptr, nullptr, nullptr, nullptr);
+  (void)apply_impl<double, LOG2N, true>(0, nullptr, nd, nd, nullptr, nullptr, nullptr, nullptr);
+  (void)apply_impl<float, LOG2N, false>(0, nullptr, nf, nf, nullptr, nullptr, nullptr, nullptr);
+  (void)apply_impl<double, LOG2N, false>(0, nullptr, nd, nd, nullptr, nullptr, nullptr, nullptr);
 }
 }  // namespace fftv<variant>
 

@@ -91,7 +91,8 @@ struct cb_plan_s {
   // device memory owned by the plan
   void* d_table = nullptr;       // (N+1)^2, 1/M^2 folded, plan type
   void* d_table64 = nullptr;     // FP64 copy for FP32 plans (exact refreshes)
-  void* d_ptable = nullptr;      // preconditioner symbol 1/C(kh), (N+1)^2, 1/M^2 folded
+  void* d_ptable = nullptr;      // preconditioner symbol 1/C(kh) on the N-periodic grid,
+                                 // (N/2+1)^2, 1/N^2 folded
   void* d_pinv = nullptr;        // preconditioner symbol 1/K^(k), same layout
   void* d_y = nullptr;           // preconditioned residual of the fixed-set CG (8 B per cell)
   int precond_auto = 0;          // automatic preconditioner of a cold start: 0 none, 1 layer
@@ -122,6 +123,9 @@ struct cb_plan_s {
 namespace cb {
 // prec: -1 the plan's precision, 0 FP64, 1 FP32 (the table defaults to the
 // transfer table of that precision).  Runs the plan's FFT variant for prec.
+// stages: bits 0..2 select K1..K3; bit 3 (8) runs the N-periodic
+// convolution instead of the padded one, with a (N/2+1)^2 table that must
+// be given (the preconditioner symbols).
 hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages = 7,
                         const int* skip = nullptr, const void* table = nullptr, int prec = -1);
 inline size_t intermediate_elems(int N) { return (size_t)N * (N + 1); }

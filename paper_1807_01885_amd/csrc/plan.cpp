@@ -261,24 +261,29 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
   std::vector<double> tdev(P->table64);
   const double inv = 1.0 / ((double)M * M);
   for (double& v : tdev) v *= inv;
-  // Preconditioner symbol of the constrained CG: 1 / C(k h) with
-  // C = E1* k K^ / 2, i.e. the ratio of the homogeneous-coating kernel to
-  // the layered one (tends to 1 at high k), with the same 1/M^2 folded in.
-  std::vector<double> pdev((size_t)NC * NC);
+  // Preconditioner symbols of the constrained CG, applied as N-periodic
+  // convolutions (real transforms of length N, a (N/2+1)^2 quadrant with
+  // 1/N^2 folded in; measured no more iterations than the padded form at a
+  // third of its cost).  Wavenumbers k = (2 pi / L) |(a, b)|, which are the
+  // padded grid's at (2a, 2b).
+  //  - 1 / C(k h), C = E1* k K^ / 2: the ratio of the homogeneous-coating
+  //    kernel to the layered one (tends to 1 at high k);
+  //  - 1 / K^(k): the inverse of the operator itself, which undoes the 1/k
+  //    decay of the half-space kernel as well as the layer's stiffness
+  //    contrast (the padded table's DC value at k = 0).
+  const int NP = N / 2 + 1;
+  const double invN = 1.0 / ((double)N * N);
+  std::vector<double> pdev((size_t)NP * NP), qdev((size_t)NP * NP);
   {
     const Coef cf = coefficients(E1, nu1, E2, nu2);
-    const double dk = 2.0 * M_PI / (M * P->dx);
-    for (int a = 0; a < NC; a++)
-      for (int b = 0; b < NC; b++) {
+    const double dk = 2.0 * M_PI / L;
+    for (int a = 0; a < NP; a++)
+      for (int b = 0; b < NP; b++) {
         const double k = dk * std::sqrt((double)a * a + (double)b * b);
-        pdev[(size_t)a * NC + b] = inv / shape(k * h, cf);
+        pdev[(size_t)a * NP + b] = invN / shape(k * h, cf);
+        qdev[(size_t)a * NP + b] = invN / P->table64[(size_t)(2 * a) * NC + 2 * b];
       }
   }
-  // Second symbol: the inverse of the operator itself, 1 / K^(k) (with the
-  // same 1/M^2), which undoes the 1/k decay of the half-space kernel as well
-  // as the layer's stiffness contrast.
-  std::vector<double> qdev((size_t)NC * NC);
-  for (size_t e = 0; e < qdev.size(); e++) qdev[e] = inv / P->table64[e];
   // automatic choice from a cold start: the layer multiplier for a coating
   // at least 3x stiffer than the substrate and thin relative to the domain,
   // else none (from a caller's guess the solver takes the inverse symbol)
@@ -301,8 +306,8 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
     P->nbr = (int)(nb < RED_BLOCKS_MAX ? (nb < 1 ? 1 : nb) : RED_BLOCKS_MAX);
   }
   alloc(&P->d_table, (size_t)NC * NC * es);
-  alloc(&P->d_ptable, (size_t)NC * NC * es);
-  alloc(&P->d_pinv, (size_t)NC * NC * es);
+  alloc(&P->d_ptable, (size_t)NP * NP * es);
+  alloc(&P->d_pinv, (size_t)NP * NP * es);
   // the intermediate and the solver arrays are sized for FP64 in both
   // precisions: solves keep their state (p, u, f, gap) in FP64 and FP32
   // plans refresh u with an FP64 convolution
@@ -429,6 +434,14 @@ extern "C" int cb_apply_K(cb_plan P, const void* p, void* u) {
   if (!p || !u) return cb_fail(CB_E_INVALID, "null array");
   if (p == u) return cb_fail(CB_E_INVALID, "u must not alias p");
   CB_HIP(cb::launch_apply(P, p, u, P->stream));
+  return CB_OK;
+}
+
+extern "C" int cb_apply_precond(cb_plan P, int which, const void* x, void* y) {
+  if (!P) return cb_fail(CB_E_INVALID, "null plan");
+  if (which != 1 && which != 2) return cb_fail(CB_E_INVALID, "which must be 1 or 2");
+  if (!x || !y) return cb_fail(CB_E_INVALID, "null array");
+  CB_HIP(cb::launch_apply(P, x, y, P->stream, 15, nullptr, which == 1 ? P->d_ptable : P->d_pinv));
   return CB_OK;
 }
 

@@ -841,6 +841,10 @@ static int write_state(cb_plan_s* P, const SolverState& s) {
 static hipError_t apply_dir(const Ctx& c, const void* x, void* y, const int* skip, const void* table = nullptr) {
   return launch_apply(c.P, x, y, c.st, 7, skip, table, -1);
 }
+// Fourier preconditioner (N-periodic convolution with the symbol `table`)
+static hipError_t apply_pc(const Ctx& c, const void* x, void* y, const int* skip, const void* table) {
+  return launch_apply(c.P, x, y, c.st, 15, skip, table, -1);
+}
 // FP64 convolution of the FP64 state
 static hipError_t apply64(const Ctx& c, const double* x, double* y, const int* skip) {
   return launch_apply(c.P, x, y, c.st, 7, skip, nullptr, 0);
@@ -879,7 +883,7 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
     hipLaunchKernelGGL(k_pk_gmask<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)g, gm, st, gb, part,
                        c.nb, c.n, par, run_phase);
     // z' = M^-1 gm (into r, free until K t is formed)
-    if (hipError_t e = apply_dir(c, gm, r, skip, pc_k == 2 ? c.P->d_pinv : c.P->d_ptable)) return e;
+    if (hipError_t e = apply_pc(c, gm, r, skip, pc_k == 2 ? c.P->d_pinv : c.P->d_ptable)) return e;
     hipLaunchKernelGGL(k_pk_zdot<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)g, (const TD*)r, st,
                        part, c.n, par, run_phase);
     hipLaunchKernelGGL(k_pk_dir_pc<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)r, t, st, part,
@@ -931,7 +935,7 @@ static hipError_t mcg_enqueue_chunk(const Ctx& c, double* x, const unsigned char
       hipLaunchKernelGGL(k_mcg_zq<TD>, grid, blk, 0, c.st, (const TD*)z, (const TD*)q, S, st, part, c.n);
       hipLaunchKernelGGL(k_mcg_upd_pc<TD>, grid, blk, 0, c.st, x, r, rt, (const TD*)z, (const TD*)q, S, st, part,
                          c.nb, c.n, par);
-      if (hipError_t e = apply_dir(c, rt, y, &st->done, ptab)) return e;
+      if (hipError_t e = apply_pc(c, rt, y, &st->done, ptab)) return e;
       hipLaunchKernelGGL(k_mcg_ry<TD>, grid, blk, 0, c.st, (const double*)r, (const TD*)y, S, st, part, c.nb, c.n,
                          par);
       hipLaunchKernelGGL(k_mcg_dir_pc<TD>, grid, blk, 0, c.st, z, (const TD*)y, S, st, part, c.nb, c.n, par);
@@ -1165,7 +1169,7 @@ static int set_solve(const Ctx& c, const double* f, double d, const unsigned cha
     resid = s.resid;
     if (s.done || attempt == 2 || budget <= 0) return (s.done || attempt == 2) ? CB_OK : CB_E_NOCONV;
     if (pk > 0) {  // y = M^-1 r (z holds r in the direction type), z = y on S
-      CB_HIP(apply_dir(c, z, P->d_y, nullptr, pk == 2 ? P->d_pinv : P->d_ptable));
+      CB_HIP(apply_pc(c, z, P->d_y, nullptr, pk == 2 ? P->d_pinv : P->d_ptable));
       hipLaunchKernelGGL(k_mcg_pc0<TD>, grid, blk, 0, c.st, (const double*)r, (const TD*)P->d_y, z, S, P->d_state,
                          P->d_part, c.n);
     }
