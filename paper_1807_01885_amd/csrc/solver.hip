@@ -41,7 +41,7 @@
 
 namespace cb {
 
-constexpr int RT = 256;  // threads per solver block
+constexpr int RT = 512;  // threads per solver block (8 waves per CU at 256 blocks)
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
