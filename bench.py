@@ -9,7 +9,8 @@ direction convolutions with FP64 state and reductions, the learned warm
 start (network forward pass inside the step), all 32 solves concurrent
 through cb_solve_batch, FFT launch shapes from the shipped tune cache.
 
-Also timed on the same set and tolerance: the FP32 path from a cold start,
+Also timed on the same set and tolerance: the FP32 path from the solver's
+own cold start (the overlap at an approach estimated from the profile),
 and the plain FP64 solver (cold start, one solve after another).  Every
 path's pressures are checked against an FP64 solve to residual 1e-10.
 

@@ -92,7 +92,13 @@ typedef struct {
   int max_iter;      /* conjugate-gradient iteration limit per solve; <= 0: 20000 */
   int chunk;         /* iterations run on the device between host checks of
                         the convergence flag; <= 0: 16 */
-  int init;          /* 0: cold start; 1: the caller's p_io is the initial guess */
+  int init;          /* 0: cold start; 1: the caller's p_io is the initial
+                        guess (negative values read as 0; a guess with no
+                        positive value is no guess: cold start).  Cold start
+                        under displacement control: p = (d - f)+ / k00;
+                        under force control: p = (d0 - f)+ rescaled to F, d0
+                        estimated from the profile's depth distribution and
+                        the layered modulus (uniform if no such d0 exists) */
   double attach_tol; /* adhesive: a cell outside the contact attaches when
                         its gap is below -attach_tol (length); < 0: 1e-12 L
                         (FP64), 1e-9 L (FP32) */
@@ -328,9 +334,9 @@ int cb_net_features(cb_net net, const double* f, int Nf, double L, double h,
  * interpolated (bilinear, cell-centred) or averaged onto the plan's
  * N x N grid into p_out (double).  Pass p_out to cb_solve_force with
  * opts.init = 1.  Plans of coatings >= 3x stiffer than the substrate with
- * h <= L/16 get the uniform unit pressure instead (the cold start): there
- * the network's guess measured slower than a cold start.  Synchronises the
- * net's stream. */
+ * h <= L/16 get no guess (zeros, which the solve takes as a cold start):
+ * there the network's guess measured slower than a cold start.
+ * Synchronises the net's stream. */
 int cb_net_warmstart(cb_net net, cb_plan plan, const double* f, double F,
                      double cut, double* p_out);
 

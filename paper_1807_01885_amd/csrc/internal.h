@@ -1,5 +1,6 @@
 // Internal plan state and launch entry points of libcoatbem.
 #pragma once
+#include <cmath>
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -119,6 +120,27 @@ struct cb_plan_s {
   int variant[2] = {0, 0};  // FFT launch-shape variant of the FP64 / FP32 convolutions
   double tune_us = 0.0;     // autotuned time of one convolution (0: not tuned)
 };
+
+namespace cb {
+// Dimensionless coefficients of the normalised Eq. 9-10: with
+// mu_i = E_i / (2(1+nu_i)), alpha = mu1/mu2, kappa_i = 3 - 4 nu_i,
+// A/D = -a b, B/D = 4 b, 2C/D = -(a + b).
+struct Coef {
+  double a, b;
+};
+inline Coef coefficients(double E1, double nu1, double E2, double nu2) {
+  const double mu1 = E1 / (2.0 * (1.0 + nu1)), mu2 = E2 / (2.0 * (1.0 + nu2));
+  const double al = mu1 / mu2, k1 = 3.0 - 4.0 * nu1, k2 = 3.0 - 4.0 * nu2;
+  return {(al * k2 - k1) / (1.0 + al * k2), (al - 1.0) / (al + k1)};
+}
+// C(t) = E1* k K^(k) / 2 at t = k h.
+inline double shape(double t, const Coef& c) {
+  const double e2 = std::exp(-2.0 * t), e4 = e2 * e2;
+  const double num = 1.0 + 4.0 * c.b * t * e2 - c.a * c.b * e4;
+  const double den = 1.0 - (c.a + c.b + 4.0 * c.b * t * t) * e2 + c.a * c.b * e4;
+  return num / den;
+}
+}  // namespace cb
 
 namespace cb {
 // prec: -1 the plan's precision, 0 FP64, 1 FP32 (the table defaults to the

@@ -674,9 +674,9 @@ extern "C" int cb_net_adam_step(cb_net N, float lr) {
   return CB_OK;
 }
 
-__global__ void k_fill1(double* __restrict__ p, long long n) {
+__global__ void k_fill0(double* __restrict__ p, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    p[i] = 1.0;
+    p[i] = 0.0;
 }
 
 // features of one problem into x, its min f kept in scratch[slot]
@@ -723,9 +723,9 @@ extern "C" int cb_net_warmstart_batch(cb_net N, int n, const cb_plan* plans, con
   for (int i = 0; i < n; i++) {
     const cb_plan P = plans[i];
     if (P->precond_auto == 1) {
-      // stiff thin coating: the uniform start (the network's guess measured
-      // slower than a cold start on these)
-      hipLaunchKernelGGL(k_fill1, egrid((long long)P->N * P->N), dim3(256), 0, N->stream, p_out[i],
+      // stiff thin coating: no guess (zeros; the solve then takes its cold
+      // start): the network's guess measured slower than a cold start there
+      hipLaunchKernelGGL(k_fill0, egrid((long long)P->N * P->N), dim3(256), 0, N->stream, p_out[i],
                          (long long)P->N * P->N);
       continue;
     }

@@ -35,25 +35,10 @@ extern "C" int cb_version(void) { return 100; }
 
 namespace {
 
-// Dimensionless coefficients of the normalised Eq. 9-10: with
-// mu_i = E_i / (2(1+nu_i)), alpha = mu1/mu2, kappa_i = 3 - 4 nu_i,
-// A/D = -a b, B/D = 4 b, 2C/D = -(a + b).
-struct Coef {
-  double a, b;
-};
-Coef coefficients(double E1, double nu1, double E2, double nu2) {
-  const double mu1 = E1 / (2.0 * (1.0 + nu1)), mu2 = E2 / (2.0 * (1.0 + nu2));
-  const double al = mu1 / mu2, k1 = 3.0 - 4.0 * nu1, k2 = 3.0 - 4.0 * nu2;
-  return {(al * k2 - k1) / (1.0 + al * k2), (al - 1.0) / (al + k1)};
-}
+using cb::Coef;
+using cb::coefficients;
+using cb::shape;
 
-// C(t) = E1* k K^(k) / 2 at t = k h.
-inline double shape(double t, const Coef& c) {
-  const double e2 = std::exp(-2.0 * t), e4 = e2 * e2;
-  const double num = 1.0 + 4.0 * c.b * t * e2 - c.a * c.b * e4;
-  const double den = 1.0 - (c.a + c.b + 4.0 * c.b * t * t) * e2 + c.a * c.b * e4;
-  return num / den;
-}
 // C(t) - 1 without cancellation for large t.
 inline double shape_m1(double t, const Coef& c) {
   const double e2 = std::exp(-2.0 * t), e4 = e2 * e2;

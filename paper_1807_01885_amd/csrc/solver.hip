@@ -670,17 +670,57 @@ __global__ void __launch_bounds__(RT) k_zero_off(double* __restrict__ p, const u
 __global__ void __launch_bounds__(RT) k_zero_bytes(unsigned char* __restrict__ a, int n) { GRID_LOOP(i, n) a[i] = 0; }
 
 // min f, max f, non-finite -> R_MISC (as max of -f, max of f, flag)
-__global__ void __launch_bounds__(RT) k_minmax(const double* __restrict__ x, double* part, int n) {
-  double v[3] = {-INFINITY, -INFINITY, 0.0};
-  const bool mx[3] = {true, true, true};
+// -min f, max f, non-finite flag, and max p of a caller's guess (p nullable)
+__global__ void __launch_bounds__(RT) k_minmax(const double* __restrict__ x, const double* __restrict__ p,
+                                               double* part, int n) {
+  double v[4] = {-INFINITY, -INFINITY, 0.0, -INFINITY};
+  const bool mx[4] = {true, true, true, true};
   GRID_LOOP(i, n) {
     const double a = x[i];
     v[0] = fmax(v[0], -a);
     v[1] = fmax(v[1], a);
     if (!isfinite(a)) v[2] = 1.0;
+    if (p) v[3] = fmax(v[3], p[i]);
   }
-  block_allreduce<3>(v, mx);
-  write_partials<3>(region(part, R_MISC), v);
+  block_allreduce<4>(v, mx);
+  write_partials<4>(region(part, R_MISC), v);
+}
+
+// Histogram of the profile depth e = f - fmin for the force-control cold
+// start: HB bins, bin 0 e <= emin, bin b e in (emin r^(b-1), emin r^b];
+// per block the cell counts and the sums of e in fixed point (units of
+// range 2^-40, so that the totals are exact and order-independent), into
+// out[block][2 HB].
+constexpr int HB = 128;
+constexpr double HSPAN = 1e7;  // emin = range / HSPAN
+__global__ void __launch_bounds__(RT) k_depth_hist(const double* __restrict__ f, double fmin, double range,
+                                                   unsigned long long* __restrict__ out, int n) {
+  __shared__ unsigned long long h[2 * HB];
+  for (int i = threadIdx.x; i < 2 * HB; i += RT) h[i] = 0ull;
+  __syncthreads();
+  const double emin = range / HSPAN;
+  const double inv_lr = (HB - 1) / log(HSPAN);
+  const double unit = 1099511627776.0 / range;  // 2^40 / range
+  GRID_LOOP(i, n) {
+    const double e = f[i] - fmin;
+    int b = e > emin ? 1 + (int)(log(e / emin) * inv_lr) : 0;
+    b = b < HB - 1 ? b : HB - 1;
+    const double q = e * unit + 0.5;
+    atomicAdd(&h[b], 1ull);
+    atomicAdd(&h[HB + b], (unsigned long long)(q > 0.0 ? q : 0.0));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * HB; i += RT) out[(size_t)blockIdx.x * 2 * HB + i] = h[i];
+}
+// Sum of the block histograms (fixed order) as doubles: counts, then sums
+// of e in units of range 2^-40.
+__global__ void __launch_bounds__(RT) k_depth_hist_fold(const unsigned long long* __restrict__ in, int nb,
+                                                        double* __restrict__ out) {
+  for (int i = threadIdx.x; i < 2 * HB; i += RT) {
+    unsigned long long t = 0ull;
+    for (int b = 0; b < nb; b++) t += in[(size_t)b * 2 * HB + i];
+    out[i] = (double)t;
+  }
 }
 
 // sum p, |S| (or |p > 0|), sum p u, non-finite -> R_MISC
@@ -1063,6 +1103,57 @@ static SolverState base_state(const cb_plan_s* P, double tol, double d_in, bool 
   return s;
 }
 
+// Force-control cold start: the overlap {f < d0} of the rigid indenter at
+// an approach d0 estimated from the distribution of the profile depth
+// e = f - fmin, with p0 = d0 - f there (the solve rescales it to F).  A
+// region of area A pressed to mean depth dbar carries about
+// 1.1 E(k) sqrt(A) dbar, with E(k) = E1* / C(k h) the layered modulus at
+// k = 2 / sqrt(A) (on a half-space the exact factors are 2/sqrt(pi) = 1.13
+// for a flat punch, 1.06 for a paraboloid, about 1.1 for a cone).  d0 is
+// taken at 0.7
+// of the depth where that force reaches F, since the overlap exceeds the
+// contact of curved indenters.  A uniform start over the grid spends most
+// of its iterations shrinking the contact set (CPU sweep of the N = 256
+// force set: 670 -> 473 iterations).  Too large a load for any overlap:
+// the uniform start.
+static int cold_start_force(const Ctx& c, const double* f, double fmin, double fmax, double F, double* p) {
+  cb_plan_s* P = c.P;
+  const dim3 grid(c.nb), blk(RT);
+  const double range = fmax - fmin;
+  double d0 = 0.0;
+  bool found = false;
+  if (range > 0.0) {
+    // block histograms in y (2 HB words each; N^2 >= 2 HB words for N >= 16)
+    int nbh = (int)std::min<long long>(c.nb, std::max<long long>(1, (long long)c.n / (2 * HB)));
+    hipLaunchKernelGGL(k_depth_hist, dim3(nbh), blk, 0, c.st, f, fmin, range, (unsigned long long*)P->d_y, c.n);
+    hipLaunchKernelGGL(k_depth_hist_fold, dim3(1), blk, 0, c.st, (const unsigned long long*)P->d_y, nbh,
+                       (double*)P->d_pold);
+    double hist[2 * HB];
+    CB_HIP(hipMemcpyAsync(hist, P->d_pold, sizeof(hist), hipMemcpyDeviceToHost, c.st));
+    CB_HIP(hipStreamSynchronize(c.st));
+    const Coef cf = coefficients(P->E1, P->nu1, P->E2, P->nu2);
+    const double emin = range / HSPAN, r = std::pow(HSPAN, 1.0 / (HB - 1));
+    const double unit = range / 1099511627776.0;
+    const double dA = P->dx * P->dx;
+    double C = 0.0, S = 0.0, edge = emin;
+    for (int b = 0; b < HB && !found; b++, edge *= r) {
+      C += hist[b];
+      S += hist[HB + b] * unit;
+      if (C <= 0.0) continue;
+      const double A = C * dA, dbar = edge - S / C, k = 2.0 / std::sqrt(A);
+      const double Fm = 1.1 * P->E1s / shape(k * P->h, cf) * std::sqrt(A) * dbar;
+      if (Fm >= F) {
+        d0 = fmin + 0.7 * edge;
+        found = true;
+      }
+    }
+  }
+  if (found) hipLaunchKernelGGL(k_init_disp, grid, blk, 0, c.st, p, f, c.n, d0, P->k00);
+  else hipLaunchKernelGGL(k_fill, grid, blk, 0, c.st, p, c.n, F / (P->dx * P->dx * c.n));
+  CB_HIP(hipGetLastError());
+  return CB_OK;
+}
+
 template <typename TD>
 static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, double* p, unsigned char* mask,
                     const cb_solve_opts* o, cb_result* res) {
@@ -1074,12 +1165,14 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
   if (op.precond < -1 || op.precond > 3) return cb_fail(CB_E_INVALID, "precond must be -1, 0, 1, 2 or 3");
   if (int rc = enter(P)) return rc;
   const dim3 grid(c.nb), blk(RT);
-  hipLaunchKernelGGL(k_minmax, grid, blk, 0, c.st, f, P->d_part, c.n);
-  hipLaunchKernelGGL(k_fold_misc<3>, dim3(1), blk, 0, c.st, P->d_part, c.nb, 7);
-  double mm[3];
-  if (int rc = read_scratch(c, mm, 3)) return rc;
+  hipLaunchKernelGGL(k_minmax, grid, blk, 0, c.st, f, op.init == 1 ? (const double*)p : nullptr, P->d_part, c.n);
+  hipLaunchKernelGGL(k_fold_misc<4>, dim3(1), blk, 0, c.st, P->d_part, c.nb, 15);
+  double mm[4];
+  if (int rc = read_scratch(c, mm, 4)) return rc;
   if (mm[2] > 0.0) return cb_fail(CB_E_NONFINITE, "profile f contains NaN/Inf");
-  const double fmin = -mm[0];
+  const double fmin = -mm[0], fmax = mm[1];
+  // a caller's guess without a positive value is no guess: cold start
+  const bool guess = op.init == 1 && mm[3] > 0.0;
   const bool trivial = force ? !(target > 0.0) : (target <= fmin);
   if (trivial) {
     hipLaunchKernelGGL(k_fill, grid, blk, 0, c.st, p, c.n, 0.0);
@@ -1091,9 +1184,13 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
     return CB_OK;
   }
   // initial pressure
-  if (op.init == 1) hipLaunchKernelGGL(k_clamp_pos, grid, blk, 0, c.st, p, c.n);
-  else if (force) hipLaunchKernelGGL(k_fill, grid, blk, 0, c.st, p, c.n, target / (dA * c.n));
-  else hipLaunchKernelGGL(k_init_disp, grid, blk, 0, c.st, p, f, c.n, target, P->k00);
+  if (guess) {
+    hipLaunchKernelGGL(k_clamp_pos, grid, blk, 0, c.st, p, c.n);
+  } else if (force) {
+    if (int rc = cold_start_force(c, f, fmin, fmax, target, p)) return rc;
+  } else {
+    hipLaunchKernelGGL(k_init_disp, grid, blk, 0, c.st, p, f, c.n, target, P->k00);
+  }
   if (int rc = write_state(P, base_state(P, op.tol, force ? 0.0 : target, force, force ? target : 0.0))) return rc;
   CB_HIP(hipMemsetAsync(gbar2_ptr(P), 0, 2 * sizeof(double), c.st));
   // direction buffers start at zero so that a solve never depends on what a
@@ -1117,7 +1214,7 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
   const int two = 3 + P->precond_auto;
   const int pk = op.precond == 3 ? two
                  : op.precond >= 0 ? op.precond
-                 : (op.init == 1 && P->precond_auto == 0) ? 2 : two;
+                 : (guess && P->precond_auto == 0) ? 2 : two;
   auto enq = [&]() { return pk_enqueue_chunk<TD>(c, p, f, force, pk, op.chunk); };
   if (int rc = run_chunks(P, (force ? 1 : 0) + 4 * pk, p, f, nullptr, op.chunk, op.max_iter, enq, &s)) return rc;
   const int status = s.nonfinite ? CB_E_NONFINITE : (s.done ? CB_OK : CB_E_NOCONV);

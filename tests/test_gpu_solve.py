@@ -174,3 +174,47 @@ def test_repeat_solves_replay_graphs_bitwise(lib, prec):
         assert math.isfinite(junk)
         assert r["status"] == 0
     assert torch.equal(ps[0], ps[1]) and torch.equal(ps[0], ps[2])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_force_cold_start_paths(lib, prec):
+    """Force-control cold start: a guess with no positive value is no guess
+    (bit-identical to init = 0); a flat profile (no depth distribution) and
+    a load beyond what any overlap region carries take the uniform start;
+    every path converges to the oracle's pressure."""
+    print(f"force cold start paths {prec}", flush=True)
+    N, L = 64, 1.0
+    mat = Material(0.05, 3.0, 0.3, 1.0, 0.3)
+    op = Operator(N, L, mat)
+    tol = 1e-10 if prec == "fp64" else 1e-8
+    bar = 1e-7 if prec == "fp64" else 2e-4
+    plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, 0.0, prec)
+    f = inputs.paraboloid(N, L, 1.0)
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
+    F = 3e-3
+    ref = solve_pk(op, f, F, mode="force", tol=1e-11)
+    p0 = torch.zeros_like(ft)
+    r0 = lib.cb_solve_force(plan, ft, F, p0, tol=tol)
+    for guess in (torch.zeros_like(ft), -torch.ones_like(ft)):
+        r1 = lib.cb_solve_force(plan, ft, F, guess, tol=tol, init=1)
+        assert r1["iters"] == r0["iters"] and torch.equal(guess, p0)
+    e = np.linalg.norm(p0.cpu().numpy() - ref.p) / np.linalg.norm(ref.p)
+    print(f"  paraboloid iters {r0['iters']} (oracle uniform start {ref.iters}) e_p {e:.1e}", flush=True)
+    assert r0["status"] == 0 and e < bar
+    # flat profile: the whole grid is a flat punch
+    fz = torch.zeros_like(ft)
+    refz = solve_pk(op, np.zeros((N, N)), F, mode="force", tol=1e-11)
+    pz = torch.zeros_like(ft)
+    rz = lib.cb_solve_force(plan, fz, F, pz, tol=tol)
+    ez = np.linalg.norm(pz.cpu().numpy() - refz.p) / np.linalg.norm(refz.p)
+    print(f"  flat profile iters {rz['iters']} e_p {ez:.1e}", flush=True)
+    assert rz["status"] == 0 and ez < bar
+    # a load that presses the whole grid into contact
+    Fb = 40.0
+    refb = solve_pk(op, f, Fb, mode="force", tol=1e-11)
+    assert (refb.p > 0).all()
+    pb = torch.zeros_like(ft)
+    rb = lib.cb_solve_force(plan, ft, Fb, pb, tol=tol)
+    eb = np.linalg.norm(pb.cpu().numpy() - refb.p) / np.linalg.norm(refb.p)
+    print(f"  full-contact load iters {rb['iters']} e_p {eb:.1e}", flush=True)
+    assert rb["status"] == 0 and eb < bar
