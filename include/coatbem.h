@@ -154,7 +154,7 @@ typedef struct {
  *   Eq. 9-11 (Sec. 2): the transfer function is evaluated in FP64 from the
  *   normalised form of Eq. 9-10 at k = sqrt(kx^2 + ky^2) on the 2N-padded
  *   frequency grid, with the DC value of opts->dc_mode; sigma_c from Eq. 12.
- *   N: power of two, 16 <= N <= 2048.  L > 0, h >= 0, E1, E2 > 0,
+ *   N: power of two, 16 <= N <= 4096.  L > 0, h >= 0, E1, E2 > 0,
  *   0 <= nu < 0.5, dgamma >= 0 (0: non-adhesive).
  *   On success *out owns device tables and workspace (see cb_plan_info);
  *   on failure *out is NULL and a CB_E_* code is returned.

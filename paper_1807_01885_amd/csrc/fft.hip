@@ -414,6 +414,7 @@ static hipError_t apply_dispatch(int stages, const int* skip, int log2n, const T
     case 9: return apply_impl<T, 9, PAD>(stages, skip, p, u, S, Tq, tw, st);
     case 10: return apply_impl<T, 10, PAD>(stages, skip, p, u, S, Tq, tw, st);
     case 11: return apply_impl<T, 11, PAD>(stages, skip, p, u, S, Tq, tw, st);
+    case 12: return apply_impl<T, 12, PAD>(stages, skip, p, u, S, Tq, tw, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -465,7 +466,7 @@ size_t CB_CAT(lds_bytes_v, CB_FFT_VARIANT)(int log2n, int prec) {
 #define CB_LDS_CASE(k) \
   case k: return prec == 0 ? lds_need<double, k>() : lds_need<float, k>();
     CB_LDS_CASE(4) CB_LDS_CASE(5) CB_LDS_CASE(6) CB_LDS_CASE(7)
-    CB_LDS_CASE(8) CB_LDS_CASE(9) CB_LDS_CASE(10) CB_LDS_CASE(11)
+    CB_LDS_CASE(8) CB_LDS_CASE(9) CB_LDS_CASE(10) CB_LDS_CASE(11) CB_LDS_CASE(12)
 #undef CB_LDS_CASE
     default: return 0;
   }
@@ -482,6 +483,7 @@ void CB_CAT(prepare_apply_v, CB_FFT_VARIANT)(int log2n) {
     case 9: prepare_n<9>(); break;
     case 10: prepare_n<10>(); break;
     case 11: prepare_n<11>(); break;
+    case 12: prepare_n<12>(); break;
     default: break;
   }
 }

@@ -161,8 +161,8 @@ static void build_table(int N, double L, double h, double E1, double nu1, double
 
 static int check_params(int N, double L, double h, double E1, double nu1, double E2, double nu2,
                         double dgamma) {
-  if (N < 16 || N > 2048 || (N & (N - 1)))
-    return cb_fail(CB_E_INVALID, "N must be a power of two in [16, 2048]");
+  if (N < 16 || N > 4096 || (N & (N - 1)))
+    return cb_fail(CB_E_INVALID, "N must be a power of two in [16, 4096]");
   if (!finite_pos(L)) return cb_fail(CB_E_INVALID, "L must be finite and > 0");
   if (!std::isfinite(h) || h < 0.0) return cb_fail(CB_E_INVALID, "h must be finite and >= 0");
   if (!finite_pos(E1) || !finite_pos(E2)) return cb_fail(CB_E_INVALID, "E1, E2 must be finite and > 0");

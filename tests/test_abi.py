@@ -78,7 +78,7 @@ def test_host_table_dc_zero(lib):
 
 @pytest.mark.parametrize("args", [
     (15, 1.0, 0.1, 1.0, 0.3, 1.0, 0.3),      # N not a power of two
-    (4096, 1.0, 0.1, 1.0, 0.3, 1.0, 0.3),    # N too large
+    (8192, 1.0, 0.1, 1.0, 0.3, 1.0, 0.3),    # N too large
     (64, 0.0, 0.1, 1.0, 0.3, 1.0, 0.3),      # L = 0
     (64, 1.0, -0.1, 1.0, 0.3, 1.0, 0.3),     # h < 0
     (64, 1.0, 0.1, -1.0, 0.3, 1.0, 0.3),     # E1 < 0

@@ -29,7 +29,7 @@ def _run(lib, N, L, mat, p, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("N", [16, 32, 64, 128, 256, 512, 1024, 2048])
+@pytest.mark.parametrize("N", [16, 32, 64, 128, 256, 512, 1024, 2048, 4096])
 def test_apply_random(lib, N, prec):
     print(f"apply random N={N} {prec}", flush=True)
     rng = np.random.default_rng(N + (0 if prec == "fp64" else 7))

@@ -24,7 +24,7 @@ DT = {"fp64": torch.float64, "fp32": torch.float32}
 NVAR = 6
 
 
-@pytest.mark.parametrize("N", [16, 64, 256, 1024, 2048])
+@pytest.mark.parametrize("N", [16, 64, 256, 1024, 2048, 4096])
 def test_every_variant_matches_oracle(lib, N):
     print(f"variants N={N}", flush=True)
     rng = np.random.default_rng(N + 11)
@@ -39,7 +39,7 @@ def test_every_variant_matches_oracle(lib, N):
             except lib.CoatbemError as e:
                 # only a shape too large for one block (LDS or 1024 threads)
                 # at the largest size may be refused
-                assert e.status == lib.CB_E_UNSUPPORTED and N == 2048, str(e)
+                assert e.status == lib.CB_E_UNSUPPORTED and N >= 2048, str(e)
                 print(f"  {prec} variant {v}: not launchable at this size", flush=True)
                 continue
             assert lib.cb_plan_get_info(plan)["fft_variant"] == v

@@ -152,3 +152,30 @@ def test_c2_other_sweeps_fp32(lib, k):
         print(f"  d={seg[-1]:+.3e} F {r[-1]['F']:+.4e} min F {min(x['F'] for x in r):+.4e} area {A[-1]:.4f} "
               f"gap on S {on:.1e} pen {pen:.1e} {sum(x['ms'] for x in r):.0f} ms", flush=True)
         assert on < 1e-6 and pen < 1e-6 and off == 0.0 and low <= 1.0 + 1e-9
+
+
+def test_n4096_force_solve_contact_conditions(lib):
+    """The largest grid the library takes (N = 4096, padded 8192^2), FP32
+    convolutions: a force-controlled paraboloid on a stiff coating, checked
+    through the contact conditions with the FP64 oracle's operator."""
+    N, L = 4096, 1.0
+    mat = Material(0.01, 20.0, 0.3, 1.0, 0.3)
+    print(f"N={N} force solve fp32", flush=True)
+    f = inputs.paraboloid(N, L, 1.0)
+    F = 2e-3
+    plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, 0.0, "fp32")
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
+    p = torch.zeros_like(ft)
+    res = lib.cb_solve_force(plan, ft, F, p, tol=1e-8)
+    pn = p.cpu().numpy()
+    op = Operator(N, L, mat)
+    g = _gap(op, pn, f, res["d"])
+    S = pn > 0
+    rel = np.linalg.norm(g[S]) / np.linalg.norm((res["d"] - f)[S])
+    scale = np.linalg.norm((res["d"] - f)[S]) / np.sqrt(S.sum())
+    pen = max(0.0, -g[~S].min()) / scale
+    print(f"  iters {res['iters']} {res['ms']:.0f} ms F {res['F']:.6e} area {res['area']:.4f} "
+          f"gap on S {rel:.1e} penetration off S {pen:.1e}", flush=True)
+    assert res["status"] == 0 and pn.min() >= 0.0
+    assert abs(res["F"] - F) <= 1e-6 * F
+    assert rel < 1e-6 and pen < 1e-6

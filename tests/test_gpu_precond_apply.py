@@ -51,7 +51,7 @@ def _run(lib, N, L, mat, x, prec, which, variant=0):
 
 @pytest.mark.parametrize("which", [1, 2])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("N", [16, 32, 64, 128, 256, 512, 1024, 2048])
+@pytest.mark.parametrize("N", [16, 32, 64, 128, 256, 512, 1024, 2048, 4096])
 def test_precond_random(lib, N, prec, which):
     print(f"precond apply N={N} {prec} which={which}", flush=True)
     mat = Material(0.02, 30.0, 0.3, 1.0, 0.35)
