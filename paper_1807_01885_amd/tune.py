@@ -20,7 +20,7 @@ TUNE_CACHE = os.path.join(HERE, "tune", "gfx950.txt")
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TUNE_CACHE)
-    ap.add_argument("--sizes", default="16,32,64,128,256,512,1024,2048")
+    ap.add_argument("--sizes", default="16,32,64,128,256,512,1024,2048,4096")
     a = ap.parse_args(argv)
     from . import coatbem as cb
     sizes = [int(s) for s in a.sizes.split(",")]
