@@ -90,8 +90,10 @@ typedef struct {
 typedef struct {
   double tol;        /* relative residual target; <= 0: 1e-10 (FP64), 1e-8 (FP32) */
   int max_iter;      /* conjugate-gradient iteration limit per solve; <= 0: 20000 */
-  int chunk;         /* iterations run on the device between host checks of
-                        the convergence flag; <= 0: 16 */
+  int chunk;         /* longest run of iterations on the device between host
+                        checks of the convergence flag (the runs adapt to
+                        the residual's progress, from min(8, chunk)); <= 0:
+                        16; odd values are rounded up */
   int init;          /* 0: cold start; 1: the caller's p_io is the initial
                         guess (negative values read as 0; a guess with no
                         positive value is no guess: cold start).  Cold start

@@ -67,7 +67,7 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   unsigned long long used = 0;
 };
-constexpr int GRAPH_CACHE = 6;
+constexpr int GRAPH_CACHE = 12;
 
 namespace cb {
 // FFT launch-shape variants: complex elements per thread in the row

@@ -384,13 +384,16 @@ k_pk_update(double* __restrict__ p, double* __restrict__ u, const TD* __restrict
 // iteration measured best: 32.1 mean iterations on the N = 1024 force set
 // against 36.4 after two and 37.2 after three).
 constexpr int QUIET = 1;
-__global__ void __launch_bounds__(RT) k_pk_post(SolverState* st, const double* part, int nb, int refresh,
-                                                int two_phase) {
+// u = K p is recomputed at least every REFRESH iterations (FP32 linear
+// updates drift), whatever the chunking.
+constexpr int REFRESH = 16;
+__global__ void __launch_bounds__(RT) k_pk_post(SolverState* st, const double* part, int nb, int two_phase) {
   if (st->done) return;
   const bool mx4[4] = {false, false, false, false};
   double a[4];
   fold<4>(region(part, R_UPD), nb, mx4, a);
   if (threadIdx.x == 0) {
+    const bool refresh = st->iters % REFRESH == 0;
     const bool changed = a[1] > 0.0 || a[2] > 0.0;
     st->skip_u = (refresh || changed) ? 0 : 1;
     st->pscale = (st->force && a[0] > 0.0) ? st->Ftarget / (st->dA * a[0]) : 1.0;
@@ -948,8 +951,7 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
     const bool clip = two || pk0 > 0;
     hipLaunchKernelGGL(k_pk_update<TD>, grid, blk, 0, c.st, p, u, (const TD*)g, (const TD*)t, (const TD*)r, st, part,
                        act, clip ? P->d_det : nullptr, pk0 > 0 ? 0 : 1, c.nb, c.n);
-    hipLaunchKernelGGL(k_pk_post, dim3(1), blk, 0, c.st, st, (const double*)part, c.nb, i == chunk - 1 ? 1 : 0,
-                       two ? 1 : 0);
+    hipLaunchKernelGGL(k_pk_post, dim3(1), blk, 0, c.st, st, (const double*)part, c.nb, two ? 1 : 0);
     if (hipError_t e = apply64(c, p, u, skip_u)) return e;
   }
   return hipGetLastError();
@@ -1034,31 +1036,40 @@ static hipGraphExec_t chunk_graph(cb_plan_s* P, int kind, const void* a, const v
 }
 
 // Run chunks until the device flags convergence (or max_iter launched).
-// Up to two chunks are in flight while the host checks the older one.
+// One chunk is in flight at a time: its iterations after convergence exit
+// at entry but still cost a dispatch each (about 25 us of GPU time per
+// iteration at N = 1024, and in a concurrent batch they hold the hardware
+// queues they share with other solves), so the length of the next chunk
+// follows the residual's progress: the iterations still needed at the
+// rate of the last chunk (from r0 at iteration 0 for the first), rounded
+// up to a power of two in [2, chunk].  The first chunk is min(8, chunk).
 template <class Enq>
 static int run_chunks(cb_plan_s* P, int kind, const void* a, const void* b, const void* cc, int chunk, int max_iter,
-                      Enq enqueue, SolverState* out) {
-  hipGraphExec_t ex = chunk_graph(P, kind, a, b, cc, chunk, enqueue);
-  int launched = 0, slot = 0;
-  int inflight[2], nin = 0;  // state-copy slots of launched, unchecked chunks (oldest first)
+                      Enq enqueue, SolverState* out, double r0) {
+  int launched = 0, len = chunk < 8 ? chunk : 8;
+  double r_prev = r0;
+  int it_prev = 0;
   while (true) {
-    if (launched < max_iter && nin < 2) {
-      if (ex) CB_HIP(hipGraphLaunch(ex, P->istream));
-      else CB_HIP(enqueue());
-      launched += chunk;
-      CB_HIP(hipMemcpyAsync(&P->h_state[slot], P->d_state, sizeof(SolverState), hipMemcpyDeviceToHost, P->istream));
-      CB_HIP(hipEventRecord(P->ev_state[slot], P->istream));
-      inflight[nin++] = slot;
-      slot ^= 1;
-      continue;
+    const int n = len;
+    hipGraphExec_t ex = chunk_graph(P, kind, a, b, cc, n, [&]() { return enqueue(n); });
+    if (ex) CB_HIP(hipGraphLaunch(ex, P->istream));
+    else CB_HIP(enqueue(n));
+    launched += n;
+    CB_HIP(hipMemcpyAsync(&P->h_state[0], P->d_state, sizeof(SolverState), hipMemcpyDeviceToHost, P->istream));
+    CB_HIP(hipEventRecord(P->ev_state[0], P->istream));
+    CB_HIP(hipEventSynchronize(P->ev_state[0]));
+    const SolverState& s = P->h_state[0];
+    if (s.done || s.nonfinite || launched >= max_iter) break;
+    len = chunk;
+    if (r_prev > 0.0 && s.resid > 0.0 && s.resid < r_prev && s.iters > it_prev && s.tol > 0.0) {
+      const double rate = (std::log(s.resid) - std::log(r_prev)) / (s.iters - it_prev);  // < 0
+      const double need = (std::log(s.tol) - std::log(s.resid)) / rate + 1.0;
+      len = 2;
+      while (len < chunk && len < need) len *= 2;
+      if (len > chunk) len = chunk;
     }
-    if (nin == 0) break;
-    const int chk = inflight[0];
-    inflight[0] = inflight[1];
-    nin--;
-    CB_HIP(hipEventSynchronize(P->ev_state[chk]));
-    const SolverState& s = P->h_state[chk];
-    if (s.done || s.nonfinite) break;
+    r_prev = s.resid;
+    it_prev = s.iters;
   }
   CB_HIP(hipStreamSynchronize(P->istream));
   return read_state(P, out);
@@ -1215,8 +1226,8 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
   const int pk = op.precond == 3 ? two
                  : op.precond >= 0 ? op.precond
                  : (guess && P->precond_auto == 0) ? 2 : two;
-  auto enq = [&]() { return pk_enqueue_chunk<TD>(c, p, f, force, pk, op.chunk); };
-  if (int rc = run_chunks(P, (force ? 1 : 0) + 4 * pk, p, f, nullptr, op.chunk, op.max_iter, enq, &s)) return rc;
+  auto enq = [&](int n) { return pk_enqueue_chunk<TD>(c, p, f, force, pk, n); };
+  if (int rc = run_chunks(P, (force ? 1 : 0) + 4 * pk, p, f, nullptr, op.chunk, op.max_iter, enq, &s, 1.0)) return rc;
   const int status = s.nonfinite ? CB_E_NONFINITE : (s.done ? CB_OK : CB_E_NOCONV);
   hipLaunchKernelGGL(k_pk_pending_scale, grid, blk, 0, c.st, p, (double*)P->d_u, P->d_state, c.n);
   hipLaunchKernelGGL(k_stats, grid, blk, 0, c.st, (const double*)p, (const double*)P->d_u,
@@ -1270,8 +1281,8 @@ static int set_solve(const Ctx& c, const double* f, double d, const unsigned cha
       hipLaunchKernelGGL(k_mcg_pc0<TD>, grid, blk, 0, c.st, (const double*)r, (const TD*)P->d_y, z, S, P->d_state,
                          P->d_part, c.n);
     }
-    auto enq = [&]() { return mcg_enqueue_chunk<TD>(c, x, S, chunk, pk); };
-    if (int rc = run_chunks(P, 2 + 16 * pk, x, S, f, chunk, budget, enq, &s)) return rc;
+    auto enq = [&](int n) { return mcg_enqueue_chunk<TD>(c, x, S, n, pk); };
+    if (int rc = run_chunks(P, 2 + 16 * pk, x, S, f, chunk, budget, enq, &s, resid)) return rc;
     iters += s.iters;
     budget -= s.iters;
     if (s.nonfinite) return CB_E_NONFINITE;
