@@ -105,16 +105,27 @@ __device__ __forceinline__ const double* region(const double* part, int r) { ret
 
 // ---------------------------------------------------------------------------
 // Constrained CG (non-adhesive), one iteration =
-//   gap -> dir -> K t -> step -> update -> post [-> K p]
+//   gap -> dir -> K t -> step -> update [-> K p]
 // (preconditioned: gap -> gmask -> M^-1 gm -> zdot -> dir_pc -> K t -> ...)
 // The contact set Ic = {p > 0} is kept as a byte mask `act`, written by the
 // update, so that only the update reads p.  Under force control the stored
-// p and u lag the true ones by the factor st->pscale decided at the end of
-// the previous iteration: the gap and update kernels apply it as they read
-// (u recomputed from the stored p scales the same way, K being linear), the
-// update writes true values, and the solve applies the last factor at its
-// end.
+// p and u lag the true ones by the factor F / (dA sum p) of the previous
+// update's sum: every gap block folds that sum and applies the factor as
+// it reads u (u recomputed from the stored p scales the same way, K being
+// linear), block 0 leaves it in st->pscale for the update, which writes
+// true values, and the solve applies the last factor at its end.  The
+// recomputation K p after the update runs when a block of the update saw
+// a cell change state (it clears st->skip_u, which the gap set).
 // ---------------------------------------------------------------------------
+// Two-phase solve (two_phase = 1): after QUIET iterations without a change
+// of the contact set the direction switches to the inverse-symbol
+// preconditioner, which converges fastest on a settled set (one quiet
+// iteration measured best: 32.1 mean iterations on the N = 1024 force set
+// against 36.4 after two and 37.2 after three).
+constexpr int QUIET = 1;
+// u = K p is recomputed at least every REFRESH iterations (FP32 linear
+// updates drift), whatever the chunking.
+constexpr int REFRESH = 16;
 // stored gap g' = u + f - s (s = d, or under force control the shift
 // gbar[par], the previous mean); partials over Ic = {p > 0}:
 // S1 = sum g', S2 = sum g'^2, n, A1 = sum (s - f), A2 = sum (s - f)^2;
@@ -122,11 +133,32 @@ __device__ __forceinline__ const double* region(const double* part, int r) { ret
 template <typename TD>
 __global__ void __launch_bounds__(RT)
 k_pk_gap(const unsigned char* __restrict__ act, const double* __restrict__ u, const double* __restrict__ f,
-         TD* __restrict__ g, const SolverState* __restrict__ st, const double* __restrict__ gbar2,
-         double* part, int n, int par) {
+         TD* __restrict__ g, SolverState* __restrict__ st, const double* __restrict__ gbar2,
+         double* part, int nb, int n, int par, int two_phase) {
   if (st->done) return;
   const double s = st->force ? gbar2[par] : st->d_in;
-  const double sc = st->pscale;  // pending load factor of the stored u
+  // the previous update's totals: sum p, activations, clips, restarts
+  const bool mx4[4] = {false, false, false, false};
+  double a4[4];
+  fold<4>(region(part, R_UPD), nb, mx4, a4);
+  // pending load factor of the stored p and u (force control)
+  const double sc = (st->force && a4[0] > 0.0) ? st->Ftarget / (st->dA * a4[0]) : 1.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const bool changed = a4[1] > 0.0 || a4[2] > 0.0;
+    st->pscale = sc;
+    // u = K p is recomputed after this iteration's update if a cell then
+    // changes state (the update clears this) or every REFRESH iterations
+    st->skip_u = (st->iters + 1) % REFRESH == 0 ? 0 : 1;
+    if (two_phase && st->phase == 0) {
+      st->quiet = changed ? 0 : st->quiet + 1;
+      if (st->quiet >= QUIET) {
+        st->phase = 1;
+        st->switch_it = st->iters;
+        st->pskip[0] = 1;
+        st->pskip[2] = 0;
+      }
+    }
+  }
   double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, 0.0};
   const bool mx[7] = {false, false, false, false, false, true, true};
 #pragma unroll 4
@@ -334,7 +366,7 @@ k_pk_step(const unsigned char* __restrict__ act, const TD* __restrict__ g, const
 template <typename TD>
 __global__ void __launch_bounds__(RT)
 k_pk_update(double* __restrict__ p, double* __restrict__ u, const TD* __restrict__ g,
-            const TD* __restrict__ t, const TD* __restrict__ r, const SolverState* __restrict__ st, double* part,
+            const TD* __restrict__ t, const TD* __restrict__ r, SolverState* __restrict__ st, double* part,
             unsigned char* __restrict__ act, unsigned char* __restrict__ clip, int bounce_from, int nb, int n) {
   if (st->done) return;
   const bool mx4[4] = {false, false, false, false};
@@ -372,42 +404,11 @@ k_pk_update(double* __restrict__ p, double* __restrict__ u, const TD* __restrict
   }
   block_allreduce<4>(v, mx);
   write_partials<4>(region(part, R_UPD), v);
+  // a cell changed state in this block: u is recomputed from p (every
+  // block that writes, writes 0)
+  if (threadIdx.x == 0 && (v[1] > 0.0 || v[2] > 0.0)) st->skip_u = 0;
 }
 
-// One block: whether u must be recomputed from p (a cell changed state, or
-// a refresh is due), and under force control the rescale F / (dA sum p)
-// of p and u, which the next gap kernel applies as it reads them (u
-// recomputed from the unscaled p scales the same way, K being linear).
-// Two-phase solve (two_phase = 1): after QUIET iterations without a change
-// of the contact set the direction switches to the inverse-symbol
-// preconditioner, which converges fastest on a settled set (one quiet
-// iteration measured best: 32.1 mean iterations on the N = 1024 force set
-// against 36.4 after two and 37.2 after three).
-constexpr int QUIET = 1;
-// u = K p is recomputed at least every REFRESH iterations (FP32 linear
-// updates drift), whatever the chunking.
-constexpr int REFRESH = 16;
-__global__ void __launch_bounds__(RT) k_pk_post(SolverState* st, const double* part, int nb, int two_phase) {
-  if (st->done) return;
-  const bool mx4[4] = {false, false, false, false};
-  double a[4];
-  fold<4>(region(part, R_UPD), nb, mx4, a);
-  if (threadIdx.x == 0) {
-    const bool refresh = st->iters % REFRESH == 0;
-    const bool changed = a[1] > 0.0 || a[2] > 0.0;
-    st->skip_u = (refresh || changed) ? 0 : 1;
-    st->pscale = (st->force && a[0] > 0.0) ? st->Ftarget / (st->dA * a[0]) : 1.0;
-    if (two_phase && st->phase == 0) {
-      st->quiet = changed ? 0 : st->quiet + 1;
-      if (st->quiet >= QUIET) {
-        st->phase = 1;
-        st->switch_it = st->iters;
-        st->pskip[0] = 1;
-        st->pskip[2] = 0;
-      }
-    }
-  }
-}
 
 // the load factor still pending on the stored p and u when the iterations stop
 __global__ void __launch_bounds__(RT) k_pk_pending_scale(double* __restrict__ p, double* __restrict__ u,
@@ -936,7 +937,7 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
   for (int i = 0; i < chunk; i++) {
     const int par = i & 1;
     hipLaunchKernelGGL(k_pk_gap<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const double*)u, f, g, st, gb,
-                       part, c.n, par);
+                       part, c.nb, c.n, par, two ? 1 : 0);
     if (two) {
       if (hipError_t e = direction(pk0, 0, &st->pskip[0], par)) return e;
       if (hipError_t e = direction(2, 1, &st->pskip[2], par)) return e;
@@ -951,7 +952,6 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
     const bool clip = two || pk0 > 0;
     hipLaunchKernelGGL(k_pk_update<TD>, grid, blk, 0, c.st, p, u, (const TD*)g, (const TD*)t, (const TD*)r, st, part,
                        act, clip ? P->d_det : nullptr, pk0 > 0 ? 0 : 1, c.nb, c.n);
-    hipLaunchKernelGGL(k_pk_post, dim3(1), blk, 0, c.st, st, (const double*)part, c.nb, two ? 1 : 0);
     if (hipError_t e = apply64(c, p, u, skip_u)) return e;
   }
   return hipGetLastError();
@@ -1211,7 +1211,11 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
   CB_HIP(hipMemsetAsync(P->d_pold, 0, (size_t)c.n * 8, c.st));
   hipLaunchKernelGGL(k_zero_bytes, grid, blk, 0, c.st, P->d_det, c.n);  // clip flags of the preconditioned method
   hipLaunchKernelGGL(k_pk_seed, grid, blk, 0, c.st, (const double*)p, P->d_part, c.n);
-  if (force) hipLaunchKernelGGL(k_pk_scale0, grid, blk, 0, c.st, p, P->d_state, P->d_part, c.nb, c.n);
+  if (force) {
+    hipLaunchKernelGGL(k_pk_scale0, grid, blk, 0, c.st, p, P->d_state, P->d_part, c.nb, c.n);
+    // the first gap folds sum p from here: that of the scaled p
+    hipLaunchKernelGGL(k_pk_seed, grid, blk, 0, c.st, (const double*)p, P->d_part, c.n);
+  }
   hipLaunchKernelGGL(k_mask_from_p, grid, blk, 0, c.st, (const double*)p, P->d_mask2, c.n);
   CB_HIP(apply64(c, p, (double*)P->d_u, nullptr));
   SolverState s;
