@@ -112,9 +112,10 @@ typedef struct {
                         the inverse of the operator's symbol, 3 two-phase:
                         1 for coatings >= 3x stiffer than the substrate with
                         h <= L/16, else 0, until an iteration leaves the
-                        contact set unchanged, then 2.  Automatic: 3, but 2
-                        from a caller's guess (init = 1) unless the coating
-                        is stiff and thin as above.
+                        contact set unchanged, then 2.  Automatic: 2 from a
+                        start close to the contact (a caller's guess, the
+                        estimated force-control cold start), else 3; always
+                        3 on coatings stiff and thin as above.
                         Adhesive solves (CG on the contact set): 0, 1 or 2,
                         automatic 2.  The converged pressure is the same;
                         other values: CB_E_INVALID. */

@@ -901,7 +901,10 @@ template <typename TD>
 // pk: 0 plain, 1 preconditioned by 1/C(kh), 2 preconditioned by 1/K^
 // mode: 0 plain, 1 / 2 preconditioned by 1/C(kh) / 1/K^ throughout; 3 / 4
 // two-phase, plain / 1/C(kh) until the contact set settles, then 1/K^.
-static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, bool force, int mode, int chunk) {
+// second: a two-phase solve already past its switch (the host saw phase 1):
+// the first phase's block, which would only exit at entry, is left out.
+static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, bool force, int mode, int chunk,
+                                   bool second = false) {
   cb_plan_s* P = c.P;
   const bool two = mode >= 3;
   const int pk0 = two ? mode - 3 : mode;  // preconditioner of the first (or only) phase
@@ -939,7 +942,8 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
     hipLaunchKernelGGL(k_pk_gap<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const double*)u, f, g, st, gb,
                        part, c.nb, c.n, par, two ? 1 : 0);
     if (two) {
-      if (hipError_t e = direction(pk0, 0, &st->pskip[0], par)) return e;
+      if (!second)
+        if (hipError_t e = direction(pk0, 0, &st->pskip[0], par)) return e;
       if (hipError_t e = direction(2, 1, &st->pskip[2], par)) return e;
     } else if (hipError_t e = direction(pk0, -1, skip_done, par)) {
       return e;
@@ -1043,23 +1047,28 @@ static hipGraphExec_t chunk_graph(cb_plan_s* P, int kind, const void* a, const v
 // follows the residual's progress: the iterations still needed at the
 // rate of the last chunk (from r0 at iteration 0 for the first), rounded
 // up to a power of two in [2, chunk].  The first chunk is min(8, chunk).
-template <class Enq>
-static int run_chunks(cb_plan_s* P, int kind, const void* a, const void* b, const void* cc, int chunk, int max_iter,
-                      Enq enqueue, SolverState* out, double r0) {
+// A solve whose state reaches phase 1 continues with kind1 / enqueue1
+// (the same iteration without its first phase's kernels).
+template <class Enq, class Enq1>
+static int run_chunks(cb_plan_s* P, int kind, int kind1, const void* a, const void* b, const void* cc, int chunk,
+                      int max_iter, Enq enqueue, Enq1 enqueue1, SolverState* out, double r0) {
   int launched = 0, len = chunk < 8 ? chunk : 8;
   double r_prev = r0;
   int it_prev = 0;
+  bool second = false;
   while (true) {
     const int n = len;
-    hipGraphExec_t ex = chunk_graph(P, kind, a, b, cc, n, [&]() { return enqueue(n); });
+    hipGraphExec_t ex = second ? chunk_graph(P, kind1, a, b, cc, n, [&]() { return enqueue1(n); })
+                               : chunk_graph(P, kind, a, b, cc, n, [&]() { return enqueue(n); });
     if (ex) CB_HIP(hipGraphLaunch(ex, P->istream));
-    else CB_HIP(enqueue(n));
+    else CB_HIP(second ? enqueue1(n) : enqueue(n));
     launched += n;
     CB_HIP(hipMemcpyAsync(&P->h_state[0], P->d_state, sizeof(SolverState), hipMemcpyDeviceToHost, P->istream));
     CB_HIP(hipEventRecord(P->ev_state[0], P->istream));
     CB_HIP(hipEventSynchronize(P->ev_state[0]));
     const SolverState& s = P->h_state[0];
     if (s.done || s.nonfinite || launched >= max_iter) break;
+    second = second || s.phase == 1;
     len = chunk;
     if (r_prev > 0.0 && s.resid > 0.0 && s.resid < r_prev && s.iters > it_prev && s.tol > 0.0) {
       const double rate = (std::log(s.resid) - std::log(r_prev)) / (s.iters - it_prev);  // < 0
@@ -1127,7 +1136,8 @@ static SolverState base_state(const cb_plan_s* P, double tol, double d_in, bool 
 // of its iterations shrinking the contact set (CPU sweep of the N = 256
 // force set: 670 -> 473 iterations).  Too large a load for any overlap:
 // the uniform start.
-static int cold_start_force(const Ctx& c, const double* f, double fmin, double fmax, double F, double* p) {
+static int cold_start_force(const Ctx& c, const double* f, double fmin, double fmax, double F, double* p,
+                            bool* found_out) {
   cb_plan_s* P = c.P;
   const dim3 grid(c.nb), blk(RT);
   const double range = fmax - fmin;
@@ -1159,6 +1169,7 @@ static int cold_start_force(const Ctx& c, const double* f, double fmin, double f
       }
     }
   }
+  *found_out = found;
   if (found) hipLaunchKernelGGL(k_init_disp, grid, blk, 0, c.st, p, f, c.n, d0, P->k00);
   else hipLaunchKernelGGL(k_fill, grid, blk, 0, c.st, p, c.n, F / (P->dx * P->dx * c.n));
   CB_HIP(hipGetLastError());
@@ -1194,11 +1205,12 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
     res->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return CB_OK;
   }
-  // initial pressure
+  // initial pressure; `near`: a start whose support is close to the contact
+  bool near = guess;
   if (guess) {
     hipLaunchKernelGGL(k_clamp_pos, grid, blk, 0, c.st, p, c.n);
   } else if (force) {
-    if (int rc = cold_start_force(c, f, fmin, fmax, target, p)) return rc;
+    if (int rc = cold_start_force(c, f, fmin, fmax, target, p, &near)) return rc;
   } else {
     hipLaunchKernelGGL(k_init_disp, grid, blk, 0, c.st, p, f, c.n, target, P->k00);
   }
@@ -1219,19 +1231,25 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
   hipLaunchKernelGGL(k_mask_from_p, grid, blk, 0, c.st, (const double*)p, P->d_mask2, c.n);
   CB_HIP(apply64(c, p, (double*)P->d_u, nullptr));
   SolverState s;
-  // Automatic.  From a cold start, two-phase: while the contact set
+  // Automatic.  From a start far from the contact set (the uniform force
+  // start, the overlap of displacement control), two-phase: while the set
   // changes, each change restarts the directions, and the cheap plain (or,
   // on stiff thin coatings, layer-preconditioned) iteration wins; once the
-  // set holds, the inverse symbol finishes the solve fastest (N = 1024 force
-  // set: 32.1 mean iterations against 68 with plain or layer alone).  From
-  // a caller's guess, whose set is nearly right, the inverse symbol
-  // throughout, except on stiff thin coatings, where two-phase is kept.
+  // set holds, the inverse symbol finishes the solve fastest.  From a
+  // start whose support is close to the contact (a caller's guess, the
+  // estimated force start), the inverse symbol throughout (N = 1024 force
+  // set, the 26 other coatings: 281 iterations against 309 two-phase),
+  // except on stiff thin coatings, where two-phase is kept (434 against
+  // 810 over the set's 6).
   const int two = 3 + P->precond_auto;
   const int pk = op.precond == 3 ? two
                  : op.precond >= 0 ? op.precond
-                 : (guess && P->precond_auto == 0) ? 2 : two;
+                 : (near && P->precond_auto == 0) ? 2 : two;
   auto enq = [&](int n) { return pk_enqueue_chunk<TD>(c, p, f, force, pk, n); };
-  if (int rc = run_chunks(P, (force ? 1 : 0) + 4 * pk, p, f, nullptr, op.chunk, op.max_iter, enq, &s, 1.0)) return rc;
+  auto enq1 = [&](int n) { return pk_enqueue_chunk<TD>(c, p, f, force, pk, n, true); };
+  // kinds: 0..19 (force + 4 mode), and 32 + that for the second phase
+  const int kind = (force ? 1 : 0) + 4 * pk;
+  if (int rc = run_chunks(P, kind, 32 + kind, p, f, nullptr, op.chunk, op.max_iter, enq, enq1, &s, 1.0)) return rc;
   const int status = s.nonfinite ? CB_E_NONFINITE : (s.done ? CB_OK : CB_E_NOCONV);
   hipLaunchKernelGGL(k_pk_pending_scale, grid, blk, 0, c.st, p, (double*)P->d_u, P->d_state, c.n);
   hipLaunchKernelGGL(k_stats, grid, blk, 0, c.st, (const double*)p, (const double*)P->d_u,
@@ -1286,7 +1304,7 @@ static int set_solve(const Ctx& c, const double* f, double d, const unsigned cha
                          P->d_part, c.n);
     }
     auto enq = [&](int n) { return mcg_enqueue_chunk<TD>(c, x, S, n, pk); };
-    if (int rc = run_chunks(P, 2 + 16 * pk, x, S, f, chunk, budget, enq, &s, resid)) return rc;
+    if (int rc = run_chunks(P, 2 + 16 * pk, 2 + 16 * pk, x, S, f, chunk, budget, enq, enq, &s, resid)) return rc;
     iters += s.iters;
     budget -= s.iters;
     if (s.nonfinite) return CB_E_NONFINITE;
