@@ -265,7 +265,7 @@ int cb_sweep(cb_plan plan, const double* f, const double* d_steps_host,
  *   (cb_solve_indent; adhesive plans use the adhesive procedure), 1 =
  *   prescribed force F (cb_solve_force).  Every problem runs its own
  *   graph-captured iteration chunks on its plan's stream; up to `workers`
- *   problems (<= 0: 8) are in flight at once, largest (N^2) first.
+ *   problems (<= 0: 16) are in flight at once, largest (N^2) first.
  *   opts (nullable) applies to every problem.  out_host: n results, each
  *   with its own status.  Returns CB_OK if every problem succeeded, else
  *   the first failing status in problem order.  Blocks until all are done.
