@@ -153,6 +153,13 @@ typedef struct {
 } cb_plan_info;
 
 /*
+ * Device arrays passed to this library (pressures, profiles, displacements,
+ * and the fields of cb_apply_K / cb_apply_precond) must be 16-byte aligned:
+ * every device allocation is; a view that starts at an odd element offset
+ * is not, and is rejected with CB_E_INVALID.
+ */
+
+/*
  * cb_plan_create -- build the operator u = K p for one grid and material.
  *   Eq. 9-11 (Sec. 2): the transfer function is evaluated in FP64 from the
  *   normalised form of Eq. 9-10 at k = sqrt(kx^2 + ky^2) on the 2N-padded

@@ -1,6 +1,7 @@
 // Internal plan state and launch entry points of libcoatbem.
 #pragma once
 #include <cmath>
+#include <cstdint>
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -122,6 +123,9 @@ struct cb_plan_s {
 };
 
 namespace cb {
+// Device arrays are read and written in 16-byte vectors.
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 // Dimensionless coefficients of the normalised Eq. 9-10: with
 // mu_i = E_i / (2(1+nu_i)), alpha = mu1/mu2, kappa_i = 3 - 4 nu_i,
 // A/D = -a b, B/D = 4 b, 2C/D = -(a + b).

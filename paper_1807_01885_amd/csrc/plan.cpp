@@ -418,6 +418,7 @@ extern "C" int cb_apply_K(cb_plan P, const void* p, void* u) {
   if (!P) return cb_fail(CB_E_INVALID, "null plan");
   if (!p || !u) return cb_fail(CB_E_INVALID, "null array");
   if (p == u) return cb_fail(CB_E_INVALID, "u must not alias p");
+  if (!cb::aligned16(p) || !cb::aligned16(u)) return cb_fail(CB_E_INVALID, "p and u must be 16-byte aligned");
   CB_HIP(cb::launch_apply(P, p, u, P->stream));
   return CB_OK;
 }
@@ -426,6 +427,7 @@ extern "C" int cb_apply_precond(cb_plan P, int which, const void* x, void* y) {
   if (!P) return cb_fail(CB_E_INVALID, "null plan");
   if (which != 1 && which != 2) return cb_fail(CB_E_INVALID, "which must be 1 or 2");
   if (!x || !y) return cb_fail(CB_E_INVALID, "null array");
+  if (!cb::aligned16(x) || !cb::aligned16(y)) return cb_fail(CB_E_INVALID, "x and y must be 16-byte aligned");
   CB_HIP(cb::launch_apply(P, x, y, P->stream, 15, nullptr, which == 1 ? P->d_ptable : P->d_pinv));
   return CB_OK;
 }
@@ -434,6 +436,7 @@ extern "C" int cb_apply_K_stages(cb_plan P, const void* p, void* u, int stages) 
   if (!P) return cb_fail(CB_E_INVALID, "null plan");
   if (stages < 0 || stages > 7) return cb_fail(CB_E_INVALID, "stage_mask must be in [0, 7]");
   if (((stages & 1) && !p) || ((stages & 4) && !u)) return cb_fail(CB_E_INVALID, "null array");
+  if (!cb::aligned16(p) || !cb::aligned16(u)) return cb_fail(CB_E_INVALID, "p and u must be 16-byte aligned");
   CB_HIP(cb::launch_apply(P, p, u, P->stream, stages));
   return CB_OK;
 }

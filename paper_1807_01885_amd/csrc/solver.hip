@@ -102,6 +102,14 @@ __device__ __forceinline__ double* region(double* part, int r) { return part + (
 __device__ __forceinline__ const double* region(const double* part, int r) { return part + (size_t)r * REG_STRIDE; }
 
 #define GRID_LOOP(i, n) for (int i = blockIdx.x * RT + threadIdx.x; i < (n); i += gridDim.x * RT)
+// Two consecutive cells per thread and step (n = N^2 is even): 16-byte
+// loads of the FP64 arrays, which the widest kernels need to approach the
+// bandwidth (the arrays are 16-byte aligned, as the convolution requires).
+#define GRID_LOOP2(q, n) for (int q = blockIdx.x * RT + threadIdx.x; q < ((n) >> 1); q += gridDim.x * RT)
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+template <typename T> using vec2 = typename Vec2<T>::type;
 
 // ---------------------------------------------------------------------------
 // Constrained CG (non-adhesive), one iteration =
@@ -161,22 +169,31 @@ k_pk_gap(const unsigned char* __restrict__ act, const double* __restrict__ u, co
   }
   double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, -INFINITY, 0.0};
   const bool mx[7] = {false, false, false, false, false, true, true};
-#pragma unroll 4
-  GRID_LOOP(i, n) {
-    const double fi = f[i];
-    const double x = u[i] * sc + fi - s;
-    g[i] = (TD)x;
-    if (!isfinite(x)) v[6] = 1.0;
-    if (act[i]) {
-      const double a = s - fi;
-      v[0] += x;
-      v[1] += x * x;
-      v[2] += 1.0;
-      v[3] += a;
-      v[4] += a * a;
-    } else {
-      v[5] = fmax(v[5], -x);
+#pragma unroll 2
+  GRID_LOOP2(q, n) {
+    const double2 f2 = reinterpret_cast<const double2*>(f)[q];
+    const double2 u2 = reinterpret_cast<const double2*>(u)[q];
+    const uchar2 a2 = reinterpret_cast<const uchar2*>(act)[q];
+    const double fv[2] = {f2.x, f2.y}, uv[2] = {u2.x, u2.y};
+    const bool av[2] = {a2.x != 0, a2.y != 0};
+    TD gv[2];
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      const double x = uv[k] * sc + fv[k] - s;
+      gv[k] = (TD)x;
+      if (!isfinite(x)) v[6] = 1.0;
+      if (av[k]) {
+        const double a = s - fv[k];
+        v[0] += x;
+        v[1] += x * x;
+        v[2] += 1.0;
+        v[3] += a;
+        v[4] += a * a;
+      } else {
+        v[5] = fmax(v[5], -x);
+      }
     }
+    reinterpret_cast<vec2<TD>*>(g)[q] = vec2<TD>{gv[0], gv[1]};
   }
   block_allreduce<7>(v, mx);
   write_partials<7>(region(part, R_GAP0 + par), v);
@@ -254,8 +271,15 @@ k_pk_dir(const unsigned char* __restrict__ act, const TD* __restrict__ g, TD* __
     beta = Gp > 0.0 ? gt.G / Gp : 0.0;
   }
   const double m = gt.m;
-#pragma unroll 4
-  GRID_LOOP(i, n) t[i] = act[i] ? (TD)(((double)g[i] - m) + beta * (double)t[i]) : TD(0);
+#pragma unroll 2
+  GRID_LOOP2(q, n) {
+    const uchar2 a2 = reinterpret_cast<const uchar2*>(act)[q];
+    const vec2<TD> g2 = reinterpret_cast<const vec2<TD>*>(g)[q];
+    const vec2<TD> t2 = reinterpret_cast<const vec2<TD>*>(t)[q];
+    reinterpret_cast<vec2<TD>*>(t)[q] =
+        vec2<TD>{a2.x ? (TD)(((double)g2.x - m) + beta * (double)t2.x) : TD(0),
+                 a2.y ? (TD)(((double)g2.y - m) + beta * (double)t2.y) : TD(0)};
+  }
 }
 
 // preconditioned: convergence check and gm = Ic ? g : 0
@@ -272,8 +296,13 @@ k_pk_gmask(const unsigned char* __restrict__ act, const TD* __restrict__ g, TD* 
   if (record_check(gt, st, gbar2, s, par)) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) st->gnorm2 = gt.G;
   const double m = gt.m;
-#pragma unroll 4
-  GRID_LOOP(i, n) gm[i] = act[i] ? (TD)((double)g[i] - m) : TD(0);
+#pragma unroll 2
+  GRID_LOOP2(q, n) {
+    const uchar2 a2 = reinterpret_cast<const uchar2*>(act)[q];
+    const vec2<TD> g2 = reinterpret_cast<const vec2<TD>*>(g)[q];
+    reinterpret_cast<vec2<TD>*>(gm)[q] =
+        vec2<TD>{a2.x ? (TD)((double)g2.x - m) : TD(0), a2.y ? (TD)((double)g2.y - m) : TD(0)};
+  }
 }
 
 // preconditioned: partials over Ic of sum z', sum g z' (z' = M^-1 gm)
@@ -285,12 +314,18 @@ k_pk_zdot(const unsigned char* __restrict__ act, const TD* __restrict__ g, const
   const double m = st->gdev;
   double v[2] = {0.0, 0.0};
   const bool mx[2] = {false, false};
-#pragma unroll 4
-  GRID_LOOP(i, n) {
-    if (act[i]) {
-      const double z = (double)zp[i];
-      v[0] += z;
-      v[1] += ((double)g[i] - m) * z;
+#pragma unroll 2
+  GRID_LOOP2(q, n) {
+    const uchar2 a2 = reinterpret_cast<const uchar2*>(act)[q];
+    const vec2<TD> g2 = reinterpret_cast<const vec2<TD>*>(g)[q];
+    const vec2<TD> z2 = reinterpret_cast<const vec2<TD>*>(zp)[q];
+    if (a2.x) {
+      v[0] += (double)z2.x;
+      v[1] += ((double)g2.x - m) * (double)z2.x;
+    }
+    if (a2.y) {
+      v[0] += (double)z2.y;
+      v[1] += ((double)g2.y - m) * (double)z2.y;
     }
   }
   block_allreduce<2>(v, mx);
@@ -324,8 +359,15 @@ k_pk_dir_pc(const unsigned char* __restrict__ act, const TD* __restrict__ zp, TD
     fold<2>(region(part, R_PZ0 + (par ^ 1)), nb, mx2, b);
     beta = b[1] > 0.0 ? a[1] / b[1] : 0.0;
   }
-#pragma unroll 4
-  GRID_LOOP(i, n) t[i] = act[i] ? (TD)(((double)zp[i] - zbar) + beta * (double)t[i]) : TD(0);
+#pragma unroll 2
+  GRID_LOOP2(q, n) {
+    const uchar2 a2 = reinterpret_cast<const uchar2*>(act)[q];
+    const vec2<TD> z2 = reinterpret_cast<const vec2<TD>*>(zp)[q];
+    const vec2<TD> t2 = reinterpret_cast<const vec2<TD>*>(t)[q];
+    reinterpret_cast<vec2<TD>*>(t)[q] =
+        vec2<TD>{a2.x ? (TD)(((double)z2.x - zbar) + beta * (double)t2.x) : TD(0),
+                 a2.y ? (TD)(((double)z2.y - zbar) + beta * (double)t2.y) : TD(0)};
+  }
 }
 
 // partials over Ic: sum g t, sum r t, sum r, sum t (g = g' - gdev)
@@ -337,11 +379,22 @@ k_pk_step(const unsigned char* __restrict__ act, const TD* __restrict__ g, const
   const double m = st->gdev;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const bool mx[4] = {false, false, false, false};
-#pragma unroll 4
-  GRID_LOOP(i, n) {
-    if (act[i]) {
-      const double ti = (double)t[i], ri = (double)r[i];
-      v[0] += ((double)g[i] - m) * ti;
+#pragma unroll 2
+  GRID_LOOP2(q, n) {
+    const uchar2 a2 = reinterpret_cast<const uchar2*>(act)[q];
+    const vec2<TD> g2 = reinterpret_cast<const vec2<TD>*>(g)[q];
+    const vec2<TD> t2 = reinterpret_cast<const vec2<TD>*>(t)[q];
+    const vec2<TD> r2 = reinterpret_cast<const vec2<TD>*>(r)[q];
+    if (a2.x) {
+      const double ti = (double)t2.x, ri = (double)r2.x;
+      v[0] += ((double)g2.x - m) * ti;
+      v[1] += ri * ti;
+      v[2] += ri;
+      v[3] += ti;
+    }
+    if (a2.y) {
+      const double ti = (double)t2.y, ri = (double)r2.y;
+      v[0] += ((double)g2.y - m) * ti;
       v[1] += ri * ti;
       v[2] += ri;
       v[3] += ti;
@@ -382,25 +435,45 @@ k_pk_update(double* __restrict__ p, double* __restrict__ u, const TD* __restrict
   const bool bounce = clip && st->phase >= bounce_from;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   const bool mx[4] = {false, false, false, false};
-#pragma unroll 4
-  GRID_LOOP(i, n) {
-    double pi = p[i] * sc;
-    const bool on = pi > 0.0;
-    if (on) pi -= tau * (double)t[i];
-    double pn = pi > 0.0 ? pi : 0.0;
-    const bool clipped = on && pn == 0.0;
-    if (clipped) v[2] += 1.0;
-    const double gi = (double)g[i] - m;
-    if (pn == 0.0 && gi < -theta) {
-      pn = -tau * st->act_scale * gi;
-      v[1] += 1.0;
-      if (!bounce || !(clipped || clip[i])) v[3] += 1.0;
+  const double as = st->act_scale;
+#pragma unroll 2
+  GRID_LOOP2(q, n) {
+    const double2 p2 = reinterpret_cast<const double2*>(p)[q];
+    const double2 u2 = reinterpret_cast<const double2*>(u)[q];
+    const vec2<TD> t2 = reinterpret_cast<const vec2<TD>*>(t)[q];
+    const vec2<TD> g2 = reinterpret_cast<const vec2<TD>*>(g)[q];
+    const vec2<TD> r2 = reinterpret_cast<const vec2<TD>*>(r)[q];
+    uchar2 c2 = clip ? reinterpret_cast<const uchar2*>(clip)[q] : uchar2{0, 0};
+    const double pv[2] = {p2.x, p2.y}, uv[2] = {u2.x, u2.y};
+    const double tv[2] = {(double)t2.x, (double)t2.y}, gvv[2] = {(double)g2.x, (double)g2.y};
+    const double rv[2] = {(double)r2.x, (double)r2.y};
+    const bool cv[2] = {c2.x != 0, c2.y != 0};
+    double po[2], uo[2];
+    unsigned char ao[2], co[2];
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+      double pi = pv[k] * sc;
+      const bool on = pi > 0.0;
+      if (on) pi -= tau * tv[k];
+      double pn = pi > 0.0 ? pi : 0.0;
+      const bool clipped = on && pn == 0.0;
+      if (clipped) v[2] += 1.0;
+      const double gi = gvv[k] - m;
+      if (pn == 0.0 && gi < -theta) {
+        pn = -tau * as * gi;
+        v[1] += 1.0;
+        if (!bounce || !(clipped || cv[k])) v[3] += 1.0;
+      }
+      co[k] = clipped ? 1 : 0;
+      po[k] = pn;
+      ao[k] = pn > 0.0 ? 1 : 0;
+      uo[k] = uv[k] * sc - tau * rv[k];
+      v[0] += pn;
     }
-    if (clip) clip[i] = clipped ? 1 : 0;
-    p[i] = pn;
-    act[i] = pn > 0.0 ? 1 : 0;
-    u[i] = u[i] * sc - tau * (double)r[i];
-    v[0] += pn;
+    if (clip) reinterpret_cast<uchar2*>(clip)[q] = uchar2{co[0], co[1]};
+    reinterpret_cast<double2*>(p)[q] = double2{po[0], po[1]};
+    reinterpret_cast<uchar2*>(act)[q] = uchar2{ao[0], ao[1]};
+    reinterpret_cast<double2*>(u)[q] = double2{uo[0], uo[1]};
   }
   block_allreduce<4>(v, mx);
   write_partials<4>(region(part, R_UPD), v);
@@ -1413,6 +1486,7 @@ using namespace cb;
 extern "C" int cb_solve_indent(cb_plan P, const double* f, double d, double* p_io, unsigned char* mask_io,
                                const cb_solve_opts* o, cb_result* res) {
   if (!P || !f || !p_io || !res) return cb_fail(CB_E_INVALID, "null argument");
+  if (!aligned16(f) || !aligned16(p_io)) return cb_fail(CB_E_INVALID, "f and p must be 16-byte aligned");
   if (!std::isfinite(d)) return cb_fail(CB_E_INVALID, "d must be finite");
   if (P->dgamma > 0.0) {
     if (P->precision == CB_FP64) return adhesive_indent<double>(P, f, d, p_io, mask_io, o, res);
@@ -1425,6 +1499,7 @@ extern "C" int cb_solve_indent(cb_plan P, const double* f, double d, double* p_i
 extern "C" int cb_solve_force(cb_plan P, const double* f, double F, double* p_io, unsigned char* mask_io,
                               const cb_solve_opts* o, cb_result* res) {
   if (!P || !f || !p_io || !res) return cb_fail(CB_E_INVALID, "null argument");
+  if (!aligned16(f) || !aligned16(p_io)) return cb_fail(CB_E_INVALID, "f and p must be 16-byte aligned");
   if (!std::isfinite(F) || F < 0.0) return cb_fail(CB_E_INVALID, "F must be finite and >= 0");
   if (P->dgamma > 0.0) return cb_fail(CB_E_UNSUPPORTED, "force control is provided for non-adhesive plans");
   if (P->precision == CB_FP64) return pk_solve<double>(P, f, F, true, p_io, mask_io, o, res);
@@ -1435,6 +1510,7 @@ extern "C" int cb_sweep(cb_plan P, const double* f, const double* d_steps, int n
                         unsigned char* mask_state, const cb_solve_opts* o, cb_result* per_step) {
   if (!P || !f || !d_steps || !p_state || !mask_state || !per_step || nsteps < 0)
     return cb_fail(CB_E_INVALID, "null argument or negative step count");
+  if (!aligned16(f) || !aligned16(p_state)) return cb_fail(CB_E_INVALID, "f and p must be 16-byte aligned");
   if (!(P->dgamma > 0.0)) return cb_fail(CB_E_UNSUPPORTED, "sweep needs an adhesive plan (dgamma > 0)");
   for (int k = 0; k < nsteps; k++)
     if (!std::isfinite(d_steps[k])) return cb_fail(CB_E_INVALID, "non-finite displacement step");

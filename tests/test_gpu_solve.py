@@ -153,6 +153,17 @@ def test_error_paths(lib):
     # no overlap: zero pressure, OK
     res = lib.cb_solve_indent(plan, f, -1e-3, p)
     assert res["status"] == 0 and torch.count_nonzero(p).item() == 0
+    # arrays that start off a 16-byte boundary are refused, not misread
+    n = c.N * c.N
+    buf = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+    p_odd = buf[1:].view(c.N, c.N)
+    for args in ((f, p_odd), (buf[1:].view(c.N, c.N).copy_(f), p)):
+        with pytest.raises(lib.CoatbemError) as e:
+            lib.cb_solve_force(plan, args[0], 1e-3, args[1])
+        assert e.value.status == lib.CB_E_INVALID
+    with pytest.raises(lib.CoatbemError) as e:
+        lib.cb_apply_K(plan, f, p_odd)
+    assert e.value.status == lib.CB_E_INVALID
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
