@@ -153,7 +153,7 @@ typedef struct {
 } cb_plan_info;
 
 /*
- * Device arrays passed to this library (pressures, profiles, displacements,
+ * Device arrays passed to this library (pressures, profiles, masks, displacements,
  * and the fields of cb_apply_K / cb_apply_precond) must be 16-byte aligned:
  * every device allocation is; a view that starts at an odd element offset
  * is not, and is rejected with CB_E_INVALID.

@@ -566,8 +566,14 @@ k_mcg_zq(const TD* __restrict__ z, const TD* __restrict__ q, const unsigned char
   if (st->done) return;
   double v[1] = {0.0};
   const bool mx[1] = {false};
-#pragma unroll 4
-  GRID_LOOP(i, n) if (S[i]) v[0] += (double)z[i] * (double)q[i];
+#pragma unroll 2
+  GRID_LOOP2(k, n) {
+    const uchar2 s2 = reinterpret_cast<const uchar2*>(S)[k];
+    const vec2<TD> z2 = reinterpret_cast<const vec2<TD>*>(z)[k];
+    const vec2<TD> q2 = reinterpret_cast<const vec2<TD>*>(q)[k];
+    if (s2.x) v[0] += (double)z2.x * (double)q2.x;
+    if (s2.y) v[0] += (double)z2.y * (double)q2.y;
+  }
   block_allreduce<1>(v, mx);
   write_partials<1>(region(part, R_ZQ), v);
 }
@@ -664,17 +670,31 @@ k_mcg_upd_pc(double* __restrict__ x, double* __restrict__ r, TD* __restrict__ rt
   const double al = rho[0] / zq[0];
   double v[2] = {0.0, 0.0};
   const bool mx2[2] = {false, true};
-#pragma unroll 4
-  GRID_LOOP(i, n) {
-    double ri = 0.0;
-    if (S[i]) {
-      x[i] += al * (double)z[i];
-      ri = r[i] - al * (double)q[i];
-      r[i] = ri;
-      v[0] += ri * ri;
-      if (!isfinite(ri)) v[1] = 1.0;
+#pragma unroll 2
+  GRID_LOOP2(k, n) {
+    const uchar2 s2 = reinterpret_cast<const uchar2*>(S)[k];
+    const vec2<TD> z2 = reinterpret_cast<const vec2<TD>*>(z)[k];
+    const vec2<TD> q2 = reinterpret_cast<const vec2<TD>*>(q)[k];
+    double2 x2 = reinterpret_cast<const double2*>(x)[k];
+    double2 r2 = reinterpret_cast<const double2*>(r)[k];
+    double o0 = 0.0, o1 = 0.0;
+    if (s2.x) {
+      x2.x += al * (double)z2.x;
+      o0 = r2.x - al * (double)q2.x;
+      r2.x = o0;
+      v[0] += o0 * o0;
+      if (!isfinite(o0)) v[1] = 1.0;
     }
-    rt[i] = (TD)ri;
+    if (s2.y) {
+      x2.y += al * (double)z2.y;
+      o1 = r2.y - al * (double)q2.y;
+      r2.y = o1;
+      v[0] += o1 * o1;
+      if (!isfinite(o1)) v[1] = 1.0;
+    }
+    reinterpret_cast<double2*>(x)[k] = x2;
+    reinterpret_cast<double2*>(r)[k] = r2;
+    reinterpret_cast<vec2<TD>*>(rt)[k] = vec2<TD>{(TD)o0, (TD)o1};
   }
   block_allreduce<2>(v, mx2);
   write_partials<2>(region(part, R_RR0 + par), v);
@@ -701,8 +721,14 @@ k_mcg_ry(const double* __restrict__ r, const TD* __restrict__ y, const unsigned 
   if (stop) return;
   double v[1] = {0.0};
   const bool mx[1] = {false};
-#pragma unroll 4
-  GRID_LOOP(i, n) if (S[i]) v[0] += r[i] * (double)y[i];
+#pragma unroll 2
+  GRID_LOOP2(k, n) {
+    const uchar2 s2 = reinterpret_cast<const uchar2*>(S)[k];
+    const double2 r2 = reinterpret_cast<const double2*>(r)[k];
+    const vec2<TD> y2 = reinterpret_cast<const vec2<TD>*>(y)[k];
+    if (s2.x) v[0] += r2.x * (double)y2.x;
+    if (s2.y) v[0] += r2.y * (double)y2.y;
+  }
   block_allreduce<1>(v, mx);
   write_partials<1>(region(part, R_RY0 + par), v);
 }
@@ -718,8 +744,14 @@ k_mcg_dir_pc(TD* __restrict__ z, const TD* __restrict__ y, const unsigned char* 
   fold<1>(region(part, R_RY0 + par), nb, mx1, a);
   fold<1>(region(part, R_RY0 + (par ^ 1)), nb, mx1, b);
   const double beta = b[0] > 0.0 ? a[0] / b[0] : 0.0;
-#pragma unroll 4
-  GRID_LOOP(i, n) z[i] = S[i] ? (TD)((double)y[i] + beta * (double)z[i]) : TD(0);
+#pragma unroll 2
+  GRID_LOOP2(k, n) {
+    const uchar2 s2 = reinterpret_cast<const uchar2*>(S)[k];
+    const vec2<TD> y2 = reinterpret_cast<const vec2<TD>*>(y)[k];
+    const vec2<TD> z2 = reinterpret_cast<const vec2<TD>*>(z)[k];
+    reinterpret_cast<vec2<TD>*>(z)[k] = vec2<TD>{s2.x ? (TD)((double)y2.x + beta * (double)z2.x) : TD(0),
+                                                 s2.y ? (TD)((double)y2.y + beta * (double)z2.y) : TD(0)};
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1486,7 +1518,8 @@ using namespace cb;
 extern "C" int cb_solve_indent(cb_plan P, const double* f, double d, double* p_io, unsigned char* mask_io,
                                const cb_solve_opts* o, cb_result* res) {
   if (!P || !f || !p_io || !res) return cb_fail(CB_E_INVALID, "null argument");
-  if (!aligned16(f) || !aligned16(p_io)) return cb_fail(CB_E_INVALID, "f and p must be 16-byte aligned");
+  if (!aligned16(f) || !aligned16(p_io) || (mask_io && !aligned16(mask_io)))
+    return cb_fail(CB_E_INVALID, "f, p and mask must be 16-byte aligned");
   if (!std::isfinite(d)) return cb_fail(CB_E_INVALID, "d must be finite");
   if (P->dgamma > 0.0) {
     if (P->precision == CB_FP64) return adhesive_indent<double>(P, f, d, p_io, mask_io, o, res);
@@ -1499,7 +1532,8 @@ extern "C" int cb_solve_indent(cb_plan P, const double* f, double d, double* p_i
 extern "C" int cb_solve_force(cb_plan P, const double* f, double F, double* p_io, unsigned char* mask_io,
                               const cb_solve_opts* o, cb_result* res) {
   if (!P || !f || !p_io || !res) return cb_fail(CB_E_INVALID, "null argument");
-  if (!aligned16(f) || !aligned16(p_io)) return cb_fail(CB_E_INVALID, "f and p must be 16-byte aligned");
+  if (!aligned16(f) || !aligned16(p_io) || (mask_io && !aligned16(mask_io)))
+    return cb_fail(CB_E_INVALID, "f, p and mask must be 16-byte aligned");
   if (!std::isfinite(F) || F < 0.0) return cb_fail(CB_E_INVALID, "F must be finite and >= 0");
   if (P->dgamma > 0.0) return cb_fail(CB_E_UNSUPPORTED, "force control is provided for non-adhesive plans");
   if (P->precision == CB_FP64) return pk_solve<double>(P, f, F, true, p_io, mask_io, o, res);
@@ -1510,7 +1544,8 @@ extern "C" int cb_sweep(cb_plan P, const double* f, const double* d_steps, int n
                         unsigned char* mask_state, const cb_solve_opts* o, cb_result* per_step) {
   if (!P || !f || !d_steps || !p_state || !mask_state || !per_step || nsteps < 0)
     return cb_fail(CB_E_INVALID, "null argument or negative step count");
-  if (!aligned16(f) || !aligned16(p_state)) return cb_fail(CB_E_INVALID, "f and p must be 16-byte aligned");
+  if (!aligned16(f) || !aligned16(p_state) || !aligned16(mask_state))
+    return cb_fail(CB_E_INVALID, "f, p and mask must be 16-byte aligned");
   if (!(P->dgamma > 0.0)) return cb_fail(CB_E_UNSUPPORTED, "sweep needs an adhesive plan (dgamma > 0)");
   for (int k = 0; k < nsteps; k++)
     if (!std::isfinite(d_steps[k])) return cb_fail(CB_E_INVALID, "non-finite displacement step");
