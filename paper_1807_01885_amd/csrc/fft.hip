@@ -230,10 +230,11 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
 // ---------------------------------------------------------------------------
 // K3: inverse row transform (half spectrum -> first N real outputs)
 // ---------------------------------------------------------------------------
-template <typename T, int LOG2N, bool PAD, int RB, int NT1, int G>
+// EPI: the reduction of EpiArgs mode EPI (0: none) over the cells written.
+template <typename T, int LOG2N, bool PAD, int RB, int NT1, int G, int EPI = 0>
 __global__ void __launch_bounds__(G * RB * NT1)
 k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restrict__ tw_g,
-           const int* __restrict__ skip) {
+           const int* __restrict__ skip, EpiArgs ea) {
   if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
   constexpr int N = 1 << LOG2N, M = PAD ? 2 * N : N, L = M / 2, NC = L + 1;
@@ -309,12 +310,72 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
 #pragma unroll
       for (int i = 0; i < RL; i++) a[b][i] = line[padi<PS>(j + i * (L / RL))];
     }
+    constexpr int Q = EPI == 1 ? 4 : 2;
+    double v[Q] = {};
+    const size_t row = (size_t)blockIdx.x * ROWS + lrow;
+    double m = 0.0;
+    if constexpr (EPI != 0) m = ea.st->gdev;
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = t + b * NT1;
       butterfly<T, L, M, RL, L / RL, -1>(a[b], j, tw);
 #pragma unroll
-      for (int i = 0; i < (PAD ? RL / 2 : RL); i++) zo[j + i * (L / RL)] = a[b][i];
+      for (int i = 0; i < (PAD ? RL / 2 : RL); i++) {
+        const int c = j + i * (L / RL);
+        zo[c] = a[b][i];
+        if constexpr (EPI != 0) {
+          // cells 2c, 2c + 1 of this row: x = (a.x, a.y)
+          const size_t cell = row * N + 2 * c;
+          const uchar2 a2 = *reinterpret_cast<const uchar2*>(ea.act + cell);
+          const cx<T> g2 = *reinterpret_cast<const cx<T>*>(static_cast<const T*>(ea.g) + cell);
+          const double x0 = (double)a[b][i].x, x1 = (double)a[b][i].y;
+          const double g0 = (double)g2.x - m, g1 = (double)g2.y - m;
+          if constexpr (EPI == 1) {
+            const cx<T> t2 = *reinterpret_cast<const cx<T>*>(static_cast<const T*>(ea.t) + cell);
+            const double t0 = (double)t2.x, t1 = (double)t2.y;
+            if (a2.x) {
+              v[0] += g0 * t0;
+              v[1] += x0 * t0;
+              v[2] += x0;
+              v[3] += t0;
+            }
+            if (a2.y) {
+              v[0] += g1 * t1;
+              v[1] += x1 * t1;
+              v[2] += x1;
+              v[3] += t1;
+            }
+          } else {
+            if (a2.x) {
+              v[0] += x0;
+              v[1] += g0 * x0;
+            }
+            if (a2.y) {
+              v[0] += x1;
+              v[1] += g1 * x1;
+            }
+          }
+        }
+      }
+    }
+    if constexpr (EPI != 0) {
+      // fixed-order tree over the block, in the (now free) LDS
+      double* red = reinterpret_cast<double*>(smem_raw);
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < Q; q++) red[q * NTH + tid] = v[q];
+      __syncthreads();
+      for (int h = NTH / 2; h > 0; h >>= 1) {
+        if (tid < h) {
+#pragma unroll
+          for (int q = 0; q < Q; q++) red[q * NTH + tid] += red[q * NTH + tid + h];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+#pragma unroll
+        for (int q = 0; q < Q; q++) ea.region[8 + blockIdx.x * Q + q] = red[q * NTH];
+      }
     }
   }
 }
@@ -378,7 +439,7 @@ static size_t lds_need() {
 
 template <typename T, int LOG2N, bool PAD>
 static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T>* S, const T* Tq, const cx<T>* tw,
-                             hipStream_t st) {
+                             hipStream_t st, const EpiArgs* epi = nullptr) {
   using SH = Shape<LOG2N, PAD>;
   constexpr int N = SH::N, RB = row_tile<T>();
   constexpr int G = tiles_per_block<T, LOG2N, PAD>();
@@ -387,49 +448,68 @@ static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T
   auto k1 = k_rows_fwd<T, LOG2N, PAD, RB, SH::NT1, G>;
   auto k2 = k_cols<T, LOG2N, PAD, RB, SH::NT2, SH::CB>;
   auto k3 = k_rows_inv<T, LOG2N, PAD, RB, SH::NT1, G>;
+  // the reduction a K3 may carry: mode 1 on the padded (direction)
+  // convolution, mode 2 on the periodic (preconditioner) one
+  constexpr int EPI = PAD ? 1 : 2;
+  auto k3e = k_rows_inv<T, LOG2N, PAD, RB, SH::NT1, G, EPI>;
   static bool attr = false;
   if (!attr) {
     hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
     hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
     hipFuncSetAttribute((const void*)k3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
+    hipFuncSetAttribute((const void*)k3e, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
     attr = true;
   }
   const int nb_rows = N / (RB * G);
   const int nb_cols = (NC + SH::CB - 1) / SH::CB;
   if (stages & 1) hipLaunchKernelGGL(k1, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw, skip);
   if (stages & 2) hipLaunchKernelGGL(k2, dim3(nb_cols), dim3(SH::CB * SH::NT2), lc, st, S, Tq, tw, skip);
-  if (stages & 4) hipLaunchKernelGGL(k3, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw, skip);
+  if (stages & 4) {
+    if (epi && epi->mode != 0) {
+      if (epi->mode != EPI) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k3e, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw, skip, *epi);
+    } else {
+      hipLaunchKernelGGL(k3, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw, skip,
+                         EpiArgs{});
+    }
+  }
   return hipGetLastError();
+}
+
+template <typename T, int LOG2N, bool PAD>
+constexpr int rows_blocks_n() {
+  return (1 << LOG2N) / (row_tile<T>() * tiles_per_block<T, LOG2N, PAD>());
 }
 
 template <typename T, bool PAD>
 static hipError_t apply_dispatch(int stages, const int* skip, int log2n, const T* p, T* u, cx<T>* S, const T* Tq,
-                                 const cx<T>* tw, hipStream_t st) {
+                                 const cx<T>* tw, hipStream_t st, const EpiArgs* epi = nullptr) {
   switch (log2n) {
-    case 4: return apply_impl<T, 4, PAD>(stages, skip, p, u, S, Tq, tw, st);
-    case 5: return apply_impl<T, 5, PAD>(stages, skip, p, u, S, Tq, tw, st);
-    case 6: return apply_impl<T, 6, PAD>(stages, skip, p, u, S, Tq, tw, st);
-    case 7: return apply_impl<T, 7, PAD>(stages, skip, p, u, S, Tq, tw, st);
-    case 8: return apply_impl<T, 8, PAD>(stages, skip, p, u, S, Tq, tw, st);
-    case 9: return apply_impl<T, 9, PAD>(stages, skip, p, u, S, Tq, tw, st);
-    case 10: return apply_impl<T, 10, PAD>(stages, skip, p, u, S, Tq, tw, st);
-    case 11: return apply_impl<T, 11, PAD>(stages, skip, p, u, S, Tq, tw, st);
-    case 12: return apply_impl<T, 12, PAD>(stages, skip, p, u, S, Tq, tw, st);
+    case 4: return apply_impl<T, 4, PAD>(stages, skip, p, u, S, Tq, tw, st, epi);
+    case 5: return apply_impl<T, 5, PAD>(stages, skip, p, u, S, Tq, tw, st, epi);
+    case 6: return apply_impl<T, 6, PAD>(stages, skip, p, u, S, Tq, tw, st, epi);
+    case 7: return apply_impl<T, 7, PAD>(stages, skip, p, u, S, Tq, tw, st, epi);
+    case 8: return apply_impl<T, 8, PAD>(stages, skip, p, u, S, Tq, tw, st, epi);
+    case 9: return apply_impl<T, 9, PAD>(stages, skip, p, u, S, Tq, tw, st, epi);
+    case 10: return apply_impl<T, 10, PAD>(stages, skip, p, u, S, Tq, tw, st, epi);
+    case 11: return apply_impl<T, 11, PAD>(stages, skip, p, u, S, Tq, tw, st, epi);
+    case 12: return apply_impl<T, 12, PAD>(stages, skip, p, u, S, Tq, tw, st, epi);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T>
 static hipError_t apply_any(bool periodic, int stages, const int* skip, int log2n, const T* p, T* u, cx<T>* S,
-                            const T* Tq, hipStream_t st) {
-  return periodic ? apply_dispatch<T, false>(stages, skip, log2n, p, u, S, Tq, nullptr, st)
-                  : apply_dispatch<T, true>(stages, skip, log2n, p, u, S, Tq, nullptr, st);
+                            const T* Tq, hipStream_t st, const EpiArgs* epi) {
+  return periodic ? apply_dispatch<T, false>(stages, skip, log2n, p, u, S, Tq, nullptr, st, epi)
+                  : apply_dispatch<T, true>(stages, skip, log2n, p, u, S, Tq, nullptr, st, epi);
 }
 
 }  // namespace fftv<variant>
 
 hipError_t CB_CAT(launch_apply_v, CB_FFT_VARIANT)(const cb_plan_s* P, const void* p, void* u, hipStream_t st,
-                                                 int stages, const int* skip, const void* table, int prec) {
+                                                 int stages, const int* skip, const void* table, int prec,
+                                                 const EpiArgs* epi) {
   using namespace CB_CAT(fftv, CB_FFT_VARIANT);
   // stages bit 3: the N-periodic convolution (its table must be given)
   const bool periodic = (stages & 8) != 0;
@@ -438,11 +518,11 @@ hipError_t CB_CAT(launch_apply_v, CB_FFT_VARIANT)(const cb_plan_s* P, const void
   if (prec == 0) {
     if (!table) table = P->precision == 0 ? P->d_table : P->d_table64;
     return apply_any<double>(periodic, stages, skip, P->log2n, (const double*)p, (double*)u, (cx<double>*)P->d_S,
-                             (const double*)table, st);
+                             (const double*)table, st, epi);
   }
   if (!table) table = P->d_table;
   return apply_any<float>(periodic, stages, skip, P->log2n, (const float*)p, (float*)u, (cx<float>*)P->d_S,
-                          (const float*)table, st);
+                          (const float*)table, st, epi);
 }
 
 // Set the dynamic-LDS attributes of every convolution kernel of this size
@@ -459,6 +539,20 @@ static void prepare_n() {
   (void)apply_impl<double, LOG2N, false>(0, nullptr, nd, nd, nullptr, nullptr, nullptr, nullptr);
 }
 }  // namespace fftv<variant>
+
+int CB_CAT(rows_blocks_v, CB_FFT_VARIANT)(int log2n, int prec, int periodic) {
+  using namespace CB_CAT(fftv, CB_FFT_VARIANT);
+  switch (log2n) {
+#define CB_ROWS_CASE(k)                                                                               \
+  case k:                                                                                             \
+    return prec == 0 ? (periodic ? rows_blocks_n<double, k, false>() : rows_blocks_n<double, k, true>()) \
+                     : (periodic ? rows_blocks_n<float, k, false>() : rows_blocks_n<float, k, true>());
+    CB_ROWS_CASE(4) CB_ROWS_CASE(5) CB_ROWS_CASE(6) CB_ROWS_CASE(7)
+    CB_ROWS_CASE(8) CB_ROWS_CASE(9) CB_ROWS_CASE(10) CB_ROWS_CASE(11) CB_ROWS_CASE(12)
+#undef CB_ROWS_CASE
+    default: return 0;
+  }
+}
 
 size_t CB_CAT(lds_bytes_v, CB_FFT_VARIANT)(int log2n, int prec) {
   using namespace CB_CAT(fftv, CB_FFT_VARIANT);

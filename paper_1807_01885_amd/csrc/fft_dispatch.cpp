@@ -18,15 +18,25 @@
 
 namespace cb {
 
-using ApplyFn = hipError_t (*)(const cb_plan_s*, const void*, void*, hipStream_t, int, const int*, const void*, int);
+using ApplyFn = hipError_t (*)(const cb_plan_s*, const void*, void*, hipStream_t, int, const int*, const void*, int,
+                                const EpiArgs*);
 static const ApplyFn kApply[CB_FFT_VARIANTS] = {launch_apply_v0, launch_apply_v1, launch_apply_v2,
                                                 launch_apply_v3, launch_apply_v4, launch_apply_v5};
+using RowsFn = int (*)(int, int, int);
+static const RowsFn kRows[CB_FFT_VARIANTS] = {rows_blocks_v0, rows_blocks_v1, rows_blocks_v2,
+                                              rows_blocks_v3, rows_blocks_v4, rows_blocks_v5};
 
 hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages, const int* skip,
-                        const void* table, int prec) {
+                        const void* table, int prec, const EpiArgs* epi) {
   if (prec < 0) prec = P->precision;
   const int v = P->variant[prec == 0 ? 0 : 1];
-  return kApply[v](P, p, u, st, stages, skip, table, prec);
+  return kApply[v](P, p, u, st, stages, skip, table, prec, epi);
+}
+
+int rows_blocks(const cb_plan_s* P, int prec, bool periodic) {
+  if (prec < 0) prec = P->precision;
+  const int v = P->variant[prec == 0 ? 0 : 1];
+  return kRows[v](P->log2n, prec, periodic ? 1 : 0);
 }
 
 void prepare_apply(int log2n) {

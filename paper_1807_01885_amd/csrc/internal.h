@@ -55,7 +55,12 @@ struct SolverState {
 enum {
   R_GAP0 = 0, R_GAP1, R_STEP, R_UPD, R_RR0, R_RR1, R_ZQ, R_INIT, R_MISC, R_PZ0, R_PZ1, R_RY0, R_RY1, R_NUM
 };
-constexpr int RED_BLOCKS_MAX = 256;
+// partials of the solver kernels (<= 256 blocks) and of the inverse row
+// transforms that carry a reduction (N / row tile blocks, up to 2048)
+constexpr int RED_BLOCKS_MAX = 2048;
+// blocks of the solver's elementwise kernels: at most one 512-thread block
+// per CU (more lost throughput when concurrent solves share the GPU)
+constexpr int SOLVER_BLOCKS_MAX = 256;
 constexpr int REG_STRIDE = 8 + 8 * RED_BLOCKS_MAX;
 constexpr int SCRATCH_OFF = R_NUM * REG_STRIDE;   // 32 doubles of host-read results
 
@@ -152,15 +157,31 @@ namespace cb {
 // stages: bits 0..2 select K1..K3; bit 3 (8) runs the N-periodic
 // convolution instead of the padded one, with a (N/2+1)^2 table that must
 // be given (the preconditioner symbols).
+// Reduction carried by the inverse row transform (K3) of a convolution, on
+// the cells it writes (x = the output): mode 1, over act: sum (g - m) t,
+// sum x t, sum x, sum t; mode 2, over act: sum x, sum (g - m) x; m =
+// st->gdev.  One partial per K3 block, from `region` on (8 + block x Q).
+struct EpiArgs {
+  int mode = 0;
+  const unsigned char* act = nullptr;
+  const void* g = nullptr;
+  const void* t = nullptr;
+  const SolverState* st = nullptr;
+  double* region = nullptr;
+};
 hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages = 7,
-                        const int* skip = nullptr, const void* table = nullptr, int prec = -1);
+                        const int* skip = nullptr, const void* table = nullptr, int prec = -1,
+                        const EpiArgs* epi = nullptr);
+// blocks of the inverse row transform (the partials a K3 reduction writes)
+int rows_blocks(const cb_plan_s* P, int prec, bool periodic);
 inline size_t intermediate_elems(int N) { return (size_t)N * (N + 1); }
 // dynamic-LDS attributes of every variant's kernels for this size
 void prepare_apply(int log2n);
 // one variant's entry points (fft.hip compiled once per variant)
 #define CB_DECLARE_FFT_VARIANT(k)                                                                         \
   hipError_t launch_apply_v##k(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages,   \
-                               const int* skip, const void* table, int prec);                           \
+                               const int* skip, const void* table, int prec, const EpiArgs* epi);       \
+  int rows_blocks_v##k(int log2n, int prec, int periodic);                                               \
   void prepare_apply_v##k(int log2n);                                                                    \
   size_t lds_bytes_v##k(int log2n, int prec);
 CB_DECLARE_FFT_VARIANT(0)

@@ -288,7 +288,7 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
   {
     const long long n = (long long)N * N;
     long long nb = (n + 1023) / 1024;
-    P->nbr = (int)(nb < RED_BLOCKS_MAX ? (nb < 1 ? 1 : nb) : RED_BLOCKS_MAX);
+    P->nbr = (int)(nb < SOLVER_BLOCKS_MAX ? (nb < 1 ? 1 : nb) : SOLVER_BLOCKS_MAX);
   }
   alloc(&P->d_table, (size_t)NC * NC * es);
   alloc(&P->d_ptable, (size_t)NP * NP * es);

@@ -305,42 +305,15 @@ k_pk_gmask(const unsigned char* __restrict__ act, const TD* __restrict__ g, TD* 
   }
 }
 
-// preconditioned: partials over Ic of sum z', sum g z' (z' = M^-1 gm)
-template <typename TD>
-__global__ void __launch_bounds__(RT)
-k_pk_zdot(const unsigned char* __restrict__ act, const TD* __restrict__ g, const TD* __restrict__ zp,
-          const SolverState* __restrict__ st, double* part, int n, int par, int run_phase) {
-  if (st->done || (run_phase >= 0 && st->phase != run_phase)) return;
-  const double m = st->gdev;
-  double v[2] = {0.0, 0.0};
-  const bool mx[2] = {false, false};
-#pragma unroll 2
-  GRID_LOOP2(q, n) {
-    const uchar2 a2 = reinterpret_cast<const uchar2*>(act)[q];
-    const vec2<TD> g2 = reinterpret_cast<const vec2<TD>*>(g)[q];
-    const vec2<TD> z2 = reinterpret_cast<const vec2<TD>*>(zp)[q];
-    if (a2.x) {
-      v[0] += (double)z2.x;
-      v[1] += ((double)g2.x - m) * (double)z2.x;
-    }
-    if (a2.y) {
-      v[0] += (double)z2.y;
-      v[1] += ((double)g2.y - m) * (double)z2.y;
-    }
-  }
-  block_allreduce<2>(v, mx);
-  write_partials<2>(region(part, R_PZ0 + par), v);
-}
-
 // preconditioned: t = Ic ? (z' - mean) + beta t : 0, beta = (g.z)/(g.z)_prev
 template <typename TD>
 __global__ void __launch_bounds__(RT)
 k_pk_dir_pc(const unsigned char* __restrict__ act, const TD* __restrict__ zp, TD* __restrict__ t,
-            SolverState* __restrict__ st, double* part, int nb, int n, int par, int run_phase) {
+            SolverState* __restrict__ st, double* part, int nb, int nbz, int n, int par, int run_phase) {
   if (st->done || (run_phase >= 0 && st->phase != run_phase)) return;
   const bool mx2[2] = {false, false}, mx4[4] = {false, false, false, false};
   double a[2], u4[4];
-  fold<2>(region(part, R_PZ0 + par), nb, mx2, a);
+  fold<2>(region(part, R_PZ0 + par), nbz, mx2, a);
   fold<4>(region(part, R_UPD), nb, mx4, u4);
   const double nn = st->nact;
   const double zbar = (st->force && nn > 0.0) ? a[0] / nn : 0.0;
@@ -356,7 +329,7 @@ k_pk_dir_pc(const unsigned char* __restrict__ act, const TD* __restrict__ zp, TD
   // switch of preconditioner (the previous partials belong to another one)
   if (u4[3] == 0.0 && st->iters != st->switch_it + 1) {
     double b[2];
-    fold<2>(region(part, R_PZ0 + (par ^ 1)), nb, mx2, b);
+    fold<2>(region(part, R_PZ0 + (par ^ 1)), nbz, mx2, b);
     beta = b[1] > 0.0 ? a[1] / b[1] : 0.0;
   }
 #pragma unroll 2
@@ -368,40 +341,6 @@ k_pk_dir_pc(const unsigned char* __restrict__ act, const TD* __restrict__ zp, TD
         vec2<TD>{a2.x ? (TD)(((double)z2.x - zbar) + beta * (double)t2.x) : TD(0),
                  a2.y ? (TD)(((double)z2.y - zbar) + beta * (double)t2.y) : TD(0)};
   }
-}
-
-// partials over Ic: sum g t, sum r t, sum r, sum t (g = g' - gdev)
-template <typename TD>
-__global__ void __launch_bounds__(RT)
-k_pk_step(const unsigned char* __restrict__ act, const TD* __restrict__ g, const TD* __restrict__ t,
-          const TD* __restrict__ r, const SolverState* __restrict__ st, double* part, int n) {
-  if (st->done) return;
-  const double m = st->gdev;
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  const bool mx[4] = {false, false, false, false};
-#pragma unroll 2
-  GRID_LOOP2(q, n) {
-    const uchar2 a2 = reinterpret_cast<const uchar2*>(act)[q];
-    const vec2<TD> g2 = reinterpret_cast<const vec2<TD>*>(g)[q];
-    const vec2<TD> t2 = reinterpret_cast<const vec2<TD>*>(t)[q];
-    const vec2<TD> r2 = reinterpret_cast<const vec2<TD>*>(r)[q];
-    if (a2.x) {
-      const double ti = (double)t2.x, ri = (double)r2.x;
-      v[0] += ((double)g2.x - m) * ti;
-      v[1] += ri * ti;
-      v[2] += ri;
-      v[3] += ti;
-    }
-    if (a2.y) {
-      const double ti = (double)t2.y, ri = (double)r2.y;
-      v[0] += ((double)g2.y - m) * ti;
-      v[1] += ri * ti;
-      v[2] += ri;
-      v[3] += ti;
-    }
-  }
-  block_allreduce<4>(v, mx);
-  write_partials<4>(region(part, R_STEP), v);
 }
 
 // tau; p <- max(p - tau t, 0) on Ic; p = 0 and g < -theta -> p = -tau g
@@ -987,12 +926,14 @@ static int write_state(cb_plan_s* P, const SolverState& s) {
 }
 
 // direction-type convolution (plan precision), optionally with another table
-static hipError_t apply_dir(const Ctx& c, const void* x, void* y, const int* skip, const void* table = nullptr) {
-  return launch_apply(c.P, x, y, c.st, 7, skip, table, -1);
+static hipError_t apply_dir(const Ctx& c, const void* x, void* y, const int* skip, const void* table = nullptr,
+                            const EpiArgs* epi = nullptr) {
+  return launch_apply(c.P, x, y, c.st, 7, skip, table, -1, epi);
 }
 // Fourier preconditioner (N-periodic convolution with the symbol `table`)
-static hipError_t apply_pc(const Ctx& c, const void* x, void* y, const int* skip, const void* table) {
-  return launch_apply(c.P, x, y, c.st, 15, skip, table, -1);
+static hipError_t apply_pc(const Ctx& c, const void* x, void* y, const int* skip, const void* table,
+                           const EpiArgs* epi = nullptr) {
+  return launch_apply(c.P, x, y, c.st, 15, skip, table, -1, epi);
 }
 // FP64 convolution of the FP64 state
 static hipError_t apply64(const Ctx& c, const double* x, double* y, const int* skip) {
@@ -1025,6 +966,10 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
   const dim3 grid(c.nb), blk(RT);
   const int* skip_done = &st->done;   // {done, zero}
   const int* skip_u = &st->skip_u;    // {skip_u, done}
+  // blocks of the inverse row transforms that carry the step and z' sums
+  const int nb3d = rows_blocks(P, -1, false), nb3p = rows_blocks(P, -1, true);
+  // the fused row-transform sums write 4 (step) or 2 (z') partials per block
+  if (nb3d < 1 || nb3p < 1 || 4 * nb3d > REG_STRIDE - 8 || 2 * nb3p > REG_STRIDE - 8) return hipErrorInvalidValue;
   // the direction of one phase: pc_k 0 plain, else preconditioned by its table
   auto direction = [&](int pc_k, int run_phase, const int* skip, int par) -> hipError_t {
     if (pc_k == 0) {
@@ -1034,12 +979,17 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
     }
     hipLaunchKernelGGL(k_pk_gmask<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)g, gm, st, gb, part,
                        c.nb, c.n, par, run_phase);
-    // z' = M^-1 gm (into r, free until K t is formed)
-    if (hipError_t e = apply_pc(c, gm, r, skip, pc_k == 2 ? c.P->d_pinv : c.P->d_ptable)) return e;
-    hipLaunchKernelGGL(k_pk_zdot<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)g, (const TD*)r, st,
-                       part, c.n, par, run_phase);
+    // z' = M^-1 gm (into r, free until K t is formed); its inverse row
+    // transform also sums z' and (g - m) z' over the contact set
+    EpiArgs ez;
+    ez.mode = 2;
+    ez.act = act;
+    ez.g = g;
+    ez.st = st;
+    ez.region = part + (size_t)(R_PZ0 + par) * REG_STRIDE;
+    if (hipError_t e = apply_pc(c, gm, r, skip, pc_k == 2 ? c.P->d_pinv : c.P->d_ptable, &ez)) return e;
     hipLaunchKernelGGL(k_pk_dir_pc<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)r, t, st, part,
-                       c.nb, c.n, par, run_phase);
+                       c.nb, nb3p, c.n, par, run_phase);
     return hipSuccess;
   };
   for (int i = 0; i < chunk; i++) {
@@ -1053,14 +1003,20 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
     } else if (hipError_t e = direction(pk0, -1, skip_done, par)) {
       return e;
     }
-    if (hipError_t e = apply_dir(c, t, r, skip_done)) return e;
-    hipLaunchKernelGGL(k_pk_step<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)g, (const TD*)t,
-                       (const TD*)r, st, part, c.n);
+    // r = K t; its inverse row transform also forms the step's sums
+    EpiArgs es;
+    es.mode = 1;
+    es.act = act;
+    es.g = g;
+    es.t = t;
+    es.st = st;
+    es.region = part + (size_t)R_STEP * REG_STRIDE;
+    if (hipError_t e = apply_dir(c, t, r, skip_done, nullptr, &es)) return e;
     // the bounce rule of the preconditioned directions (from phase 0 when
     // that phase is preconditioned, else from the switch)
     const bool clip = two || pk0 > 0;
     hipLaunchKernelGGL(k_pk_update<TD>, grid, blk, 0, c.st, p, u, (const TD*)g, (const TD*)t, (const TD*)r, st, part,
-                       act, clip ? P->d_det : nullptr, pk0 > 0 ? 0 : 1, c.nb, c.n);
+                       act, clip ? P->d_det : nullptr, pk0 > 0 ? 0 : 1, nb3d, c.n);
     if (hipError_t e = apply64(c, p, u, skip_u)) return e;
   }
   return hipGetLastError();
