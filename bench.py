@@ -48,10 +48,10 @@ TOL_REF = 1e-10     # FP64 reference for the accuracy checks
 # WRITE x 1.0); the summary and commands are in profiles/.  Valid while the
 # FFT sources hash to `src` and the plan uses `variant`.
 K2_TRAFFIC = {"kernel": "k2_cols", "N": 1024, "precision": "fp32", "variant": 3,
-              "src": "cad614b7965ee3ea:f7e81aeadb45feb5",
-              "fetch_bytes": 6341.35 * 1024 * 2.0, "write_bytes": 8200.0 * 1024,
+              "src": "cf22cc8557d08d3e:f7e81aeadb45feb5",
+              "fetch_bytes": 6340.66 * 1024 * 2.0, "write_bytes": 8192.0 * 1024,
               # SQ_INSTS_VALU per launch (same probe, same conditions)
-              "valu_wave_insts": 3530100.0}
+              "valu_wave_insts": 3537334.0}
 # wave64 VALU instructions the chip issues per second without packed FP32:
 # 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per instruction on a 16-lane SIMD
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4

@@ -3,22 +3,28 @@
 //   K1  rows, forward real FFT of length M = 2N of each of the N rows
 //       (only the first N inputs non-zero), as a length-N complex FFT of
 //       the packed pairs (x[2n] + i x[2n+1]) followed by the standard
-//       even/odd split; writes the N+1 half-spectrum values of every row.
-//   K2  columns, for each of the N+1 half-spectrum columns: forward complex
+//       even/odd split; writes the N+1 half-spectrum values of every row,
+//       the two real ones (DC and Nyquist) packed into slot 0 as
+//       X[0] + i X[N].
+//   K2  columns, for each of the N half-spectrum columns (slot 0 carrying
+//       the DC and Nyquist columns, separated around the multiply): forward complex
 //       FFT of length M (first N inputs non-zero), multiply by the real
 //       transfer table K^(|k|)/M^2, inverse FFT of length M, keep the first
 //       N outputs.  The multiply sits between the last forward pass and the
 //       first inverse pass, both register-resident.
-//   K3  rows, inverse real FFT (Hermitian half spectrum -> first N of M
-//       real outputs).
+//   K3  rows, inverse real FFT (Hermitian half spectrum, slot 0 unpacked,
+//       -> first N of M real outputs).
 //
 // The same three kernels with PAD = false give the N-periodic convolution
 // (real transforms of length N, no zero padding, N/2 + 1 half-spectrum
 // columns): the solver's Fourier preconditioners are applied that way.
 //
 // Intermediate layout ("row tiles"): S[rb][kx][rr], rb = row / RB,
-// rr = row % RB, kx in [0, N], complex.  K1/K3 read and write whole tiles
-// (contiguous), K2 reads RB-element segments of a column.
+// rr = row % RB, kx in [0, N], complex; slot kx = N is allocated but
+// unused.  K1/K3 read and write whole tiles (contiguous), K2 reads
+// RB-element segments of a column.  With N + 1 columns one block of K2
+// would be left over after an even share per CU; packing the two real
+// columns removes it.
 //
 // This file is compiled once per launch-shape variant (CB_FFT_VARIANT =
 // 0 .. CB_FFT_VARIANTS-1): elements per thread in K1/K3 and in K2 and the
@@ -106,13 +112,20 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
       const int k = qq / RB;
       const int rr = qq - k * RB;
       const C* ln = buf + (g * RB + rr) * LP;
-      const C zk = ln[padi<PS>(k & (L - 1))];
-      const C zn = cconj(ln[padi<PS>((L - k) & (L - 1))]);
-      const C e = cscale(cadd(zk, zn), T(0.5));
-      const C o = cscale(csub(zk, zn), T(0.5));  // times -i below
-      const C w = tw.get(k);
-      const C wo = cmul(w, mul_mi<1>(o));
-      out[q] = cadd(e, wo);
+      if (k == 0) {
+        // X[0] and X[L] are real: both travel in slot 0 as X[0] + i X[L]
+        // (slot L is left unwritten and K2 runs one column fewer)
+        const C z0 = ln[padi<PS>(0)];
+        out[q] = C{z0.x + z0.y, z0.x - z0.y};
+      } else if (k < L) {
+        const C zk = ln[padi<PS>(k)];
+        const C zn = cconj(ln[padi<PS>(L - k)]);
+        const C e = cscale(cadd(zk, zn), T(0.5));
+        const C o = cscale(csub(zk, zn), T(0.5));  // times -i below
+        const C w = tw.get(k);
+        const C wo = cmul(w, mul_mi<1>(o));
+        out[q] = cadd(e, wo);
+      }
     }
   }
 }
@@ -126,10 +139,12 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
        const int* __restrict__ skip) {
   if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
-  constexpr int N = 1 << LOG2N, M = PAD ? 2 * N : N, L = M, NC = M / 2 + 1;
+  // NC half-spectrum columns; column 0 carries the DC and Nyquist columns
+  // packed (X[0] + i X[M/2], both real), so NC - 1 columns are transformed
+  constexpr int N = 1 << LOG2N, M = PAD ? 2 * N : N, L = M, NC = M / 2 + 1, NW = NC - 1;
   constexpr int NTH = CB * NT2, E = L / NT2;
   constexpr int LP = padded<PS>(L);
-  constexpr int NBLK = (NC + CB - 1) / CB;
+  constexpr int NBLK = (NW + CB - 1) / CB;
   using TW = Tw<T, M>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* tws = reinterpret_cast<C*>(smem_raw);
@@ -138,8 +153,9 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
   const int tid = threadIdx.x;
   const TW tw{tws, tws + TW::NLO};
   const int lc = tid / NT2, t = tid % NT2;
-  const int kx = xcd_block(blockIdx.x, NBLK) * CB + lc;
-  const bool active = kx < NC;
+  const int tile = xcd_block(blockIdx.x, NBLK);
+  const int kx = tile * CB + lc;
+  const bool active = kx < NW;
   C* line = buf + lc * LP;
 
   constexpr int R0 = pick_radix(L, E, 1);
@@ -183,19 +199,60 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
     }
     __syncthreads();
     const T* trow = Tq + (size_t)(active ? kx : 0) * NC;
+    if (tile != 0) {
 #pragma unroll
-    for (int b = 0; b < NB; b++) {
-      const int j = t + b * NT2;
-      butterfly<T, L, M, RL, L / RL, 1>(a[b], j, tw);
+      for (int b = 0; b < NB; b++) {
+        const int j = t + b * NT2;
+        butterfly<T, L, M, RL, L / RL, 1>(a[b], j, tw);
 #pragma unroll
-      for (int i = 0; i < RL; i++) {
-        const int ky = j + i * (L / RL);
-        const int kq = ky <= M / 2 ? ky : M - ky;
-        a[b][i] = cscale(a[b][i], trow[kq]);
+        for (int i = 0; i < RL; i++) {
+          const int ky = j + i * (L / RL);
+          const int kq = ky <= M / 2 ? ky : M - ky;
+          a[b][i] = cscale(a[b][i], trow[kq]);
+        }
+        dft<T, RL, -1>(a[b]);
+#pragma unroll
+        for (int i = 0; i < RL; i++) line[padi<PS>(out_index<RL, 1>(j, i))] = a[b][i];
       }
-      dft<T, RL, -1>(a[b]);
+    } else {
+      // the tile holding the packed column (block-uniform branch).  With
+      // Z = C0 + i CN, C0 and CN the transforms of two real columns,
+      // C0 = (Z[k] + conj Z[M-k]) / 2 and i CN = (Z[k] - conj Z[M-k]) / 2, so
+      // T0 C0 + i TN CN = (T0 + TN)/2 Z[k] + (T0 - TN)/2 conj Z[M-k], whose
+      // inverse is (T0 * x0) + i (TN * xN): both results stay packed.
 #pragma unroll
-      for (int i = 0; i < RL; i++) line[padi<PS>(out_index<RL, 1>(j, i))] = a[b][i];
+      for (int b = 0; b < NB; b++) {
+        const int j = t + b * NT2;
+        butterfly<T, L, M, RL, L / RL, 1>(a[b], j, tw);
+#pragma unroll
+        for (int i = 0; i < RL; i++) line[padi<PS>(j + i * (L / RL))] = a[b][i];
+      }
+      __syncthreads();
+      const T* tn = Tq + (size_t)(NC - 1) * NC;
+#pragma unroll
+      for (int b = 0; b < NB; b++) {
+        const int j = t + b * NT2;
+#pragma unroll
+        for (int i = 0; i < RL; i++) {
+          const int ky = j + i * (L / RL);
+          const int kq = ky <= M / 2 ? ky : M - ky;
+          if (kx == 0) {
+            const C zr = cconj(line[padi<PS>((L - ky) & (L - 1))]);
+            const T t0 = trow[kq], t1 = tn[kq];
+            a[b][i] = cadd(cscale(a[b][i], T(0.5) * (t0 + t1)), cscale(zr, T(0.5) * (t0 - t1)));
+          } else {
+            a[b][i] = cscale(a[b][i], trow[kq]);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < NB; b++) {
+        const int j = t + b * NT2;
+        dft<T, RL, -1>(a[b]);
+#pragma unroll
+        for (int i = 0; i < RL; i++) line[padi<PS>(out_index<RL, 1>(j, i))] = a[b][i];
+      }
     }
     __syncthreads();
   }
@@ -266,7 +323,14 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
         const int qq = q - g * (NC * RB);
         const int k = qq / RB;
         const int rr = qq - k * RB;
-        buf[(g * RB + rr) * LP + padi<PS>(k)] = v[it];
+        C* ln = buf + (g * RB + rr) * LP;
+        if (k == 0) {
+          // slot 0 holds X[0] + i X[L] (both real); slot L is unused
+          ln[padi<PS>(0)] = C{v[it].x, T(0)};
+          ln[padi<PS>(L)] = C{v[it].y, T(0)};
+        } else if (k < L) {
+          ln[padi<PS>(k)] = v[it];
+        }
       }
     }
   }
@@ -461,7 +525,7 @@ static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T
     attr = true;
   }
   const int nb_rows = N / (RB * G);
-  const int nb_cols = (NC + SH::CB - 1) / SH::CB;
+  const int nb_cols = (NC - 1 + SH::CB - 1) / SH::CB;  // DC and Nyquist columns packed
   if (stages & 1) hipLaunchKernelGGL(k1, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw, skip);
   if (stages & 2) hipLaunchKernelGGL(k2, dim3(nb_cols), dim3(SH::CB * SH::NT2), lc, st, S, Tq, tw, skip);
   if (stages & 4) {
