@@ -272,7 +272,10 @@ int cb_sweep(cb_plan plan, const double* f, const double* d_steps_host,
  *   (cb_solve_indent; adhesive plans use the adhesive procedure), 1 =
  *   prescribed force F (cb_solve_force).  Every problem runs its own
  *   graph-captured iteration chunks on its plan's stream; up to `workers`
- *   problems (<= 0: 16) are in flight at once, largest (N^2) first.
+ *   problems (<= 0: 16) are in flight at once.  They start in order of
+ *   expected length: larger N^2 first; within one N, adhesive approach
+ *   steps, then stiff thin coatings (E1* >= 3 E2*, h <= L/16) by
+ *   decreasing ratio of E1* to E2*, then the rest in the given order.
  *   opts (nullable) applies to every problem.  out_host: n results, each
  *   with its own status.  Returns CB_OK if every problem succeeded, else
  *   the first failing status in problem order.  Blocks until all are done.
