@@ -32,6 +32,7 @@
 // plan picks one (built-in default or the autotuner's choice).
 #include "fft_core.h"
 #include "internal.h"
+#include "pk_dev.h"
 
 #ifndef CB_FFT_VARIANT
 #define CB_FFT_VARIANT 0
@@ -51,10 +52,11 @@ constexpr int PS = 4;  // LDS padding shift
 // ---------------------------------------------------------------------------
 // K1: forward row transform
 // ---------------------------------------------------------------------------
-template <typename T, int LOG2N, bool PAD, int RB, int NT1, int G>
+// PRO: the input EpiArgs `pro` mode PRO forms (0: p as given).
+template <typename T, int LOG2N, bool PAD, int RB, int NT1, int G, int PRO = 0>
 __global__ void __launch_bounds__(G * RB * NT1)
 k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restrict__ tw_g,
-           const int* __restrict__ skip) {
+           const int* __restrict__ skip, EpiArgs ea) {
   if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
   // real transform length M, packed complex line L = M / 2
@@ -77,13 +79,51 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
   {
     constexpr int R = pick_radix(L, E, 1);
     constexpr int NB = L / (R * NT1);
-    const C* z = reinterpret_cast<const C*>(p + (size_t)(row0 + lrow) * N);
+    const size_t rowoff = (size_t)(row0 + lrow) * N;
+    const C* z = reinterpret_cast<const C*>(p + rowoff);
+    // the scalars of the input (every block folds the partials itself;
+    // the block-uniform return ends a converged solve's iteration here)
+    double xbar = 0.0, beta = 0.0;
+    const T* xs = nullptr;
+    if constexpr (PRO == 1) {
+      if (!masked_gradient_scalars<NTH>(ea, xbar)) return;
+      xs = static_cast<const T*>(ea.g);
+    } else if constexpr (PRO == 2) {
+      bool pre = false;
+      if (!direction_scalars<NTH>(ea, xbar, beta, pre)) return;
+      xs = static_cast<const T*>(pre ? ea.x : ea.g);
+    }
     C a[NB][R];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = t + b * NT1;
 #pragma unroll
-      for (int i = 0; i < R; i++) a[b][i] = (!PAD || i < R / 2) ? z[j + i * (L / R)] : C{T(0), T(0)};
+      for (int i = 0; i < R; i++) {
+        if (PAD && i >= R / 2) {
+          a[b][i] = C{T(0), T(0)};
+          continue;
+        }
+        const int pi = j + i * (L / R);  // pair (cells 2 pi, 2 pi + 1 of the row)
+        if constexpr (PRO == 0) {
+          a[b][i] = z[pi];
+        } else {
+          const size_t cell = rowoff + 2 * pi;
+          const uchar2 a2 = *reinterpret_cast<const uchar2*>(ea.act + cell);
+          const C x2 = *reinterpret_cast<const C*>(xs + cell);
+          if constexpr (PRO == 1) {
+            a[b][i] = C{a2.x ? (T)((double)x2.x - xbar) : T(0), a2.y ? (T)((double)x2.y - xbar) : T(0)};
+          } else {
+            // t is read and rewritten through tdir (the input pointer is
+            // declared restrict)
+            C* td = reinterpret_cast<C*>(static_cast<T*>(ea.tdir) + rowoff);
+            const C t2 = td[pi];
+            const C tn = C{a2.x ? (T)(((double)x2.x - xbar) + beta * (double)t2.x) : T(0),
+                           a2.y ? (T)(((double)x2.y - xbar) + beta * (double)t2.y) : T(0)};
+            td[pi] = tn;
+            a[b][i] = tn;
+          }
+        }
+      }
     }
     TW::compute(tws, tid, NTH);
 #pragma unroll
@@ -375,6 +415,8 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
       for (int i = 0; i < RL; i++) a[b][i] = line[padi<PS>(j + i * (L / RL))];
     }
     constexpr int Q = EPI == 1 ? 4 : 2;
+    // the reduction below reuses the LDS: Q x NTH doubles
+    static_assert(EPI == 0 || E >= 4, "row tile LDS too small for the K3 reductions");
     double v[Q] = {};
     const size_t row = (size_t)blockIdx.x * ROWS + lrow;
     double m = 0.0;
@@ -512,13 +554,17 @@ static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T
   auto k1 = k_rows_fwd<T, LOG2N, PAD, RB, SH::NT1, G>;
   auto k2 = k_cols<T, LOG2N, PAD, RB, SH::NT2, SH::CB>;
   auto k3 = k_rows_inv<T, LOG2N, PAD, RB, SH::NT1, G>;
-  // the reduction a K3 may carry: mode 1 on the padded (direction)
-  // convolution, mode 2 on the periodic (preconditioner) one
-  constexpr int EPI = PAD ? 1 : 2;
+  // the solver work the row transforms may carry: on the padded (direction)
+  // convolution the direction update (K1) and the step sums (K3), on the
+  // periodic (preconditioner) one the masked gradient (K1) and the sums of
+  // the preconditioned gradient (K3)
+  constexpr int EPI = PAD ? 1 : 2, PRO = PAD ? 2 : 1;
+  auto k1e = k_rows_fwd<T, LOG2N, PAD, RB, SH::NT1, G, PRO>;
   auto k3e = k_rows_inv<T, LOG2N, PAD, RB, SH::NT1, G, EPI>;
   static bool attr = false;
   if (!attr) {
     hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
+    hipFuncSetAttribute((const void*)k1e, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
     hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
     hipFuncSetAttribute((const void*)k3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
     hipFuncSetAttribute((const void*)k3e, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
@@ -526,11 +572,17 @@ static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T
   }
   const int nb_rows = N / (RB * G);
   const int nb_cols = (NC - 1 + SH::CB - 1) / SH::CB;  // DC and Nyquist columns packed
-  if (stages & 1) hipLaunchKernelGGL(k1, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw, skip);
+  if (epi && ((epi->mode != 0 && epi->mode != EPI) || (epi->pro != 0 && epi->pro != PRO)))
+    return hipErrorInvalidValue;
+  if (stages & 1) {
+    if (epi && epi->pro != 0)
+      hipLaunchKernelGGL(k1e, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw, skip, *epi);
+    else
+      hipLaunchKernelGGL(k1, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw, skip, EpiArgs{});
+  }
   if (stages & 2) hipLaunchKernelGGL(k2, dim3(nb_cols), dim3(SH::CB * SH::NT2), lc, st, S, Tq, tw, skip);
   if (stages & 4) {
     if (epi && epi->mode != 0) {
-      if (epi->mode != EPI) return hipErrorInvalidValue;
       hipLaunchKernelGGL(k3e, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw, skip, *epi);
     } else {
       hipLaunchKernelGGL(k3, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw, skip,

@@ -157,17 +157,40 @@ namespace cb {
 // stages: bits 0..2 select K1..K3; bit 3 (8) runs the N-periodic
 // convolution instead of the padded one, with a (N/2+1)^2 table that must
 // be given (the preconditioner symbols).
-// Reduction carried by the inverse row transform (K3) of a convolution, on
-// the cells it writes (x = the output): mode 1, over act: sum (g - m) t,
-// sum x t, sum x, sum t; mode 2, over act: sum x, sum (g - m) x; m =
-// st->gdev.  One partial per K3 block, from `region` on (8 + block x Q).
+// Solver work carried by the row transforms of a convolution.
+// K3 (inverse rows), `mode`, on the cells it writes (x = the output): 1,
+// over act: sum (g - m) t, sum x t, sum x, sum t; 2, over act: sum x,
+// sum (g - m) x; m = st->gdev.  One partial per K3 block, from `region` on
+// (8 + block x Q).
+// K1 (forward rows), `pro`, in place of reading its input: 1, the masked
+// gradient act ? g - m : 0, after the convergence check from the gap
+// kernel's partials (`gap`, `nb` blocks); 2, the search direction
+// t = act ? (x - xbar) + beta t : 0, written back to `tdir` and
+// transformed, with x, xbar and beta those of the plain method (x = g;
+// convergence check here) or of the preconditioned one (x = `x`, sums of
+// the preconditioner's K3 in `pz`, `nbz` blocks), whichever the phase
+// uses.  Every K1 block folds the partials itself.
 struct EpiArgs {
   int mode = 0;
+  int pro = 0;
   const unsigned char* act = nullptr;
   const void* g = nullptr;
   const void* t = nullptr;
-  const SolverState* st = nullptr;
+  SolverState* st = nullptr;
   double* region = nullptr;
+  const void* x = nullptr;
+  void* tdir = nullptr;
+  const double* gap = nullptr;
+  const double* gap_prev = nullptr;
+  const double* pz = nullptr;
+  const double* pz_prev = nullptr;
+  const double* upd = nullptr;
+  double* gbar2 = nullptr;
+  int nb = 0;
+  int nbz = 0;
+  int par = 0;
+  int plain0 = 0;  // the first (or only) phase uses the plain direction
+  int two = 0;     // two-phase solve
 };
 hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages = 7,
                         const int* skip = nullptr, const void* table = nullptr, int prec = -1,

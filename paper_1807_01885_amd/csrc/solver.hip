@@ -38,68 +38,9 @@
 #include <vector>
 
 #include "internal.h"
+#include "pk_dev.h"
 
 namespace cb {
-
-constexpr int RT = 512;  // threads per solver block (8 waves per CU at 256 blocks)
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Every thread receives the block totals (identical in all threads).
-template <int Q>
-__device__ __forceinline__ void block_allreduce(double (&v)[Q], const bool (&mx)[Q]) {
-  __shared__ double sh[RT / 64 * Q];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < Q; q++) v[q] = mx[q] ? wave_max(v[q]) : wave_sum(v[q]);
-  if (lane == 0) {
-#pragma unroll
-    for (int q = 0; q < Q; q++) sh[w * Q + q] = v[q];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < Q; q++) {
-    double a = sh[q];
-    for (int i = 1; i < RT / 64; i++) a = mx[q] ? fmax(a, sh[i * Q + q]) : a + sh[i * Q + q];
-    v[q] = a;
-  }
-  __syncthreads();
-}
-
-template <int Q>
-__device__ __forceinline__ void write_partials(double* region, const double (&v)[Q]) {
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < Q; q++) region[8 + blockIdx.x * Q + q] = v[q];
-  }
-}
-
-template <int Q>
-__device__ __forceinline__ void fold(const double* __restrict__ region, int nb, const bool (&mx)[Q],
-                                     double (&tot)[Q]) {
-#pragma unroll
-  for (int q = 0; q < Q; q++) tot[q] = mx[q] ? -INFINITY : 0.0;
-  for (int b = threadIdx.x; b < nb; b += RT) {
-#pragma unroll
-    for (int q = 0; q < Q; q++) {
-      const double x = region[8 + b * Q + q];
-      tot[q] = mx[q] ? fmax(tot[q], x) : tot[q] + x;
-    }
-  }
-  block_allreduce<Q>(tot, mx);
-}
-
-__device__ __forceinline__ double* region(double* part, int r) { return part + (size_t)r * REG_STRIDE; }
-__device__ __forceinline__ const double* region(const double* part, int r) { return part + (size_t)r * REG_STRIDE; }
 
 #define GRID_LOOP(i, n) for (int i = blockIdx.x * RT + threadIdx.x; i < (n); i += gridDim.x * RT)
 // Two consecutive cells per thread and step (n = N^2 is even): 16-byte
@@ -113,8 +54,14 @@ template <typename T> using vec2 = typename Vec2<T>::type;
 
 // ---------------------------------------------------------------------------
 // Constrained CG (non-adhesive), one iteration =
-//   gap -> dir -> K t -> step -> update [-> K p]
-// (preconditioned: gap -> gmask -> M^-1 gm -> zdot -> dir_pc -> K t -> ...)
+//   gap
+//   [-> z' = M^-1 (Ic (g - m)): K1 checks convergence and forms the masked
+//       gradient, K3 sums z' and (g - m) z' over Ic]
+//   -> r = K t: K1 forms the direction's scalars (the plain method: after
+//      the convergence check) and t, which it stores; K3 sums the step's
+//      terms
+//   -> update [-> K p]
+// (each K1 block folds the partials it needs itself)
 // The contact set Ic = {p > 0} is kept as a byte mask `act`, written by the
 // update, so that only the update reads p.  Under force control the stored
 // p and u lag the true ones by the factor F / (dA sum p) of the previous
@@ -197,150 +144,6 @@ k_pk_gap(const unsigned char* __restrict__ act, const double* __restrict__ u, co
   }
   block_allreduce<7>(v, mx);
   write_partials<7>(region(part, R_GAP0 + par), v);
-}
-
-struct GapTotals {
-  double m, G, resid, n, scale;
-  bool conv, nonfinite;
-};
-
-__device__ __forceinline__ GapTotals gap_totals(const double (&a)[7], const SolverState* st) {
-  GapTotals r;
-  const bool force = st->force;
-  const double nn = a[2];
-  r.n = nn;
-  r.m = (force && nn > 0.0) ? a[0] / nn : 0.0;
-  double G = force ? a[1] - a[0] * r.m : a[1];
-  G = G > 0.0 ? G : 0.0;
-  r.G = G;
-  const double rhs2 = force ? a[4] + 2.0 * r.m * a[3] + nn * r.m * r.m : a[4];
-  r.resid = rhs2 > 0.0 ? sqrt(G / rhs2) : sqrt(G);
-  const double scale = sqrt((rhs2 > 0.0 ? rhs2 : 0.0) / (nn > 1.0 ? nn : 1.0));
-  const double gmin_off = -a[5] - r.m;  // +inf when every cell is in contact
-  const bool viol = gmin_off < -st->tol * scale;
-  r.nonfinite = a[6] > 0.0;
-  r.conv = (r.resid <= st->tol) && !viol;
-  r.scale = scale;
-  return r;
-}
-
-// block 0 records the check; returns true when the solve stops here
-__device__ __forceinline__ bool record_check(const GapTotals& gt, SolverState* st, double* gbar2, double s,
-                                             int par) {
-  const bool stop = gt.conv || gt.nonfinite;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->iters += 1;
-    st->resid = gt.resid;
-    st->nact = gt.n;
-    st->gdev = gt.m;
-    st->theta = gt.resid * gt.scale;
-    if (st->force) {
-      st->d = s + gt.m;
-      gbar2[par ^ 1] = s + gt.m;
-    }
-    if (gt.nonfinite) st->nonfinite = 1;
-    if (stop) {
-      st->done = 1;
-      st->pskip[0] = st->pskip[2] = 1;
-    }
-  }
-  return stop;
-}
-
-// convergence check, conjugate coefficient, t = Ic ? g + beta t : 0
-template <typename TD>
-__global__ void __launch_bounds__(RT)
-k_pk_dir(const unsigned char* __restrict__ act, const TD* __restrict__ g, TD* __restrict__ t, SolverState* st,
-         double* gbar2, double* part, int nb, int n, int par, int run_phase) {
-  if (st->done || (run_phase >= 0 && st->phase != run_phase)) return;
-  const bool mx7[7] = {false, false, false, false, false, true, true};
-  const bool mx4[4] = {false, false, false, false};
-  double a[7], u4[4];
-  fold<7>(region(part, R_GAP0 + par), nb, mx7, a);
-  fold<4>(region(part, R_UPD), nb, mx4, u4);
-  const double s = st->force ? gbar2[par] : st->d_in;
-  const GapTotals gt = gap_totals(a, st);
-  if (record_check(gt, st, gbar2, s, par)) return;
-  double beta = 0.0;
-  if (u4[3] == 0.0) {  // no restart requested by the previous update
-    double b[7];
-    fold<7>(region(part, R_GAP0 + (par ^ 1)), nb, mx7, b);
-    const double nb2 = b[2];
-    const double mb = (st->force && nb2 > 0.0) ? b[0] / nb2 : 0.0;
-    const double Gp = st->force ? b[1] - b[0] * mb : b[1];
-    beta = Gp > 0.0 ? gt.G / Gp : 0.0;
-  }
-  const double m = gt.m;
-#pragma unroll 2
-  GRID_LOOP2(q, n) {
-    const uchar2 a2 = reinterpret_cast<const uchar2*>(act)[q];
-    const vec2<TD> g2 = reinterpret_cast<const vec2<TD>*>(g)[q];
-    const vec2<TD> t2 = reinterpret_cast<const vec2<TD>*>(t)[q];
-    reinterpret_cast<vec2<TD>*>(t)[q] =
-        vec2<TD>{a2.x ? (TD)(((double)g2.x - m) + beta * (double)t2.x) : TD(0),
-                 a2.y ? (TD)(((double)g2.y - m) + beta * (double)t2.y) : TD(0)};
-  }
-}
-
-// preconditioned: convergence check and gm = Ic ? g : 0
-template <typename TD>
-__global__ void __launch_bounds__(RT)
-k_pk_gmask(const unsigned char* __restrict__ act, const TD* __restrict__ g, TD* __restrict__ gm, SolverState* st,
-           double* gbar2, double* part, int nb, int n, int par, int run_phase) {
-  if (st->done || (run_phase >= 0 && st->phase != run_phase)) return;
-  const bool mx7[7] = {false, false, false, false, false, true, true};
-  double a[7];
-  fold<7>(region(part, R_GAP0 + par), nb, mx7, a);
-  const double s = st->force ? gbar2[par] : st->d_in;
-  const GapTotals gt = gap_totals(a, st);
-  if (record_check(gt, st, gbar2, s, par)) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->gnorm2 = gt.G;
-  const double m = gt.m;
-#pragma unroll 2
-  GRID_LOOP2(q, n) {
-    const uchar2 a2 = reinterpret_cast<const uchar2*>(act)[q];
-    const vec2<TD> g2 = reinterpret_cast<const vec2<TD>*>(g)[q];
-    reinterpret_cast<vec2<TD>*>(gm)[q] =
-        vec2<TD>{a2.x ? (TD)((double)g2.x - m) : TD(0), a2.y ? (TD)((double)g2.y - m) : TD(0)};
-  }
-}
-
-// preconditioned: t = Ic ? (z' - mean) + beta t : 0, beta = (g.z)/(g.z)_prev
-template <typename TD>
-__global__ void __launch_bounds__(RT)
-k_pk_dir_pc(const unsigned char* __restrict__ act, const TD* __restrict__ zp, TD* __restrict__ t,
-            SolverState* __restrict__ st, double* part, int nb, int nbz, int n, int par, int run_phase) {
-  if (st->done || (run_phase >= 0 && st->phase != run_phase)) return;
-  const bool mx2[2] = {false, false}, mx4[4] = {false, false, false, false};
-  double a[2], u4[4];
-  fold<2>(region(part, R_PZ0 + par), nbz, mx2, a);
-  fold<4>(region(part, R_UPD), nb, mx4, u4);
-  const double nn = st->nact;
-  const double zbar = (st->force && nn > 0.0) ? a[0] / nn : 0.0;
-  // A cell that becomes active takes the step -tau * act_scale * g: the
-  // direction t = M^-1 g is on a different scale from g (M^-1 damps the
-  // long waves by up to E2*/E1*), so -tau * g alone would overshoot there.
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const double G = st->gnorm2;
-    st->act_scale = (G > 0.0 && a[1] > 0.0) ? a[1] / G : 1.0;
-  }
-  double beta = 0.0;
-  // no conjugation across a restart, nor in the first iteration after the
-  // switch of preconditioner (the previous partials belong to another one)
-  if (u4[3] == 0.0 && st->iters != st->switch_it + 1) {
-    double b[2];
-    fold<2>(region(part, R_PZ0 + (par ^ 1)), nbz, mx2, b);
-    beta = b[1] > 0.0 ? a[1] / b[1] : 0.0;
-  }
-#pragma unroll 2
-  GRID_LOOP2(q, n) {
-    const uchar2 a2 = reinterpret_cast<const uchar2*>(act)[q];
-    const vec2<TD> z2 = reinterpret_cast<const vec2<TD>*>(zp)[q];
-    const vec2<TD> t2 = reinterpret_cast<const vec2<TD>*>(t)[q];
-    reinterpret_cast<vec2<TD>*>(t)[q] =
-        vec2<TD>{a2.x ? (TD)(((double)z2.x - zbar) + beta * (double)t2.x) : TD(0),
-                 a2.y ? (TD)(((double)z2.y - zbar) + beta * (double)t2.y) : TD(0)};
-  }
 }
 
 // tau; p <- max(p - tau t, 0) on Ic; p = 0 and g < -theta -> p = -tau g
@@ -959,7 +762,6 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
   unsigned char* act = P->d_mask2;  // contact set {p > 0}
   TD* t = (TD*)P->d_t;
   TD* r = (TD*)P->d_r;
-  TD* gm = (TD*)P->d_pold;
   SolverState* st = P->d_state;
   double* part = P->d_part;
   double* gb = gbar2_ptr(P);
@@ -970,27 +772,27 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
   const int nb3d = rows_blocks(P, -1, false), nb3p = rows_blocks(P, -1, true);
   // the fused row-transform sums write 4 (step) or 2 (z') partials per block
   if (nb3d < 1 || nb3p < 1 || 4 * nb3d > REG_STRIDE - 8 || 2 * nb3p > REG_STRIDE - 8) return hipErrorInvalidValue;
-  // the direction of one phase: pc_k 0 plain, else preconditioned by its table
-  auto direction = [&](int pc_k, int run_phase, const int* skip, int par) -> hipError_t {
-    if (pc_k == 0) {
-      hipLaunchKernelGGL(k_pk_dir<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)g, t, st, gb, part,
-                         c.nb, c.n, par, run_phase);
-      return hipSuccess;
-    }
-    hipLaunchKernelGGL(k_pk_gmask<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)g, gm, st, gb, part,
-                       c.nb, c.n, par, run_phase);
-    // z' = M^-1 gm (into r, free until K t is formed); its inverse row
-    // transform also sums z' and (g - m) z' over the contact set
+  double* pgap = part + (size_t)(R_GAP0) * REG_STRIDE;
+  double* ppz = part + (size_t)(R_PZ0) * REG_STRIDE;
+  // The preconditioned gradient of one phase (none for the plain method):
+  // the periodic convolution's forward row transform checks convergence and
+  // forms the masked gradient from g, z' = M^-1 of it goes into r (free
+  // until K t is formed), its inverse row transform sums z' and (g - m) z'
+  // over the contact set.
+  auto precondition = [&](int pc_k, const int* skip, int par) -> hipError_t {
+    if (pc_k == 0) return hipSuccess;
     EpiArgs ez;
     ez.mode = 2;
+    ez.pro = 1;
     ez.act = act;
     ez.g = g;
     ez.st = st;
-    ez.region = part + (size_t)(R_PZ0 + par) * REG_STRIDE;
-    if (hipError_t e = apply_pc(c, gm, r, skip, pc_k == 2 ? c.P->d_pinv : c.P->d_ptable, &ez)) return e;
-    hipLaunchKernelGGL(k_pk_dir_pc<TD>, grid, blk, 0, c.st, (const unsigned char*)act, (const TD*)r, t, st, part,
-                       c.nb, nb3p, c.n, par, run_phase);
-    return hipSuccess;
+    ez.region = ppz + (size_t)par * REG_STRIDE;
+    ez.gap = pgap + (size_t)par * REG_STRIDE;
+    ez.gbar2 = gb;
+    ez.nb = c.nb;
+    ez.par = par;
+    return apply_pc(c, g, r, skip, pc_k == 2 ? P->d_pinv : P->d_ptable, &ez);
   };
   for (int i = 0; i < chunk; i++) {
     const int par = i & 1;
@@ -998,19 +800,34 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
                        part, c.nb, c.n, par, two ? 1 : 0);
     if (two) {
       if (!second)
-        if (hipError_t e = direction(pk0, 0, &st->pskip[0], par)) return e;
-      if (hipError_t e = direction(2, 1, &st->pskip[2], par)) return e;
-    } else if (hipError_t e = direction(pk0, -1, skip_done, par)) {
+        if (hipError_t e = precondition(pk0, &st->pskip[0], par)) return e;
+      if (hipError_t e = precondition(2, &st->pskip[2], par)) return e;
+    } else if (hipError_t e = precondition(pk0, skip_done, par)) {
       return e;
     }
-    // r = K t; its inverse row transform also forms the step's sums
+    // the forward row transform forms the direction (plain, or from z' in r)
+    // and stores t; r = K t; the inverse row transform forms the step's sums
     EpiArgs es;
     es.mode = 1;
+    es.pro = 2;
     es.act = act;
     es.g = g;
     es.t = t;
     es.st = st;
     es.region = part + (size_t)R_STEP * REG_STRIDE;
+    es.x = r;
+    es.tdir = t;
+    es.gap = pgap + (size_t)par * REG_STRIDE;
+    es.gap_prev = pgap + (size_t)(par ^ 1) * REG_STRIDE;
+    es.pz = ppz + (size_t)par * REG_STRIDE;
+    es.pz_prev = ppz + (size_t)(par ^ 1) * REG_STRIDE;
+    es.upd = part + (size_t)R_UPD * REG_STRIDE;
+    es.gbar2 = gb;
+    es.nb = c.nb;
+    es.nbz = nb3p;
+    es.par = par;
+    es.plain0 = pk0 == 0 ? 1 : 0;
+    es.two = two ? 1 : 0;
     if (hipError_t e = apply_dir(c, t, r, skip_done, nullptr, &es)) return e;
     // the bounce rule of the preconditioned directions (from phase 0 when
     // that phase is preconditioned, else from the switch)
