@@ -1,7 +1,11 @@
 // Device helpers shared by the constrained-CG kernels and the row
 // transforms that carry part of an iteration's work: block reductions, the
 // per-block partial sums, the convergence check and the scalars of the
-// search direction.
+// search direction.  Inside the iteration the forward row transform (K1)
+// forms its own input (the masked gradient, or the search direction, which
+// it stores) from arrays already in HBM after folding the partial sums it
+// needs, and the inverse row transform (K3) sums the products of its
+// output with the contact set's arrays as it writes it (EpiArgs).
 #pragma once
 
 #include <hip/hip_runtime.h>
