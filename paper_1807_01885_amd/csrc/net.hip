@@ -321,8 +321,24 @@ constexpr int RP = 64;
 // partial minima of f over N*N
 __global__ void __launch_bounds__(256) k_fmin(const double* __restrict__ f, int n, double* part) {
   __shared__ double sh[256];
-  double m = INFINITY;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += RP * 256) m = fmin(m, f[e]);
+  // 16-byte loads, four independent minima per thread (n even: N x N, N >= 8)
+  double m0 = INFINITY, m1 = INFINITY, m2 = INFINITY, m3 = INFINITY;
+  const double2* f2 = reinterpret_cast<const double2*>(f);
+  const int n2 = n >> 1, stride = RP * 256;
+  int e = blockIdx.x * 256 + threadIdx.x;
+  for (; e + stride < n2; e += 2 * stride) {
+    const double2 a = f2[e], b = f2[e + stride];
+    m0 = fmin(m0, a.x);
+    m1 = fmin(m1, a.y);
+    m2 = fmin(m2, b.x);
+    m3 = fmin(m3, b.y);
+  }
+  if (e < n2) {
+    const double2 a = f2[e];
+    m0 = fmin(m0, a.x);
+    m1 = fmin(m1, a.y);
+  }
+  const double m = fmin(fmin(m0, m1), fmin(m2, m3));
   sh[threadIdx.x] = m;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -405,7 +421,10 @@ __device__ __forceinline__ double qcut(const float* Z16, int G, int yy, int xx, 
 __global__ void k_prolong(const float* __restrict__ Z16, int G, int N, const double* meanp, double cut,
                           double* __restrict__ p) {
   const int tot = N * N;
-  const double im = ((double)G * G) / fold_sum(meanp);
+  __shared__ double im_s;
+  if (threadIdx.x == 0) im_s = ((double)G * G) / fold_sum(meanp);
+  __syncthreads();
+  const double im = im_s;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
     const int y = e / N, x = e % N;
     double v;
@@ -683,6 +702,7 @@ __global__ void k_fill0(double* __restrict__ p, long long n) {
 static int features_into(cb_net N, const double* f, int Nf, double L, double h, double E1, double nu1, double E2,
                          double nu2, double F, float* x, int slot) {
   if (!N || !f || !x) return cb_fail(CB_E_INVALID, "null argument");
+  if (!cb::aligned16(f)) return cb_fail(CB_E_INVALID, "f must be 16-byte aligned");
   if (N->H != N->W) return cb_fail(CB_E_INVALID, "square net grid required");
   const int G = N->H;
   if (Nf < 8 || (Nf % G != 0 && G % Nf != 0)) return cb_fail(CB_E_INVALID, "N must divide or be a multiple of the net grid");
