@@ -189,6 +189,24 @@ def test_features(lib, Nf):
     np.testing.assert_allclose(x.double().cpu().numpy(), ref, rtol=1e-6, atol=1e-6)
 
 
+def test_features_rejects_misaligned_profile(lib):
+    """The feature kernel reads f 16 bytes at a time: a view starting at an
+    odd element is refused, and the aligned copy of the same profile gives
+    the reference features."""
+    Nf, L = 128, 1.0
+    f = inputs.cone(Nf, L, 0.11)
+    net = lib.cb_net_create(1, 256, 256)
+    x = torch.empty((256, 256, 16), dtype=torch.float32, device="cuda")
+    args = (L, 0.013, 7.5, 0.31, 1.0, 0.27, 2.2e-3)
+    buf = torch.empty(Nf * Nf + 1, dtype=torch.float64, device="cuda")
+    view = buf[1:].view(Nf, Nf)
+    view.copy_(torch.tensor(f, dtype=torch.float64))
+    with pytest.raises(lib.CoatbemError):
+        lib.cb_net_features(net, view, *args, x)
+    lib.cb_net_features(net, view.clone(), *args, x)
+    np.testing.assert_allclose(x.double().cpu().numpy(), nr.features(f, 256, *args), rtol=1e-6, atol=1e-6)
+
+
 @pytest.mark.parametrize("N", [512, 256, 128])
 def test_warmstart_prolongation(lib, N):
     """The initial pressure equals the reference network's output carried
