@@ -30,6 +30,8 @@
 // 0 .. CB_FFT_VARIANTS-1): elements per thread in K1/K3 and in K2 and the
 // row-tile height differ, each variant lives in its own namespace, and the
 // plan picks one (built-in default or the autotuner's choice).
+#include <atomic>
+
 #include "fft_core.h"
 #include "internal.h"
 #include "pk_dev.h"
@@ -561,14 +563,17 @@ static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T
   constexpr int EPI = PAD ? 1 : 2, PRO = PAD ? 2 : 1;
   auto k1e = k_rows_fwd<T, LOG2N, PAD, RB, SH::NT1, G, PRO>;
   auto k3e = k_rows_inv<T, LOG2N, PAD, RB, SH::NT1, G, EPI>;
-  static bool attr = false;
-  if (!attr) {
+  // set once per instantiation (plan creation calls this before any
+  // capture; plans may be created on several threads, and setting the
+  // attributes twice is harmless)
+  static std::atomic<bool> attr{false};
+  if (!attr.load(std::memory_order_acquire)) {
     hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
     hipFuncSetAttribute((const void*)k1e, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
     hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
     hipFuncSetAttribute((const void*)k3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
     hipFuncSetAttribute((const void*)k3e, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
-    attr = true;
+    attr.store(true, std::memory_order_release);
   }
   const int nb_rows = N / (RB * G);
   const int nb_cols = (NC - 1 + SH::CB - 1) / SH::CB;  // DC and Nyquist columns packed
