@@ -244,8 +244,20 @@ int cb_solve_indent(cb_plan plan, const double* f, double d, double* p_io,
                     cb_result* res);
 
 /*
- * cb_solve_force -- non-adhesive contact at prescribed total force F > 0;
- *   res->d returns the approach found.  Adhesive plans: CB_E_UNSUPPORTED.
+ * cb_solve_force -- contact at prescribed total force F > 0;
+ *   res->d returns the approach found.  Non-adhesive plans: the constrained
+ *   conjugate gradients with the mean-gap shift (Sec. 2, after Eq. 11).
+ *   Adhesive plans (stable branch): the approach d whose single adhesive
+ *   solve (as cb_solve_indent: geometric overlap, then the Eq. 12 detach
+ *   rounds) carries F, found by a bracketed regula falsi over such solves
+ *   from the non-adhesive approach for F.  F(d) steps where a cell attaches
+ *   or detaches, so the force is met to 1e-6 F or, where a step lies across
+ *   F, to the nearer side of that step; on a coarse grid F(d) also drops
+ *   where a ring of cells detaches, and then several approaches carry F:
+ *   the search returns the one its bracket closes on.  res->F is the force reached,
+ *   p_io / mask_io the solve at res->d, res->iters and res->rounds the
+ *   totals over all solves of the search.  F <= 0 on an adhesive plan:
+ *   CB_E_UNSUPPORTED; no bracket within 60 doublings: CB_E_NOCONV.
  */
 int cb_solve_force(cb_plan plan, const double* f, double F, double* p_io,
                    unsigned char* mask_io, const cb_solve_opts* opts,

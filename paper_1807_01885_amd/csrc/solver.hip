@@ -1260,6 +1260,98 @@ static int adhesive_indent(cb_plan_s* P, const double* f, double d, double* p, u
   return CB_OK;
 }
 
+// Adhesive force control (stable branch, F > 0).  The single adhesive
+// solve at approach d (the geometric overlap, then the Eq. 12 detach
+// rounds) defines F(d), which grows with d on the stable branch.  Adhesion
+// lowers the force at a given approach, so the non-adhesive approach for F
+// starts the bracket from below; the upper end is found by doubling steps,
+// then Illinois regula falsi narrows it.  F(d) steps where a cell attaches
+// or detaches, so the search stops when |F(d) - F| <= 1e-6 F or when the
+// bracket has shrunk to 1e-13 of its first width; the result is the single
+// solve at the d whose force came closest.
+template <typename TD>
+static int adhesive_force(cb_plan_s* P, const double* f, double F, double* p, unsigned char* mask_io,
+                          const cb_solve_opts* o, cb_result* res) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!(F > 0.0)) return cb_fail(CB_E_UNSUPPORTED, "force control of adhesive plans needs F > 0");
+  int iters = 0, rounds = 0;
+  cb_result r{};
+  if (int rc = pk_solve<TD>(P, f, F, true, p, nullptr, o, &r)) return rc;
+  iters += r.iters;
+  // the profile's lowest point: the non-adhesive penetration r.d - fmin
+  // sets the scale of the bracket search
+  Ctx c = make_ctx(P);
+  hipLaunchKernelGGL(k_minmax, dim3(c.nb), dim3(RT), 0, c.st, f, nullptr, P->d_part, c.n);
+  hipLaunchKernelGGL(k_fold_misc<4>, dim3(1), dim3(RT), 0, c.st, P->d_part, c.nb, 15);
+  double mm[4];
+  if (int rc = read_scratch(c, mm, 4)) return rc;
+  const double fmin = -mm[0];
+  double best_d = 0.0, best_err = INFINITY;
+  auto eval = [&](double d, double* Fd) -> int {
+    cb_result q{};
+    const int rc = adhesive_indent<TD>(P, f, d, p, mask_io, o, &q);
+    iters += q.iters;
+    rounds += q.rounds;
+    if (rc != CB_OK) return rc;
+    *Fd = q.F;
+    *res = q;
+    if (std::fabs(q.F - F) < best_err) {
+      best_err = std::fabs(q.F - F);
+      best_d = d;
+    }
+    return CB_OK;
+  };
+  const double scale = std::max(0.05 * (r.d - fmin), 1e-9 * P->L);
+  double dlo = r.d, Flo = 0.0, step = scale;
+  if (int rc = eval(dlo, &Flo)) return rc;
+  for (int k = 0; Flo >= F; k++) {  // rarely: the adhesive force already exceeds F
+    if (k == 60) return cb_fail(CB_E_NOCONV, "adhesive force control: no lower bracket");
+    dlo -= step;
+    step *= 2.0;
+    if (int rc = eval(dlo, &Flo)) return rc;
+  }
+  step = scale;
+  double dhi = dlo + step, Fhi = 0.0;
+  if (int rc = eval(dhi, &Fhi)) return rc;
+  for (int k = 0; Fhi < F; k++) {
+    if (k == 60) return cb_fail(CB_E_NOCONV, "adhesive force control: no upper bracket");
+    dlo = dhi;
+    Flo = Fhi;
+    step *= 2.0;
+    dhi = dlo + step;
+    if (int rc = eval(dhi, &Fhi)) return rc;
+  }
+  const double width0 = dhi - dlo;
+  int side = 0;
+  double last_d = dhi;
+  for (int k = 0; k < 200 && best_err > 1e-6 * F && dhi - dlo > 1e-13 * width0; k++) {
+    double d = dhi - (Fhi - F) * (dhi - dlo) / (Fhi - Flo);
+    if (!(d > dlo && d < dhi)) d = 0.5 * (dlo + dhi);
+    double Fd = 0.0;
+    if (int rc = eval(d, &Fd)) return rc;
+    last_d = d;
+    if (Fd < F) {
+      if (side == -1) Fhi = F + 0.5 * (Fhi - F);
+      dlo = d;
+      Flo = Fd;
+      side = -1;
+    } else {
+      if (side == 1) Flo = F + 0.5 * (Flo - F);
+      dhi = d;
+      Fhi = Fd;
+      side = 1;
+    }
+  }
+  if (best_d != last_d) {
+    double Fd = 0.0;
+    if (int rc = eval(best_d, &Fd)) return rc;
+  }
+  res->iters = iters;
+  res->rounds = rounds;
+  res->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return CB_OK;
+}
+
 template <typename TD>
 static int sweep_impl(cb_plan_s* P, const double* f, const double* dsteps, int nsteps, double* p,
                       unsigned char* mask, const cb_solve_opts* o, cb_result* out) {
@@ -1308,7 +1400,10 @@ extern "C" int cb_solve_force(cb_plan P, const double* f, double F, double* p_io
   if (!aligned16(f) || !aligned16(p_io) || (mask_io && !aligned16(mask_io)))
     return cb_fail(CB_E_INVALID, "f, p and mask must be 16-byte aligned");
   if (!std::isfinite(F) || F < 0.0) return cb_fail(CB_E_INVALID, "F must be finite and >= 0");
-  if (P->dgamma > 0.0) return cb_fail(CB_E_UNSUPPORTED, "force control is provided for non-adhesive plans");
+  if (P->dgamma > 0.0) {
+    if (P->precision == CB_FP64) return adhesive_force<double>(P, f, F, p_io, mask_io, o, res);
+    return adhesive_force<float>(P, f, F, p_io, mask_io, o, res);
+  }
   if (P->precision == CB_FP64) return pk_solve<double>(P, f, F, true, p_io, mask_io, o, res);
   return pk_solve<float>(P, f, F, true, p_io, mask_io, o, res);
 }

@@ -107,6 +107,50 @@ def test_adhesive_single_solve_fp64(lib):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adhesive_force_control(lib, prec):
+    """Force control of an adhesive plan: the target is the oracle's force of
+    the single adhesive solve at a known approach.  On a coarse grid the
+    single solve's F(d) drops wherever a ring of cells detaches, so other
+    approaches can carry the same force: the library must reach the force,
+    return exactly its own single solve at the approach it found, and that
+    approach must carry the force in the oracle too (with the same
+    pressure)."""
+    print(f"adhesive force {prec}", flush=True)
+    N, L = 64, 1.0
+    mat = Material(0.1, 1.0, 0.3, 1.0, 0.3)
+    f = inputs.paraboloid(N, L, 1.0)
+    d_true, dg = 3e-3, 2e-4
+    op = Operator(N, L, mat)
+    sc = critical_stress(mat, dg, L / N)
+    st, _, _, _ = adhesive_solve(op, f, d_true, sc, 1e-12 * L, tol=1e-10)
+    F = (L / N) ** 2 * st.p.sum()
+    assert F > 0.0
+    plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, dg, prec)
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
+    tol = 1e-10 if prec == "fp64" else 1e-8
+    p = torch.zeros_like(ft)
+    mask = torch.zeros(N, N, dtype=torch.uint8, device="cuda")
+    res = lib.cb_solve_force(plan, ft, F, p, mask, tol=tol)
+    print(f"  d {res['d']:.9e} (target taken at {d_true:.1e}) F {res['F']:.9e} vs {F:.9e} iters {res['iters']}")
+    assert res["status"] == 0
+    assert abs(res["F"] - F) <= 1e-6 * F
+    # the returned state is the single solve at the approach found
+    p1 = torch.zeros_like(ft)
+    m1 = torch.zeros_like(mask)
+    r1 = lib.cb_solve_indent(plan, ft, res["d"], p1, m1, tol=tol)
+    assert torch.equal(p1, p) and torch.equal(m1, mask) and r1["F"] == res["F"]
+    st2, _, _, _ = adhesive_solve(op, f, res["d"], sc, 1e-12 * L, tol=1e-10)
+    F2 = (L / N) ** 2 * st2.p.sum()
+    e_p = np.linalg.norm(p.cpu().numpy() - st2.p) / np.linalg.norm(st2.p)
+    print(f"  oracle at d found: F {F2:.9e} e_p {e_p:.2e}")
+    assert abs(F2 - F) <= (1e-6 if prec == "fp64" else 1e-4) * F
+    assert e_p < (1e-8 if prec == "fp64" else 1e-4)
+    with pytest.raises(lib.CoatbemError) as e:
+        lib.cb_solve_force(plan, ft, 0.0, p, mask, tol=tol)
+    assert e.value.status == lib.CB_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_adhesive_sweep_short(lib, prec):
     print(f"sweep {prec}", flush=True)
     N, L, R = 64, 1.0, 1.0
