@@ -150,6 +150,32 @@ def test_adhesive_force_control(lib, prec):
     assert e.value.status == lib.CB_E_UNSUPPORTED
 
 
+def test_adhesive_force_control_jkr(lib):
+    """Physics check of adhesive force control on the homogeneous half-space
+    (E* = 1) under a paraboloid: at the force JKR gives for a = 0.2 (25
+    cells), the contact found satisfies JKR's F(a) within 8% of the Hertz
+    force at that radius, the bar of the oracle's retraction pin (the Eq. 12
+    criterion is mesh-dependent, about 10% at a/D of 10 to 30), and its
+    approach is JKR's within 10%."""
+    from oracle import analytic as an
+    N, L, R = 128, 1.0, 1.0
+    mat = Material(0.0, 0.91, 0.3, 0.91, 0.3)
+    dg = 2e-4
+    F, d_j = an.jkr(0.2, R, mat.E1s, dg)
+    assert F > 0.0
+    plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, dg, "fp64")
+    ft = torch.tensor(inputs.paraboloid(N, L, R), dtype=torch.float64, device="cuda")
+    p = torch.zeros_like(ft)
+    res = lib.cb_solve_force(plan, ft, F, p, tol=1e-10)
+    a = math.sqrt(res["area"] / math.pi)
+    Fa, _ = an.jkr(a, R, mat.E1s, dg)
+    hertz = 4.0 * mat.E1s * a ** 3 / (3.0 * R)
+    print(f"  F {res['F']:.6e} target {F:.6e} a {a:.4f} (JKR 0.2) F_JKR(a) {Fa:.6e} d {res['d']:.5f} (JKR {d_j:.5f})")
+    assert abs(res["F"] - F) <= 1e-6 * F
+    assert abs(Fa - F) <= 0.08 * hertz
+    assert res["d"] == pytest.approx(d_j, rel=0.1)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_adhesive_sweep_short(lib, prec):
     print(f"sweep {prec}", flush=True)
