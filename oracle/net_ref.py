@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 The network is not part of the paper: it is the learned warm start of the
 contact solve (an initial pressure field), and only the solve it seeds is
-judged.  This module fixes its definition in plain NumPy so that the GPU
+held to the paper's method.  This module fixes its definition in plain
+NumPy so that the GPU
 forward/backward kernels can be checked against it; it is pinned by
 central finite differences in tests/test_oracle_net.py.
 
