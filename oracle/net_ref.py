@@ -5,9 +5,8 @@ TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 The network is not part of the paper: it is the learned warm start of the
 contact solve (an initial pressure field), and only the solve it seeds is
 held to the paper's method.  This module fixes its definition in plain
-NumPy so that the GPU
-forward/backward kernels can be checked against it; it is pinned by
-central finite differences in tests/test_oracle_net.py.
+NumPy so that the GPU forward/backward kernels can be checked against it;
+it is pinned by central finite differences in tests/test_oracle_net.py.
 
 Definition (NHWC, 16 channels everywhere, every convolution 3x3, stride 1,
 zero "same" padding, weights W[tap][co][ci] with tap = 3 (dy+1) + (dx+1)):
