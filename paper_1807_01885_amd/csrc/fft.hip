@@ -83,17 +83,43 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
     constexpr int NB = L / (R * NT1);
     const size_t rowoff = (size_t)(row0 + lrow) * N;
     const C* z = reinterpret_cast<const C*>(p + rowoff);
-    // the scalars of the input (every block folds the partials itself;
-    // the block-uniform return ends a converged solve's iteration here)
-    double xbar = 0.0, beta = 0.0;
+    // Formed inputs (PRO): the operands are loaded first, so that their
+    // latency overlaps the folds of the partials that give the scalars
+    // (every block folds them itself; the block-uniform return ends a
+    // converged solve's iteration there).  Which x the direction takes
+    // depends only on the phase.
+    constexpr int RH = PAD ? R / 2 : R;  // pairs with data (upper half padding)
     const T* xs = nullptr;
+    C* td = nullptr;  // t is read and rewritten through tdir (p is declared restrict)
+    if constexpr (PRO == 1) {
+      xs = static_cast<const T*>(ea.g);
+    } else if constexpr (PRO == 2) {
+      const bool pre = !(ea.plain0 && (!ea.two || ea.st->phase == 0));
+      xs = static_cast<const T*>(pre ? ea.x : ea.g);
+      td = reinterpret_cast<C*>(static_cast<T*>(ea.tdir) + rowoff);
+    }
+    uchar2 oa[NB][RH];
+    C ox[NB][RH], ot[NB][RH];
+    if constexpr (PRO != 0) {
+#pragma unroll
+      for (int b = 0; b < NB; b++) {
+        const int j = t + b * NT1;
+#pragma unroll
+        for (int i = 0; i < RH; i++) {
+          const int pi = j + i * (L / R);  // pair (cells 2 pi, 2 pi + 1 of the row)
+          const size_t cell = rowoff + 2 * pi;
+          oa[b][i] = *reinterpret_cast<const uchar2*>(ea.act + cell);
+          ox[b][i] = *reinterpret_cast<const C*>(xs + cell);
+          if constexpr (PRO == 2) ot[b][i] = td[pi];
+        }
+      }
+    }
+    double xbar = 0.0, beta = 0.0;
     if constexpr (PRO == 1) {
       if (!masked_gradient_scalars<NTH>(ea, xbar)) return;
-      xs = static_cast<const T*>(ea.g);
     } else if constexpr (PRO == 2) {
       bool pre = false;
       if (!direction_scalars<NTH>(ea, xbar, beta, pre)) return;
-      xs = static_cast<const T*>(pre ? ea.x : ea.g);
     }
     C a[NB][R];
 #pragma unroll
@@ -101,24 +127,20 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
       const int j = t + b * NT1;
 #pragma unroll
       for (int i = 0; i < R; i++) {
-        if (PAD && i >= R / 2) {
+        if (i >= RH) {
           a[b][i] = C{T(0), T(0)};
           continue;
         }
-        const int pi = j + i * (L / R);  // pair (cells 2 pi, 2 pi + 1 of the row)
+        const int pi = j + i * (L / R);
         if constexpr (PRO == 0) {
           a[b][i] = z[pi];
         } else {
-          const size_t cell = rowoff + 2 * pi;
-          const uchar2 a2 = *reinterpret_cast<const uchar2*>(ea.act + cell);
-          const C x2 = *reinterpret_cast<const C*>(xs + cell);
+          const uchar2 a2 = oa[b][i];
+          const C x2 = ox[b][i];
           if constexpr (PRO == 1) {
             a[b][i] = C{a2.x ? (T)((double)x2.x - xbar) : T(0), a2.y ? (T)((double)x2.y - xbar) : T(0)};
           } else {
-            // t is read and rewritten through tdir (the input pointer is
-            // declared restrict)
-            C* td = reinterpret_cast<C*>(static_cast<T*>(ea.tdir) + rowoff);
-            const C t2 = td[pi];
+            const C t2 = ot[b][i];
             const C tn = C{a2.x ? (T)(((double)x2.x - xbar) + beta * (double)t2.x) : T(0),
                            a2.y ? (T)(((double)x2.y - xbar) + beta * (double)t2.y) : T(0)};
             td[pi] = tn;
