@@ -48,8 +48,8 @@ TOL_REF = 1e-10     # FP64 reference for the accuracy checks
 # WRITE x 1.0); the summary and commands are in profiles/.  Valid while the
 # FFT sources hash to `src` and the plan uses `variant`.
 K2_TRAFFIC = {"kernel": "k2_cols", "N": 1024, "precision": "fp32", "variant": 3,
-              "src": "bab34e8a6df3dacf:f7e81aeadb45feb5",
-              "fetch_bytes": 6336.95 * 1024 * 2.0, "write_bytes": 8192.0 * 1024,
+              "src": "8d60e008966fdcf6:f7e81aeadb45feb5",
+              "fetch_bytes": 6349.0 * 1024 * 2.0, "write_bytes": 8192.0 * 1024,
               # SQ_INSTS_VALU per launch (same probe, same conditions)
               "valu_wave_insts": 3537334.0}
 # wave64 VALU instructions the chip issues per second without packed FP32:

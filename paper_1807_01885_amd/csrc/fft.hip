@@ -371,6 +371,27 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
   constexpr int ITEMS = G * NC * RB;
   constexpr int NIT = (ITEMS + NTH - 1) / NTH;
   const C* in = S + (size_t)blockIdx.x * ITEMS;
+  // The operands of the EPI sums (the cells this thread writes in the last
+  // pass) are loaded first, so that their latency overlaps the transform.
+  constexpr int RL = last_radix(L, E);
+  constexpr int NBL = L / (RL * NT1);
+  constexpr int RHL = PAD ? RL / 2 : RL;  // outputs kept per butterfly
+  const int lrow = tid / NT1, t = tid % NT1;
+  const size_t row = (size_t)blockIdx.x * ROWS + lrow;
+  uchar2 e_act[NBL][RHL];
+  C e_g[NBL][RHL], e_t[NBL][RHL];
+  if constexpr (EPI != 0) {
+#pragma unroll
+    for (int b = 0; b < NBL; b++) {
+#pragma unroll
+      for (int i = 0; i < RHL; i++) {
+        const size_t cell = row * N + 2 * (t + b * NT1 + i * (L / RL));
+        e_act[b][i] = *reinterpret_cast<const uchar2*>(ea.act + cell);
+        e_g[b][i] = *reinterpret_cast<const C*>(static_cast<const T*>(ea.g) + cell);
+        if constexpr (EPI == 1) e_t[b][i] = *reinterpret_cast<const C*>(static_cast<const T*>(ea.t) + cell);
+      }
+    }
+  }
   {
     C v[NIT];
 #pragma unroll
@@ -424,12 +445,10 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
     }
   }
   __syncthreads();
-  const int lrow = tid / NT1, t = tid % NT1;
   C* line = buf + lrow * LP;
-  constexpr int RL = last_radix(L, E);
   MidPasses<T, L, M, NT1, -1, PS, 1, L / RL>::run(line, t, tw);
   {
-    constexpr int NB = L / (RL * NT1);
+    constexpr int NB = NBL;
     C* zo = reinterpret_cast<C*>(u + (size_t)(blockIdx.x * ROWS + lrow) * N);
     C a[NB][RL];
 #pragma unroll
@@ -442,7 +461,6 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
     // the reduction below reuses the LDS: Q x NTH doubles
     static_assert(EPI == 0 || E >= 4, "row tile LDS too small for the K3 reductions");
     double v[Q] = {};
-    const size_t row = (size_t)blockIdx.x * ROWS + lrow;
     double m = 0.0;
     if constexpr (EPI != 0) m = ea.st->gdev;
 #pragma unroll
@@ -455,13 +473,12 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
         zo[c] = a[b][i];
         if constexpr (EPI != 0) {
           // cells 2c, 2c + 1 of this row: x = (a.x, a.y)
-          const size_t cell = row * N + 2 * c;
-          const uchar2 a2 = *reinterpret_cast<const uchar2*>(ea.act + cell);
-          const cx<T> g2 = *reinterpret_cast<const cx<T>*>(static_cast<const T*>(ea.g) + cell);
+          const uchar2 a2 = e_act[b][i];
+          const C g2 = e_g[b][i];
           const double x0 = (double)a[b][i].x, x1 = (double)a[b][i].y;
           const double g0 = (double)g2.x - m, g1 = (double)g2.y - m;
           if constexpr (EPI == 1) {
-            const cx<T> t2 = *reinterpret_cast<const cx<T>*>(static_cast<const T*>(ea.t) + cell);
+            const C t2 = e_t[b][i];
             const double t0 = (double)t2.x, t1 = (double)t2.y;
             if (a2.x) {
               v[0] += g0 * t0;
