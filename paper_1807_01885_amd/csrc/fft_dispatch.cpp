@@ -97,16 +97,20 @@ static int time_variant(cb_plan_s* P, int prec, hipEvent_t e0, hipEvent_t e1, do
   hipStream_t st = P->istream;
   hipGraph_t g = nullptr;
   hipGraphExec_t ex = nullptr;
-  CB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (int r = 0; r < REPS && e == hipSuccess; r++) e = launch_apply(P, P->d_u, P->d_t, st, 7, nullptr, nullptr, prec);
-  const hipError_t ee = hipStreamEndCapture(st, &g);
-  if (e != hipSuccess || ee != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    return cb_fail(CB_E_DEVICE, std::string("autotune capture: ") + hipGetErrorString(e != hipSuccess ? e : ee));
+  {
+    std::lock_guard<std::mutex> lk(graph_mutex());
+    CB_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < REPS && e == hipSuccess; r++)
+      e = launch_apply(P, P->d_u, P->d_t, st, 7, nullptr, nullptr, prec);
+    const hipError_t ee = hipStreamEndCapture(st, &g);
+    if (e != hipSuccess || ee != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return cb_fail(CB_E_DEVICE, std::string("autotune capture: ") + hipGetErrorString(e != hipSuccess ? e : ee));
+    }
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
   }
-  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
   if (e != hipSuccess) return cb_fail(CB_E_DEVICE, std::string("autotune instantiate: ") + hipGetErrorString(e));
   float ms = 0.f;
   e = hipGraphLaunch(ex, st);
@@ -115,7 +119,11 @@ static int time_variant(cb_plan_s* P, int prec, hipEvent_t e0, hipEvent_t e1, do
   if (e == hipSuccess) e = hipEventRecord(e1, st);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-  (void)hipGraphExecDestroy(ex);
+  if (hipStreamSynchronize(st) != hipSuccess && e == hipSuccess) e = hipErrorUnknown;
+  {
+    std::lock_guard<std::mutex> lk(graph_mutex());
+    (void)hipGraphExecDestroy(ex);
+  }
   if (e != hipSuccess) return cb_fail(CB_E_DEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
   *us = 1000.0 * ms / (REPS * REPLAYS);
   return CB_OK;

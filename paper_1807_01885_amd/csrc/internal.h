@@ -4,6 +4,7 @@
 #include <cstdint>
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -73,7 +74,10 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   unsigned long long used = 0;
 };
-constexpr int GRAPH_CACHE = 12;
+// Graph cache entries per plan.  A solve of one mode uses up to eight
+// (chunk lengths 2..16, first and second phase); an adhesive force search
+// adds the fixed-set solves of both contact-set buffers.
+constexpr int GRAPH_CACHE = 24;
 
 namespace cb {
 // FFT launch-shape variants: complex elements per thread in the row
@@ -121,6 +125,10 @@ struct cb_plan_s {
   hipStream_t istream = nullptr;     // plan-owned stream for captured solves
   hipEvent_t ev_in = nullptr, ev_state[2] = {nullptr, nullptr};
   GraphEntry graphs[GRAPH_CACHE];
+  // executable graphs evicted from the cache; destroyed with the plan (or,
+  // past a bound, after the plan's stream has drained), never while a
+  // launch of theirs may still be in flight or referenced
+  std::vector<hipGraphExec_t> retired;
   unsigned long long graph_clock = 0;
   int use_graphs = 1;
   int variant[2] = {0, 0};  // FFT launch-shape variant of the FP64 / FP32 convolutions
@@ -218,6 +226,15 @@ CB_DECLARE_FFT_VARIANT(5)
 bool fft_variant_fits(int v, int log2n, int prec, int device);
 // time every fitting variant for the plan's precision, or take it from the cache
 int autotune_fft(cb_plan_s* P, int autotune, const char* cache);
+}  // namespace cb
+
+namespace cb {
+// One process-wide lock around stream capture, graph instantiation and the
+// destruction of graphs and executable graphs.  Batched solves drive many
+// plans from concurrent host threads; the lock keeps those graph-management
+// calls from running at the same time (launches of existing executable
+// graphs and all other stream work stay unserialised).
+std::mutex& graph_mutex();
 }  // namespace cb
 
 // error reporting (thread-local message)

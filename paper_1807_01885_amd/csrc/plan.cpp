@@ -185,9 +185,19 @@ extern "C" int cb_transfer_table(int N, double L, double h, double E1, double nu
   return CB_OK;
 }
 
+std::mutex& cb::graph_mutex() {
+  static std::mutex mu;
+  return mu;
+}
+
 static void free_plan_memory(cb_plan_s* P) {
-  for (auto& g : P->graphs)
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  {
+    std::lock_guard<std::mutex> lk(cb::graph_mutex());
+    for (auto& g : P->graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    for (hipGraphExec_t ex : P->retired) (void)hipGraphExecDestroy(ex);
+    P->retired.clear();
+  }
   if (P->ev_in) (void)hipEventDestroy(P->ev_in);
   for (auto& e : P->ev_state)
     if (e) (void)hipEventDestroy(e);

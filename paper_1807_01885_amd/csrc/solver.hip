@@ -892,6 +892,9 @@ static hipGraphExec_t chunk_graph(cb_plan_s* P, int kind, const void* a, const v
   }
   hipGraph_t g = nullptr;
   hipGraphExec_t ex = nullptr;
+  // the stream's earlier work (on this plan's stream only) has completed
+  // when a chunk is captured: run_chunks waits for every chunk it launches
+  std::lock_guard<std::mutex> lk(graph_mutex());
   if (hipStreamBeginCapture(P->istream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     P->use_graphs = 0;
     (void)hipGetLastError();
@@ -906,7 +909,15 @@ static hipGraphExec_t chunk_graph(cb_plan_s* P, int kind, const void* a, const v
     return nullptr;
   }
   (void)hipGraphDestroy(g);
-  if (lru->exec) (void)hipGraphExecDestroy(lru->exec);
+  if (lru->exec) {
+    // an evicted executable graph is kept until the plan is destroyed; a
+    // long list is released once the plan's stream has drained
+    P->retired.push_back(lru->exec);
+    if (P->retired.size() > 64 && hipStreamSynchronize(P->istream) == hipSuccess) {
+      for (hipGraphExec_t r : P->retired) (void)hipGraphExecDestroy(r);
+      P->retired.clear();
+    }
+  }
   lru->kind = kind;
   lru->a = a;
   lru->b = b;
@@ -1154,8 +1165,10 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
 
 // CG on the fixed set S; x in/out.  The recurrence residual is confirmed by
 // the true residual b - K x computed with an FP64 convolution; if that is
-// still above tol the CG restarts from x (iterative refinement; at most two
-// restarts).
+// still above tol the CG restarts from x (iterative refinement, at most
+// SET_REFINE restarts).  A true residual still above tol after the last
+// restart is CB_E_NOCONV.
+constexpr int SET_REFINE = 4;
 template <typename TD>
 static int set_solve(const Ctx& c, const double* f, double d, const unsigned char* S, double* x, double tol,
                      int max_iter, int chunk, int pk, int& iters, double& resid) {
@@ -1165,7 +1178,7 @@ static int set_solve(const Ctx& c, const double* f, double d, const unsigned cha
   TD* z = (TD*)P->d_t;
   const dim3 grid(c.nb), blk(RT);
   int budget = max_iter;
-  for (int attempt = 0; attempt < 3; attempt++) {
+  for (int attempt = 0; attempt <= SET_REFINE; attempt++) {
     if (int rc = write_state(P, base_state(P, tol, d, false, 0.0))) return rc;
     hipLaunchKernelGGL(k_zero_off, grid, blk, 0, c.st, x, S, c.n);
     CB_HIP(apply64(c, x, u, nullptr));
@@ -1175,7 +1188,10 @@ static int set_solve(const Ctx& c, const double* f, double d, const unsigned cha
     if (int rc = read_state(P, &s)) return rc;
     if (s.nonfinite) return CB_E_NONFINITE;
     resid = s.resid;
-    if (s.done || attempt == 2 || budget <= 0) return (s.done || attempt == 2) ? CB_OK : CB_E_NOCONV;
+    // converged on the true residual; or out of refinement restarts or
+    // iterations with the true residual still above tol
+    if (s.done) return CB_OK;
+    if (attempt == SET_REFINE || budget <= 0) return CB_E_NOCONV;
     if (pk > 0) {  // y = M^-1 r (z holds r in the direction type), z = y on S
       CB_HIP(apply_pc(c, z, P->d_y, nullptr, pk == 2 ? P->d_pinv : P->d_ptable));
       hipLaunchKernelGGL(k_mcg_pc0<TD>, grid, blk, 0, c.st, (const double*)r, (const TD*)P->d_y, z, S, P->d_state,

@@ -299,3 +299,27 @@ def test_force_cold_start_paths(lib, prec):
     eb = np.linalg.norm(pb.cpu().numpy() - refb.p) / np.linalg.norm(refb.p)
     print(f"  full-contact load iters {rb['iters']} e_p {eb:.1e}", flush=True)
     assert rb["status"] == 0 and eb < bar
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adhesive_status_matches_residual(lib, prec):
+    """The Eq. 12 rounds solve on a fixed contact set to a residual target
+    checked on the true residual (FP64 convolution).  A target below what
+    the arithmetic reaches must come back as CB_E_NOCONV, never as success
+    with the residual above the target; a reachable one as success with the
+    residual below it."""
+    print(f"adhesive status {prec}", flush=True)
+    N, L = 64, 1.0
+    mat = Material(0.1, 1.0, 0.3, 1.0, 0.3)
+    f = torch.tensor(inputs.paraboloid(N, L, 1.0), dtype=torch.float64, device="cuda")
+    plan = lib.cb_plan_create(N, L, mat.h, mat.E1, mat.nu1, mat.E2, mat.nu2, 2e-4, prec)
+    for tol in (1e-8, 1e-15 if prec == "fp64" else 1e-14):
+        p = torch.zeros_like(f)
+        res = lib.cb_solve_indent(plan, f, 3e-3, p, tol=tol, max_iter=3000, raise_on_error=False)
+        rc = res["status"]
+        print(f"  tol {tol:.0e}: status {rc} resid {res['resid']:.2e} rounds {res['rounds']}")
+        if tol == 1e-8:
+            assert rc == lib.CB_OK and res["resid"] <= tol
+        else:
+            assert rc in (lib.CB_OK, lib.CB_E_NOCONV)
+            assert (rc == lib.CB_OK) == (res["resid"] <= tol)
