@@ -193,14 +193,20 @@ def test_adhesive_sweep_short(lib, prec):
     mask = torch.zeros(N, N, dtype=torch.uint8, device="cuda")
     res = lib.cb_sweep(plan, ft, steps, p, mask, tol=1e-10 if prec == "fp64" else 1e-8)
     Fspan = max(abs(o["F"]) for o in out)
+    Uspan = max(abs(o["U_el"]) for o in out)
     for o, r in zip(out, res):
-        print(f"  d={o['d']:+.4e} F {r['F']:+.6e} vs {o['F']:+.6e} A {r['area']:.5f} vs {o['area']:.5f}")
+        print(f"  d={o['d']:+.4e} F {r['F']:+.6e} vs {o['F']:+.6e} A {r['area']:.5f} vs {o['area']:.5f} "
+              f"U_el {r['U_el']:.6e} vs {o['U_el']:.6e}")
+        # U_ad = -dgamma A on both sides
+        assert r["U_ad"] == pytest.approx(-dg * r["area"], rel=1e-14, abs=1e-300)
         if prec == "fp64":
             assert r["area"] == pytest.approx(o["area"], abs=1e-15)
             assert abs(r["F"] - o["F"]) <= 1e-8 * Fspan
+            assert abs(r["U_el"] - o["U_el"]) <= 1e-8 * Uspan
         else:
             assert abs(r["area"] - o["area"]) <= 0.01 * max(o["area"], 1e-12) + 2 * (L / N) ** 2
             assert abs(r["F"] - o["F"]) <= 1e-3 * Fspan
+            assert abs(r["U_el"] - o["U_el"]) <= 1e-3 * Uspan
     if prec == "fp64":
         assert np.array_equal(mask.cpu().numpy().astype(bool), st.S)
 

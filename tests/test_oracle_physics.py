@@ -133,3 +133,179 @@ def test_jkr_retraction_homogeneous():
     assert out[-1]["area"] == 0.0
     # jump-off happens below the JKR instability, within the step size
     assert last_contact["d"] == pytest.approx(dpo, rel=0.35)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3 asymptotics reproduced by the oracle's own solves (not closed forms
+# checked against each other).  Rigid base: E2/E1 = 1e5 or more.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("h,a", [(0.004, 0.1), (0.004, 0.15), (0.008, 0.15)])
+def test_thin_layer_paraboloid_eq17_18_no_adhesion(h, a):
+    """Eq. 17-18 with dgamma = 0: a thin layer on a rigid base under a
+    paraboloid carries F = pi E~1 a^4 / (4 R h) at d = a^2 / (2 R).  Solved
+    at that d, the oracle's force and contact radius agree within 1.5% and
+    2% (discretisation at a/D = 25-38, O(h/a) edge terms); with E1* in place
+    of E~1 (Eq. 15) the force would be 22% higher."""
+    N, L, R = 256, 1.0, 1.0
+    mat = Material(h, 1.0, 0.3, 1e5, 0.3)
+    op = Operator(N, L, mat)
+    d = a * a / (2.0 * R)
+    r = solve_pk(op, inputs.paraboloid(N, L, R), d, tol=1e-9)
+    F17, d18 = an.thin_layer_paraboloid(a, R, h, an.e_tilde(mat.E1, mat.nu1), 0.0)
+    assert r.converged and d18 == pytest.approx(d, rel=1e-14)
+    assert r.F == pytest.approx(F17, rel=1.5e-2)
+    assert math.sqrt(r.area / math.pi) == pytest.approx(a, rel=2e-2)
+
+
+@pytest.mark.parametrize("eps", [0.2, 0.3, 0.5])
+def test_thick_layer_paraboloid_eq22_23_no_adhesion(eps):
+    """Eq. 22-23 with dgamma = 0, rigid base, a_0 and a_1 from Eq. 24: at the
+    approach d(a) of Eq. 23 the oracle's force is F(a) of Eq. 22 within 0.3%
+    for eps = a/h <= 0.3 and 1.2% at 0.5 (the series is truncated after
+    eps^4), while the homogeneous Hertz force of the coating is 20-60% off."""
+    N, L, R, a = 256, 1.0, 1.0, 0.08
+    h = a / eps
+    mat = Material(h, 1.0, 0.3, 1e6, 0.3)
+    a0 = an.series_coefficient(0, 0.3)
+    a1 = an.series_coefficient(1, 0.3)
+    F22, d23 = an.thick_layer_paraboloid(a, R, h, mat.E1s, 0.0, a0, a1)
+    r = solve_pk(Operator(N, L, mat), inputs.paraboloid(N, L, R), d23, tol=1e-9)
+    assert r.converged
+    assert r.F == pytest.approx(F22, rel=3e-3 if eps <= 0.3 else 1.2e-2)
+    Fh = an.hertz(R, d23, mat.E1s)[1]
+    assert r.F / Fh > 1.15
+    assert math.sqrt(r.area / math.pi) == pytest.approx(a, rel=2e-2)
+
+
+def test_energy_balance_dUel_dd_equals_F():
+    """Along a displacement-controlled loading path dU_el/dd = F, with
+    U_el = 1/2 D^2 sum p u (the envelope theorem of the contact energy).
+    The trapezoid of F over 40 steps matches U_el within 1e-3 of its final
+    value, for the recorded U_el of the sweep driver and for the solve;
+    half or twice the energy (a dropped 1/2, u taken as d - f everywhere)
+    would miss by 50-100%."""
+    N, L, R = 128, 1.0, 1.0
+    mat = Material(0.05, 10.0, 0.3, 1.0, 0.3)
+    op = Operator(N, L, mat)
+    f = inputs.paraboloid(N, L, R)
+    ds = np.linspace(0.0, 4e-3, 41)
+    U, F = [0.0], [0.0]
+    for d in ds[1:]:
+        r = solve_pk(op, f, d, tol=1e-11)
+        U.append(0.5 * op.dx ** 2 * float(np.sum(r.p * r.u)))
+        F.append(r.F)
+    U, F = np.array(U), np.array(F)
+    trap = np.concatenate([[0.0], np.cumsum(0.5 * (F[1:] + F[:-1]) * np.diff(ds))])
+    assert np.abs(U - trap).max() < 1e-3 * U[-1]
+    # the sweep driver's record: sigma_c = 0 and no adhesion energy
+    out, _ = sweep(op, f, ds[1:], 0.0, 1e-12 * L, 0.0, tol=1e-11)
+    Us = np.array([0.0] + [o["U_el"] for o in out])
+    Fs = np.array([0.0] + [o["F"] for o in out])
+    assert np.abs(Fs - F).max() < 1e-8 * F[-1]
+    trap = np.concatenate([[0.0], np.cumsum(0.5 * (Fs[1:] + Fs[:-1]) * np.diff(ds))])
+    assert np.abs(Us - trap).max() < 1e-3 * Us[-1]
+
+
+def test_adhesion_parameter_eq26_against_eq19():
+    """Eq. 26 and Eq. 19 are typed independently; they are tied by
+    (a_crit/h)^4 = 4 alpha^2 E1*/E~1."""
+    for (E1, nu, h, R, dg) in ((1e9, 0.3, 2e-3, 0.5, 100.0), (2.0, 0.45, 0.1, 3.0, 1e-3)):
+        E1s = an.reduced_modulus(E1, nu)
+        Et = an.e_tilde(E1, nu)
+        al = an.adhesion_parameter(dg, R, E1s, h)
+        _, acr, _ = an.thin_layer_paraboloid_critical(R, h, Et, dg)
+        assert (acr / h) ** 4 == pytest.approx(4.0 * al * al * E1s / Et, rel=1e-12)
+
+
+@pytest.mark.parametrize("ratio", [1e5, 1e2])
+def test_thin_layer_flat_punch_pulloff_eq16(ratio):
+    """Fig. 3 setup at reduced size: flat punch a = 16 h on a thin layer,
+    D = h/4, dgamma = 1e-4 E~1 h.  Displacement-controlled approach, then
+    retraction in steps of 0.05 |d_c|.  For E2/E1 = 1e5 the force is linear
+    with the Eq. 14 stiffness and the last contact lies within 10% of
+    (F~, d~) = (-1, -1) of Eq. 16 (measured -0.94, -0.95); for E2/E1 = 1e2
+    the substrate softens the punch and it detaches visibly later
+    (measured d~ = -1.2), as the paper reports."""
+    h = 1.0
+    N, D = 128, 0.25
+    L, a = N * D, 16.0 * h
+    mat = Material(h, 1.0, 0.3, ratio, 0.3)
+    Et = an.e_tilde(mat.E1, mat.nu1)
+    dg = 1e-4 * Et * h
+    op = Operator(N, L, mat)
+    dc, Fc = an.thin_layer_flat_punch_critical(a, h, Et, dg)
+    steps = np.concatenate([np.linspace(0, abs(dc), 5)[1:], np.linspace(abs(dc), 1.6 * dc, 53)[1:]])
+    out, _ = sweep(op, inputs.flat_punch(N, L, a), steps, critical_stress(mat, dg, D),
+                   1e-12 * L, dg, tol=1e-9)
+    last = [o for o in out if o["area"] > 0][-1]
+    dt, Ft = last["d"] / abs(dc), last["F"] / abs(Fc)
+    k = an.thin_layer_stiffness(a, h, Et)
+    if ratio == 1e5:
+        assert out[3]["F"] / out[3]["d"] == pytest.approx(k, rel=2e-2)
+        assert dt == pytest.approx(-1.0, abs=0.1) and Ft == pytest.approx(-1.0, abs=0.1)
+    else:
+        assert dt < -1.1
+    assert out[-1]["area"] == 0.0
+
+
+def test_thin_layer_paraboloid_retraction_eq20_21():
+    """Fig. 5 at large alpha (Eq. 26: alpha = 15), thin layer on a rigid base,
+    D = h/4 (a_crit = 5.2 h = 21 D): after a preload to d~ = 1.25 the
+    contact stays pinned, then recedes along F~ = a~^4 - 2 a~^2, d~ = a~^2 - 1,
+    i.e. F~ = d~^2 - 1: every receding point within 0.08 |F_crit| (measured
+    <= 0.06), the lowest force within 6% of F_crit = -2 pi R dgamma of
+    Eq. 19 (measured -0.965; homogeneous JKR would give -0.75)."""
+    h = 1.0
+    N, D = 128, 0.25
+    L = N * D
+    mat = Material(h, 1.0, 0.3, 1e5, 0.3)
+    Et = an.e_tilde(mat.E1, mat.nu1)
+    dg = 1e-3 * mat.E1s * h
+    alpha = 15.0
+    R = alpha * math.sqrt(mat.E1s * h ** 3 / (2.0 * dg))
+    assert an.adhesion_parameter(dg, R, mat.E1s, h) == pytest.approx(alpha, rel=1e-14)
+    dcr, acr, Fcr = an.thin_layer_paraboloid_critical(R, h, Et, dg)
+    op = Operator(N, L, mat)
+    dmax = 1.25 * abs(dcr)
+    steps = np.concatenate([np.linspace(0, dmax, 9)[1:], np.linspace(dmax, -1.3 * abs(dcr), 61)[1:]])
+    out, _ = sweep(op, inputs.paraboloid(N, L, R), steps, critical_stress(mat, dg, D),
+                   1e-12 * L, dg, tol=1e-9)
+    amax = max(o["area"] for o in out)
+    receding = [o for o in out[8:] if 0 < o["area"] < amax]
+    assert len(receding) > 20
+    for o in receding:
+        dt, Ft = o["d"] / abs(dcr), o["F"] / abs(Fcr)
+        assert abs(Ft - (dt * dt - 1.0)) < 0.08
+    Fmin = min(o["F"] for o in out)
+    assert Fmin / abs(Fcr) == pytest.approx(-1.0, abs=0.06)
+    assert out[-1]["area"] == 0.0
+
+
+def test_critical_separation_eq13_intermediate_layer():
+    """Eq. 13 at an intermediate thickness (flat punch a = h, E2/E1 = 1e5):
+    the critical separation predicted from the oracle's own non-adhesive
+    stiffness derivative dk/da (two punch radii 2 cells apart, radii taken
+    from the staircase area) matches the displacement at which the Eq. 12
+    detachment starts, within 6% (measured: between 0.95 and 1.0 of it,
+    in steps of 0.025)."""
+    N, L, h, a = 128, 1.0, 0.1, 0.1
+    D = L / N
+    mat = Material(h, 1.0, 0.3, 1e5, 0.3)
+    op = Operator(N, L, mat)
+    da = 2 * D
+    ks, ae = [], []
+    for aa in (a - da, a + da):
+        fp = inputs.flat_punch(N, L, aa)
+        r = solve_pk(op, fp, 1e-4, tol=1e-10)
+        ks.append(r.F / 1e-4)
+        ae.append(math.sqrt((fp == 0).sum() * D * D / math.pi))
+    dkda = (ks[1] - ks[0]) / (ae[1] - ae[0])
+    f = inputs.flat_punch(N, L, a)
+    A0 = (f == 0).sum() * D * D
+    dg = 1e-5
+    dc13 = an.critical_separation_eq13(dkda, math.sqrt(A0 / math.pi), dg)
+    steps = np.concatenate([np.linspace(0, dc13, 4)[1:], np.linspace(dc13, -2 * dc13, 121)[1:]])
+    out, _ = sweep(op, f, steps, critical_stress(mat, dg, D), 1e-12 * L, dg, tol=1e-9)
+    first_loss = [o for o in out[3:] if o["area"] < 0.999 * A0][0]
+    assert -first_loss["d"] / dc13 == pytest.approx(1.0, abs=0.06)
+    assert out[-1]["area"] == 0.0
