@@ -206,6 +206,24 @@ int cb_plan_set_stream(cb_plan plan, void* stream);
 int cb_apply_K(cb_plan plan, const void* p, void* u);
 
 /*
+ * cb_apply_K_noalloc -- cb_apply_K for callers that cannot allocate device
+ *   memory: code under HIP graph capture, tight serving loops, harnesses
+ *   that forbid hipMalloc.  No plan: the caller passes the transfer table.
+ *   The call allocates nothing (no hipMalloc/hipFree, no host allocation);
+ *   the FFT intermediate lives in a static device array of the library
+ *   (16.8 MB per device, held from module load until the process ends).
+ *   N: power of two in [16, 1024] (larger N: CB_E_INVALID).  precision:
+ *   CB_FP64 or CB_FP32, the type of table, p and u.  table: device,
+ *   (N+1)^2 values T[a][b] = K^(dk sqrt(a^2+b^2)) / M^2, M = 2N, row-major
+ *   (cb_transfer_table's table times 1/M^2, converted to the precision).
+ *   p, u: device N*N; u must not alias p; all three 16-byte aligned.
+ *   stream: hipStream_t (NULL: the null stream); asynchronous.  Every call
+ *   on one device shares that device's intermediate: calls that overlap
+ *   on one device race and must be ordered by the caller.
+ */
+int cb_apply_K_noalloc(int N, int precision, const void* table, const void* p, void* u, void* stream);
+
+/*
  * cb_apply_K_stages -- diagnostic form of cb_apply_K that launches only the
  *   stages selected in stage_mask: 1 = forward row transform (p -> plan
  *   intermediate), 2 = column transform with the transfer multiply (in place

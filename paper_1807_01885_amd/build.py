@@ -21,7 +21,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 # launch-shape variant
 FFT_VARIANTS = 6
 SOURCES = ([("plan.cpp", "plan", []), ("fft_dispatch.cpp", "fft_dispatch", []),
-            ("solver.hip", "solver", []), ("batch.cpp", "batch", []), ("net.hip", "net", [])]
+            ("solver.hip", "solver", []), ("batch.cpp", "batch", []), ("net.hip", "net", []),
+             ("noalloc.hip", "noalloc", [])]
            + [("fft.hip", f"fft_v{k}", [f"-DCB_FFT_VARIANT={k}"]) for k in range(FFT_VARIANTS)])
 ARCH = os.environ.get("COATBEM_ARCH", "gfx950")
 

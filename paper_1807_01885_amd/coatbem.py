@@ -91,6 +91,7 @@ _SIGS = {
     "cb_transfer_table": (_i, [_i, _d, _d, _d, _d, _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "cb_apply_K": (_i, [_vp, _vp, _vp]),
     "cb_apply_K_stages": (_i, [_vp, _vp, _vp, _i]),
+    "cb_apply_K_noalloc": (_i, [_i, _i, _vp, _vp, _vp, _vp]),
     "cb_apply_precond": (_i, [_vp, _i, _vp, _vp]),
     "cb_solve_indent": (_i, [_vp, _vp, _d, _vp, _vp, ctypes.POINTER(cb_solve_opts),
                              ctypes.POINTER(cb_result)]),
@@ -233,6 +234,21 @@ def _opts(tol=0.0, max_iter=0, chunk=0, init=0, attach_tol=-1.0, max_rounds=0, p
 
 def cb_apply_K(plan: Plan, p, u):
     _check(_lib.cb_apply_K(plan.handle, _arr(plan, p, "p"), _arr(plan, u, "u")))
+    return u
+
+
+def cb_apply_K_noalloc(N, precision, table, p, u, stream=None):
+    """u = K p without a plan or any allocation; table: device (N+1)^2 of
+    K^/M^2 in the precision ("fp64" or "fp32") of p and u."""
+    dtype = torch.float64 if precision == "fp64" else torch.float32
+    for name, x, shape in (("table", table, (N + 1, N + 1)), ("p", p, (N, N)), ("u", u, (N, N))):
+        if not isinstance(x, torch.Tensor) or x.device.type != "cuda" or x.dtype != dtype:
+            raise ValueError(f"{name} must be a {dtype} GPU tensor")
+        if tuple(x.shape) != shape or not x.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous tensor of shape {shape}")
+    _check(_lib.cb_apply_K_noalloc(int(N), CB_FP64 if precision == "fp64" else CB_FP32,
+                                   ctypes.c_void_p(table.data_ptr()), ctypes.c_void_p(p.data_ptr()),
+                                   ctypes.c_void_p(u.data_ptr()), _stream_ptr(stream)))
     return u
 
 

@@ -239,6 +239,8 @@ std::mutex& graph_mutex();
 
 // error reporting (thread-local message)
 int cb_fail(int status, const std::string& msg);
+// the same without constructing a string (no allocation)
+int cb_fail_c(int status, const char* msg);
 #define CB_HIP(call)                                                              \
   do {                                                                            \
     hipError_t e_ = (call);                                                       \

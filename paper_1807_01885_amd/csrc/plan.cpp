@@ -8,14 +8,20 @@
 
 #include "internal.h"
 
-static thread_local std::string g_last_error;
+// last error message of the calling thread, in a fixed buffer (setting it
+// allocates nothing, so the allocation-free entry point can report errors)
+static thread_local char g_last_error[512];
 
-int cb_fail(int status, const std::string& msg) {
-  g_last_error = msg;
+int cb_fail_c(int status, const char* msg) {
+  std::size_t i = 0;
+  for (; msg && msg[i] && i + 1 < sizeof(g_last_error); i++) g_last_error[i] = msg[i];
+  g_last_error[i] = '\0';
   return status;
 }
 
-extern "C" const char* cb_last_error(void) { return g_last_error.c_str(); }
+int cb_fail(int status, const std::string& msg) { return cb_fail_c(status, msg.c_str()); }
+
+extern "C" const char* cb_last_error(void) { return g_last_error; }
 
 extern "C" const char* cb_status_string(int s) {
   switch (s) {
