@@ -56,6 +56,22 @@ enum {
 
 enum { CB_FP64 = 0, CB_FP32 = 1 };
 enum { CB_DC_BZ = 0, CB_DC_ZERO = 1 };
+/* How the surface operator of Eq. 1 is represented (cb_plan_opts.kernel_mode). */
+enum {
+  CB_KERNEL_PADDED = 0,   /* the N x N patch in a 2N-zero-padded periodic cell:
+                             Eq. 11 evaluated so that it equals the
+                             non-periodic sum of Eq. 1 over the patch, with
+                             point-sampled K^ and the DC value of dc_mode */
+  CB_KERNEL_PERIODIC = 1  /* Eq. 11 literally: the surface is L-periodic, the
+                             transforms have length N (no padding) and the
+                             pressure has no DC component (K^(0) = 0: a
+                             uniform pressure produces no displacement and u
+                             has zero mean).  The mean pressure is what a
+                             force-controlled solve prescribes; the approach
+                             d it returns is relative to the mean surface.
+                             Non-adhesive only (Eq. 12 is derived for a
+                             non-periodic system) */
+};
 
 /* Plan options; a NULL pointer selects every default. */
 typedef struct {
@@ -84,6 +100,7 @@ typedef struct {
                       2 (16, 8, 1x), 3 (8, 16, 1x), 4 (16, 16, 2x),
                       5 (16, 32, 1x), 6 (8, 8, 2x).  All give the same
                       transform up to rounding order. */
+  int kernel_mode; /* CB_KERNEL_PADDED (default) or CB_KERNEL_PERIODIC */
 } cb_plan_opts;
 
 /* Solve options; a NULL pointer selects every default. */
@@ -150,7 +167,16 @@ typedef struct {
   size_t workspace_bytes;
   int fft_variant;   /* FFT launch-shape variant in use (1..6) */
   double tune_us;    /* its timed convolution, microseconds (0: not timed) */
+  int kernel_mode;   /* CB_KERNEL_* */
+  int table_n;       /* side of the transfer quadrant cb_plan_get_table
+                        returns: N + 1 (padded), N/2 + 1 (periodic) */
+  int nlayers;       /* layers of the coating (1 for cb_plan_create); h, E1,
+                        nu1 are the top layer's, E2, nu2 the half-space's */
+  double H;          /* total coating thickness */
 } cb_plan_info;
+
+/* Most layers of a cb_plan_create_layered stack. */
+#define CB_MAX_LAYERS 8
 
 /*
  * Device arrays passed to this library (pressures, profiles, masks, displacements,
@@ -165,13 +191,39 @@ typedef struct {
  *   normalised form of Eq. 9-10 at k = sqrt(kx^2 + ky^2) on the 2N-padded
  *   frequency grid, with the DC value of opts->dc_mode; sigma_c from Eq. 12.
  *   N: power of two, 16 <= N <= 4096.  L > 0, h >= 0, E1, E2 > 0,
- *   0 <= nu < 0.5, dgamma >= 0 (0: non-adhesive).
+ *   0 <= nu < 0.5, dgamma >= 0 (0: non-adhesive).  CB_KERNEL_PERIODIC
+ *   with dgamma > 0: CB_E_UNSUPPORTED.
  *   On success *out owns device tables and workspace (see cb_plan_info);
  *   on failure *out is NULL and a CB_E_* code is returned.
  */
 int cb_plan_create(cb_plan* out, int N, double L, double h, double E1,
                    double nu1, double E2, double nu2, double dgamma,
                    const cb_plan_opts* opts);
+
+/*
+ * cb_plan_create_layered -- as cb_plan_create for a coating of nlayers
+ *   bonded layers (h_host[i], E_host[i], nu_host[i]), i = 0 the top layer,
+ *   on a half-space (Es, nus).  The paper gives the one-layer solution
+ *   (Sec. 2, Eq. 5-9) and points to multi-layer systems (Sec. 1, its
+ *   reference [5]); here K^(k) is the same boundary-value problem (Eq. 5-8,
+ *   conditions (a)-(d), bonded interfaces) written for every layer and
+ *   solved per wavenumber, with the DC value of opts->dc_mode.  For one
+ *   layer it equals Eq. 9.  sigma_c (Eq. 12) uses the top layer's E*; the
+ *   Eq. 12 validity flag its h.  Host arrays of nlayers values, read only
+ *   during the call.  1 <= nlayers <= CB_MAX_LAYERS, every h > 0, E > 0,
+ *   0 <= nu < 0.5; other arguments as cb_plan_create.  Every solve, sweep
+ *   and apply entry point accepts the plan; the learned warm start gives
+ *   it no guess (zeros: the solve's cold start).
+ */
+int cb_plan_create_layered(cb_plan* out, int N, double L, int nlayers, const double* h_host,
+                           const double* E_host, const double* nu_host, double Es, double nus,
+                           double dgamma, const cb_plan_opts* opts);
+
+/* The FP64 padded-grid table of a layered stack ((N+1)^2 doubles, host),
+ * as cb_transfer_table; arguments as cb_plan_create_layered. */
+int cb_transfer_table_layered(int N, double L, int nlayers, const double* h_host, const double* E_host,
+                              const double* nu_host, double Es, double nus, int dc_mode,
+                              double* table_host, double* k00_host);
 
 /* Release a plan and everything it owns.  NULL is accepted (no-op). */
 int cb_plan_destroy(cb_plan plan);
@@ -180,8 +232,10 @@ int cb_plan_destroy(cb_plan plan);
 int cb_plan_get_info(cb_plan plan, cb_plan_info* info);
 
 /* Copy the FP64 transfer table T[a][b] = K^(Delta_k sqrt(a^2 + b^2)),
- * a, b in [0, N] ((N+1)^2 doubles, host memory, a row-major), DC at [0][0],
- * WITHOUT the 1/M^2 inverse-FFT factor the device copy carries. */
+ * a, b in [0, n), n = cb_plan_info.table_n (host memory, row-major), DC at
+ * [0][0], WITHOUT the inverse-FFT factor the device copy carries.  Padded
+ * plans: n = N + 1, Delta_k = 2 pi / (2 N Delta); periodic plans:
+ * n = N/2 + 1, Delta_k = 2 pi / L, T[0][0] = 0. */
 int cb_plan_get_table(cb_plan plan, double* table_host);
 
 /*

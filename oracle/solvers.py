@@ -295,3 +295,34 @@ def sweep(op: Operator, f, d_steps, sigma_c, attach_tol, dgamma, tol=1e-10,
                         U_el=0.5 * dA * float(np.sum(state.p * u)),
                         U_ad=-dgamma * A, rounds=rounds, converged=conv))
     return out, state
+
+
+def solve_nnls_force_singular(op, f, F, shift=None):
+    """Brute-force force control for an operator whose K is only positive
+    semi-definite along the uniform field (the periodic operator without a
+    DC term, Eq. 11): on the constraint set D^2 sum p = F the energy
+    1/2 p.K p - p.(d - f) changes by the constant c (sum p)^2 / 2 if K is
+    replaced by the definite K + c 1 1^T, so that problem is solved by
+    NNLS on its Cholesky factor with the approach d' bisected to the force,
+    and d = d' - c sum p.  Tiny grids only."""
+    dA = op.dx ** 2
+    f = np.asarray(f, dtype=np.float64)
+    K = op.dense_matrix()
+    n = K.shape[0]
+    c = float(np.trace(K)) / n if shift is None else float(shift)
+    R = scipy.linalg.cholesky(K + c * np.ones((n, n)), lower=False)
+
+    def solve(dp):
+        b = scipy.linalg.solve_triangular(R, (dp - f).ravel(), trans="T", lower=False)
+        p, _ = scipy.optimize.nnls(R, b, maxiter=50 * n)
+        return p.reshape(f.shape)
+
+    S = F / dA
+    lo = float(f.min())
+    hi = lo + 1e-3 * op.L
+    while solve(hi).sum() < S:
+        hi = lo + 2.0 * (hi - lo)
+    dp = scipy.optimize.brentq(lambda x: solve(x).sum() - S, lo, hi, xtol=1e-15 * op.L, rtol=1e-15)
+    p = solve(dp)
+    return p, dp - c * float(p.sum())
+

@@ -22,7 +22,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 FFT_VARIANTS = 6
 SOURCES = ([("plan.cpp", "plan", []), ("fft_dispatch.cpp", "fft_dispatch", []),
             ("solver.hip", "solver", []), ("batch.cpp", "batch", []), ("net.hip", "net", []),
-             ("noalloc.hip", "noalloc", [])]
+             ("noalloc.hip", "noalloc", []), ("layers.cpp", "layers", [])]
            + [("fft.hip", f"fft_v{k}", [f"-DCB_FFT_VARIANT={k}"]) for k in range(FFT_VARIANTS)])
 ARCH = os.environ.get("COATBEM_ARCH", "gfx950")
 

@@ -35,12 +35,16 @@ CB_FP64 = 0
 CB_FP32 = 1
 CB_DC_BZ = 0
 CB_DC_ZERO = 1
+CB_KERNEL_PADDED = 0
+CB_KERNEL_PERIODIC = 1
+_KERNEL_MODES = {"padded": CB_KERNEL_PADDED, "periodic": CB_KERNEL_PERIODIC}
 
 
 class cb_plan_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("dc_mode", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("autotune", ctypes.c_int),
-                ("tune_cache", ctypes.c_char_p), ("fft_variant", ctypes.c_int)]
+                ("tune_cache", ctypes.c_char_p), ("fft_variant", ctypes.c_int),
+                ("kernel_mode", ctypes.c_int)]
 
 
 class cb_solve_opts(ctypes.Structure):
@@ -72,7 +76,8 @@ class cb_plan_info(ctypes.Structure):
                 ("sigma_c", ctypes.c_double), ("k00", ctypes.c_double),
                 ("dc", ctypes.c_double), ("validity_warning", ctypes.c_int),
                 ("workspace_bytes", ctypes.c_size_t), ("fft_variant", ctypes.c_int),
-                ("tune_us", ctypes.c_double)]
+                ("tune_us", ctypes.c_double), ("kernel_mode", ctypes.c_int),
+                ("table_n", ctypes.c_int), ("nlayers", ctypes.c_int), ("H", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -84,6 +89,10 @@ _i = ctypes.c_int
 _SIGS = {
     "cb_plan_create": (_i, [ctypes.POINTER(_vp), _i, _d, _d, _d, _d, _d, _d, _d,
                             ctypes.POINTER(cb_plan_opts)]),
+    "cb_plan_create_layered": (_i, [ctypes.POINTER(_vp), _i, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d),
+                                    ctypes.POINTER(_d), _d, _d, _d, ctypes.POINTER(cb_plan_opts)]),
+    "cb_transfer_table_layered": (_i, [_i, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
+                                       _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "cb_plan_destroy": (_i, [_vp]),
     "cb_plan_get_info": (_i, [_vp, ctypes.POINTER(cb_plan_info)]),
     "cb_plan_get_table": (_i, [_vp, ctypes.POINTER(_d)]),
@@ -167,17 +176,49 @@ def _stream_ptr(stream):
 
 
 def cb_plan_create(N, L, h, E1, nu1, E2, nu2, dgamma=0.0, precision="fp64",
-                   dc_mode="bz", stream=None, autotune=0, tune_cache=None, fft_variant=0):
+                   dc_mode="bz", stream=None, autotune=0, tune_cache=None, fft_variant=0,
+                   kernel_mode="padded"):
     opts = cb_plan_opts(CB_FP64 if precision == "fp64" else CB_FP32,
                         CB_DC_BZ if dc_mode == "bz" else CB_DC_ZERO,
                         _stream_ptr(stream), int(autotune),
-                        None if tune_cache is None else os.fsencode(tune_cache), int(fft_variant))
+                        None if tune_cache is None else os.fsencode(tune_cache), int(fft_variant),
+                        _KERNEL_MODES[kernel_mode])
     h_ = ctypes.c_void_p()
     _check(_lib.cb_plan_create(ctypes.byref(h_), int(N), float(L), float(h),
                                float(E1), float(nu1), float(E2), float(nu2),
                                float(dgamma), ctypes.byref(opts)))
     return Plan(h_, int(N), torch.float64 if precision == "fp64" else torch.float32,
                 torch.device("cuda", torch.cuda.current_device()))
+
+
+def cb_plan_create_layered(N, L, layers, Es, nus, dgamma=0.0, precision="fp64", dc_mode="bz", stream=None,
+                           autotune=0, tune_cache=None, fft_variant=0, kernel_mode="padded"):
+    """layers: sequence of (h, E, nu), top layer first, on a half-space (Es, nus)."""
+    n = len(layers)
+    arr = lambda k: (_d * max(n, 1))(*[float(l[k]) for l in layers])
+    opts = cb_plan_opts(CB_FP64 if precision == "fp64" else CB_FP32,
+                        CB_DC_BZ if dc_mode == "bz" else CB_DC_ZERO,
+                        _stream_ptr(stream), int(autotune),
+                        None if tune_cache is None else os.fsencode(tune_cache), int(fft_variant),
+                        _KERNEL_MODES[kernel_mode])
+    h_ = ctypes.c_void_p()
+    _check(_lib.cb_plan_create_layered(ctypes.byref(h_), int(N), float(L), n, arr(0), arr(1), arr(2),
+                                       float(Es), float(nus), float(dgamma), ctypes.byref(opts)))
+    return Plan(h_, int(N), torch.float64 if precision == "fp64" else torch.float32,
+                torch.device("cuda", torch.cuda.current_device()))
+
+
+def cb_transfer_table_layered(N, L, layers, Es, nus, dc_mode="bz"):
+    """Host-computed FP64 padded table ((N+1)^2) of a layered stack and k00."""
+    import numpy as np
+    n = len(layers)
+    arr = lambda k: (_d * max(n, 1))(*[float(l[k]) for l in layers])
+    out = np.empty((N + 1, N + 1), dtype=np.float64)
+    k00 = ctypes.c_double()
+    _check(_lib.cb_transfer_table_layered(int(N), float(L), n, arr(0), arr(1), arr(2), float(Es), float(nus),
+                                          CB_DC_BZ if dc_mode == "bz" else CB_DC_ZERO,
+                                          out.ctypes.data_as(ctypes.POINTER(_d)), ctypes.byref(k00)))
+    return out, k00.value
 
 
 def cb_plan_destroy(plan: Plan):
@@ -194,7 +235,8 @@ def cb_plan_get_info(plan: Plan):
 
 def cb_plan_get_table(plan: Plan):
     import numpy as np
-    out = np.empty((plan.N + 1, plan.N + 1), dtype=np.float64)
+    n = cb_plan_get_info(plan)["table_n"]
+    out = np.empty((n, n), dtype=np.float64)
     _check(_lib.cb_plan_get_table(plan.handle, out.ctypes.data_as(ctypes.POINTER(_d))))
     return out
 

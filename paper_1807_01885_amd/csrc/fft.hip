@@ -595,43 +595,48 @@ static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T
   auto k1 = k_rows_fwd<T, LOG2N, PAD, RB, SH::NT1, G>;
   auto k2 = k_cols<T, LOG2N, PAD, RB, SH::NT2, SH::CB>;
   auto k3 = k_rows_inv<T, LOG2N, PAD, RB, SH::NT1, G>;
-  // the solver work the row transforms may carry: on the padded (direction)
-  // convolution the direction update (K1) and the step sums (K3), on the
-  // periodic (preconditioner) one the masked gradient (K1) and the sums of
-  // the preconditioned gradient (K3)
-  constexpr int EPI = PAD ? 1 : 2, PRO = PAD ? 2 : 1;
-  auto k1e = k_rows_fwd<T, LOG2N, PAD, RB, SH::NT1, G, PRO>;
-  auto k3e = k_rows_inv<T, LOG2N, PAD, RB, SH::NT1, G, EPI>;
+  // the solver work the row transforms may carry: on the direction
+  // convolution the direction update (K1, PRO 2) and the step sums (K3,
+  // EPI 1); on the preconditioner convolution the masked gradient (K1,
+  // PRO 1) and the sums of the preconditioned gradient (K3, EPI 2).  The
+  // padded transforms only ever carry the direction; the periodic ones
+  // carry either (periodic plans convolve their directions periodically).
+  auto k1d = k_rows_fwd<T, LOG2N, PAD, RB, SH::NT1, G, 2>;
+  auto k3d = k_rows_inv<T, LOG2N, PAD, RB, SH::NT1, G, 1>;
+  auto k1p = k_rows_fwd<T, LOG2N, PAD, RB, SH::NT1, G, PAD ? 2 : 1>;
+  auto k3p = k_rows_inv<T, LOG2N, PAD, RB, SH::NT1, G, PAD ? 1 : 2>;
   // set once per instantiation (plan creation calls this before any
   // capture; plans may be created on several threads, and setting the
   // attributes twice is harmless)
   static std::atomic<bool> attr{false};
   if (!attr.load(std::memory_order_acquire)) {
     hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
-    hipFuncSetAttribute((const void*)k1e, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
+    hipFuncSetAttribute((const void*)k1d, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
+    hipFuncSetAttribute((const void*)k1p, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
     hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
     hipFuncSetAttribute((const void*)k3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
-    hipFuncSetAttribute((const void*)k3e, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
+    hipFuncSetAttribute((const void*)k3d, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
+    hipFuncSetAttribute((const void*)k3p, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
     attr.store(true, std::memory_order_release);
   }
   const int nb_rows = N / (RB * G);
   const int nb_cols = (NC - 1 + SH::CB - 1) / SH::CB;  // DC and Nyquist columns packed
-  if (epi && ((epi->mode != 0 && epi->mode != EPI) || (epi->pro != 0 && epi->pro != PRO)))
+  if (epi && ((epi->mode != 0 && epi->mode != 1 && (PAD || epi->mode != 2)) ||
+              (epi->pro != 0 && epi->pro != 2 && (PAD || epi->pro != 1))))
     return hipErrorInvalidValue;
+  const dim3 grows(nb_rows), brows(G * RB * SH::NT1);
   if (stages & 1) {
-    if (epi && epi->pro != 0)
-      hipLaunchKernelGGL(k1e, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw, skip, *epi);
-    else
-      hipLaunchKernelGGL(k1, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, p, S, tw, skip, EpiArgs{});
+    const int pro = epi ? epi->pro : 0;
+    if (pro == 2) hipLaunchKernelGGL(k1d, grows, brows, lr, st, p, S, tw, skip, *epi);
+    else if (pro == 1) hipLaunchKernelGGL(k1p, grows, brows, lr, st, p, S, tw, skip, *epi);
+    else hipLaunchKernelGGL(k1, grows, brows, lr, st, p, S, tw, skip, EpiArgs{});
   }
   if (stages & 2) hipLaunchKernelGGL(k2, dim3(nb_cols), dim3(SH::CB * SH::NT2), lc, st, S, Tq, tw, skip);
   if (stages & 4) {
-    if (epi && epi->mode != 0) {
-      hipLaunchKernelGGL(k3e, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw, skip, *epi);
-    } else {
-      hipLaunchKernelGGL(k3, dim3(nb_rows), dim3(G * RB * SH::NT1), lr, st, (const cx<T>*)S, u, tw, skip,
-                         EpiArgs{});
-    }
+    const int mode = epi ? epi->mode : 0;
+    if (mode == 1) hipLaunchKernelGGL(k3d, grows, brows, lr, st, (const cx<T>*)S, u, tw, skip, *epi);
+    else if (mode == 2) hipLaunchKernelGGL(k3p, grows, brows, lr, st, (const cx<T>*)S, u, tw, skip, *epi);
+    else hipLaunchKernelGGL(k3, grows, brows, lr, st, (const cx<T>*)S, u, tw, skip, EpiArgs{});
   }
   return hipGetLastError();
 }
@@ -671,10 +676,12 @@ hipError_t CB_CAT(launch_apply_v, CB_FFT_VARIANT)(const cb_plan_s* P, const void
                                                  int stages, const int* skip, const void* table, int prec,
                                                  const EpiArgs* epi) {
   using namespace CB_CAT(fftv, CB_FFT_VARIANT);
-  // stages bit 3: the N-periodic convolution (its table must be given)
-  const bool periodic = (stages & 8) != 0;
+  // stages bit 3: the N-periodic convolution with the given table (the
+  // preconditioners); a periodic plan's operator is N-periodic as well
+  const bool given = (stages & 8) != 0;
+  const bool periodic = given || P->kernel_mode == CB_KERNEL_PERIODIC;
   stages &= 7;
-  if (periodic && !table) return hipErrorInvalidValue;
+  if (given && !table) return hipErrorInvalidValue;
   if (prec == 0) {
     if (!table) table = P->precision == 0 ? P->d_table : P->d_table64;
     return apply_any<double>(periodic, stages, skip, P->log2n, (const double*)p, (double*)u, (cx<double>*)P->d_S,

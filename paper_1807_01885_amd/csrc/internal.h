@@ -91,16 +91,33 @@ constexpr FftVariant kFftVariants[CB_FFT_VARIANTS] = {
     {16, 16, 1}, {16, 8, 1}, {8, 16, 1}, {16, 16, 2}, {16, 32, 1}, {8, 8, 2}};
 }  // namespace cb
 
+namespace cb {
+// A stack of bonded layers (top first) on a half-space.
+struct LayerStack {
+  std::vector<double> h, E, nu;
+  double Es = 0.0, nus = 0.0;
+};
+// K^(k) of the stack (k > 0), by the per-wavenumber boundary-value problem
+double layered_compliance(double k, const LayerStack& S);
+// out[a][b] = K^(dk sqrt(a^2 + b^2)) for a, b in [0, n) (out[0][0] = 0)
+void layered_compliance_grid(const LayerStack& S, double dk, int n, std::vector<double>& out);
+}  // namespace cb
+
 struct cb_plan_s {
   int N = 0, M = 0, log2n = 0, precision = 0, dc_mode = 0;
+  int kernel_mode = CB_KERNEL_PADDED;  // CB_KERNEL_PERIODIC: N-periodic operator, no DC
+  int table_n = 0;                     // side of the transfer quadrant (N+1 or N/2+1)
+  int layered = 0;                     // 1: transfer function of `stack` (any number of layers)
+  cb::LayerStack stack;                // layers (top first) and half-space of a layered plan
+  double H = 0.0;                      // total coating thickness (h for a single layer)
   double L = 0, dx = 0, h = 0, E1 = 0, nu1 = 0, E2 = 0, nu2 = 0, dgamma = 0;
   double E1s = 0, E2s = 0, sigma_c = 0, k00 = 0, dc = 0;
   int validity_warning = 0;
   hipStream_t stream = nullptr;
   int device = 0;
-  std::vector<double> table64;   // (N+1)^2, no 1/M^2
+  std::vector<double> table64;   // table_n^2, no inverse-FFT factor
   // device memory owned by the plan
-  void* d_table = nullptr;       // (N+1)^2, 1/M^2 folded, plan type
+  void* d_table = nullptr;       // table_n^2, 1/M^2 (periodic: 1/N^2) folded, plan type
   void* d_table64 = nullptr;     // FP64 copy for FP32 plans (exact refreshes)
   void* d_ptable = nullptr;      // preconditioner symbol 1/C(kh) on the N-periodic grid,
                                  // (N/2+1)^2, 1/N^2 folded
@@ -226,6 +243,12 @@ CB_DECLARE_FFT_VARIANT(5)
 bool fft_variant_fits(int v, int log2n, int prec, int device);
 // time every fitting variant for the plan's precision, or take it from the cache
 int autotune_fft(cb_plan_s* P, int autotune, const char* cache);
+}  // namespace cb
+
+namespace cb {
+// C(k) = E1* k K^(k) / 2 of the plan's material (E1* of the top layer): the
+// transfer function relative to a homogeneous half-space of the coating
+double plan_shape(const cb_plan_s* P, double k);
 }  // namespace cb
 
 namespace cb {

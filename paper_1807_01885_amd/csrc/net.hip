@@ -742,9 +742,10 @@ extern "C" int cb_net_warmstart_batch(cb_net N, int n, const cb_plan* plans, con
   if (int rc = cb_net_forward(N, n, N->feat, nullptr)) return rc;
   for (int i = 0; i < n; i++) {
     const cb_plan P = plans[i];
-    if (P->precond_auto == 1) {
+    if (P->precond_auto == 1 || P->layered || P->kernel_mode != CB_KERNEL_PADDED) {
       // stiff thin coating: no guess (zeros; the solve then takes its cold
-      // start): the network's guess measured slower than a cold start there
+      // start): the network's guess measured slower than a cold start there.
+      // Layered stacks and periodic plans lie outside its training data.
       hipLaunchKernelGGL(k_fill0, egrid((long long)P->N * P->N), dim3(256), 0, N->stream, p_out[i],
                          (long long)P->N * P->N);
       continue;

@@ -135,24 +135,68 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
 }  // namespace
 
-// T[a][b] = K^(dk sqrt(a^2 + b^2)), a, b in [0, N], dk = 2 pi / (M D), the
-// normalised Eq. 9-10; T[0][0] per dc_mode.  k00 = sum over the full M x M
-// grid of T, divided by M^2 (the self-influence of a cell).
+// Integral of K^ over the Brillouin zone for a layered plan:
+//   (16/E1*) [ (pi/D) ln(1+sqrt 2) + int_0^{pi/4} Phi(K(th)) dth ],
+//   Phi(K) = int_0^K (C(k) - 1) dk,  K(th) = (pi/D)/cos th,
+// with C - 1 integrated over geometric panels from 1e-4/H (H the total
+// thickness) to 40/h_top, beyond which it is below e^-80.
+static double brillouin_integral_layered(double dx, const cb::LayerStack& S, double E1s) {
+  const double kmax = M_PI / dx;
+  const double base = kmax * std::log(1.0 + std::sqrt(2.0));
+  double H = 0.0;
+  for (double hi : S.h) H += hi;
+  std::vector<double> x, w;
+  gauss_legendre(20, x, w);
+  auto cm1 = [&](double k) { return E1s * k * cb::layered_compliance(k, S) / 2.0 - 1.0; };
+  const double k0 = 1e-4 / H, kcut = 40.0 / S.h[0];
+  auto phi = [&](double K) {
+    const double top = K < kcut ? K : kcut;
+    double s = 0.0, a = 0.0, b = k0;
+    while (a < top) {
+      const double hi = b < top ? b : top;
+      s += integrate(cm1, a, hi, 1, x, w);
+      a = hi;
+      b = a * 1.3;
+    }
+    return s;
+  };
+  double outer;
+  if (kmax >= kcut) {
+    outer = (M_PI / 4.0) * phi(kcut);
+  } else {
+    outer = integrate([&](double th) { return phi(kmax / std::cos(th)); }, 0.0, M_PI / 4.0, 16, x, w);
+  }
+  return 16.0 / E1s * (base + outer);
+}
+
+// T[a][b] = K^(dk sqrt(a^2 + b^2)), a, b in [0, N], dk = 2 pi / (M D): the
+// normalised Eq. 9-10, or the layered compliance when S is given;
+// T[0][0] per dc_mode.  k00 = sum over the full M x M grid of T, divided by
+// M^2 (the self-influence of a cell).
 static void build_table(int N, double L, double h, double E1, double nu1, double E2, double nu2,
-                        int dc_mode, std::vector<double>& table, double& dc, double& k00) {
+                        int dc_mode, std::vector<double>& table, double& dc, double& k00,
+                        const cb::LayerStack* S = nullptr) {
   const int NC = N + 1, M = 2 * N;
   const double dx = L / N, E1s = E1 / (1.0 - nu1 * nu1);
   const Coef c = coefficients(E1, nu1, E2, nu2);
   const double dk = 2.0 * M_PI / (M * dx);
-  table.assign((size_t)NC * NC, 0.0);
+  if (S) {
+    cb::layered_compliance_grid(*S, dk, NC, table);
+  } else {
+    table.assign((size_t)NC * NC, 0.0);
+    for (int a = 0; a < NC; a++)
+      for (int b = 0; b < NC; b++) {
+        if (a == 0 && b == 0) continue;
+        const double k = dk * std::sqrt((double)a * a + (double)b * b);
+        table[(size_t)a * NC + b] = 2.0 / (E1s * k) * shape(k * h, c);
+      }
+  }
   // Kahan sum of K^ over the full M x M grid except k = 0, by quadrant weights
   double sum = 0.0, comp = 0.0;
   for (int a = 0; a < NC; a++) {
     for (int b = 0; b < NC; b++) {
       if (a == 0 && b == 0) continue;
-      const double k = dk * std::sqrt((double)a * a + (double)b * b);
-      const double v = 2.0 / (E1s * k) * shape(k * h, c);
-      table[(size_t)a * NC + b] = v;
+      const double v = table[(size_t)a * NC + b];
       const double wgt = (a == 0 || a == N ? 1.0 : 2.0) * (b == 0 || b == N ? 1.0 : 2.0);
       const double y = wgt * v - comp;
       const double t = sum + y;
@@ -160,9 +204,48 @@ static void build_table(int N, double L, double h, double E1, double nu1, double
       sum = t;
     }
   }
-  dc = dc_mode == CB_DC_BZ ? brillouin_integral(dx, h, E1s, c) / (dk * dk) - sum : 0.0;
+  const double bz = dc_mode != CB_DC_BZ ? 0.0
+                    : S ? brillouin_integral_layered(dx, *S, E1s)
+                        : brillouin_integral(dx, h, E1s, c);
+  dc = dc_mode == CB_DC_BZ ? bz / (dk * dk) - sum : 0.0;
   table[0] = dc;
   k00 = (sum + dc) / ((double)M * M);
+}
+
+// Eq. 11 taken literally: T[a][b] = K^((2 pi / L) sqrt(a^2 + b^2)) on the
+// N-periodic grid's quadrant a, b in [0, N/2], no DC component (T[0][0] = 0);
+// k00 = sum over the full N x N grid of T, divided by N^2.
+static void build_periodic_table(int N, double L, double h, double E1, double nu1, double E2, double nu2,
+                                 std::vector<double>& table, double& k00, const cb::LayerStack* S = nullptr) {
+  const int NP = N / 2 + 1;
+  const double E1s = E1 / (1.0 - nu1 * nu1);
+  const Coef c = coefficients(E1, nu1, E2, nu2);
+  const double dk = 2.0 * M_PI / L;
+  if (S) {
+    cb::layered_compliance_grid(*S, dk, NP, table);
+  } else {
+    table.assign((size_t)NP * NP, 0.0);
+    for (int a = 0; a < NP; a++)
+      for (int b = 0; b < NP; b++) {
+        if (a == 0 && b == 0) continue;
+        const double k = dk * std::sqrt((double)a * a + (double)b * b);
+        table[(size_t)a * NP + b] = 2.0 / (E1s * k) * shape(k * h, c);
+      }
+  }
+  double sum = 0.0, comp = 0.0;
+  for (int a = 0; a < NP; a++) {
+    for (int b = 0; b < NP; b++) {
+      if (a == 0 && b == 0) continue;
+      const double v = table[(size_t)a * NP + b];
+      const double wgt = (a == 0 || a == N / 2 ? 1.0 : 2.0) * (b == 0 || b == N / 2 ? 1.0 : 2.0);
+      const double y = wgt * v - comp;
+      const double t = sum + y;
+      comp = (t - sum) - y;
+      sum = t;
+    }
+  }
+  table[0] = 0.0;
+  k00 = sum / ((double)N * N);
 }
 
 static int check_params(int N, double L, double h, double E1, double nu1, double E2, double nu2,
@@ -191,6 +274,12 @@ extern "C" int cb_transfer_table(int N, double L, double h, double E1, double nu
   return CB_OK;
 }
 
+double cb::plan_shape(const cb_plan_s* P, double k) {
+  if (!P->layered) return shape(k * P->h, coefficients(P->E1, P->nu1, P->E2, P->nu2));
+  if (!(k > 0.0)) return P->E1s / P->E2s;
+  return P->E1s * k * layered_compliance(k, P->stack) / 2.0;
+}
+
 std::mutex& cb::graph_mutex() {
   static std::mutex mu;
   return mu;
@@ -215,8 +304,64 @@ static void free_plan_memory(cb_plan_s* P) {
   if (P->h_state) (void)hipHostFree(P->h_state);
 }
 
+// Layered stacks: 1..CB_MAX_LAYERS layers with h > 0, E > 0, 0 <= nu < 0.5.
+static int check_stack(int nlayers, const double* h, const double* E, const double* nu, double Es, double nus,
+                       cb::LayerStack& S) {
+  if (nlayers < 1 || nlayers > CB_MAX_LAYERS)
+    return cb_fail(CB_E_INVALID, "nlayers must lie in [1, " + std::to_string(CB_MAX_LAYERS) + "]");
+  if (!h || !E || !nu) return cb_fail(CB_E_INVALID, "null layer array");
+  S = cb::LayerStack{};
+  for (int i = 0; i < nlayers; i++) {
+    if (!finite_pos(h[i]) || !finite_pos(E[i]) || !(nu[i] >= 0.0 && nu[i] < 0.5))
+      return cb_fail(CB_E_INVALID, "layer " + std::to_string(i) + ": need h > 0, E > 0, 0 <= nu < 0.5");
+    S.h.push_back(h[i]);
+    S.E.push_back(E[i]);
+    S.nu.push_back(nu[i]);
+  }
+  S.Es = Es;
+  S.nus = nus;
+  return CB_OK;
+}
+
+static int plan_create_impl(cb_plan* out, int N, double L, double h, double E1, double nu1, double E2, double nu2,
+                            double dgamma, const cb_plan_opts* o, const cb::LayerStack* S);
+
 extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1, double nu1,
                               double E2, double nu2, double dgamma, const cb_plan_opts* o) {
+  return plan_create_impl(out, N, L, h, E1, nu1, E2, nu2, dgamma, o, nullptr);
+}
+
+extern "C" int cb_plan_create_layered(cb_plan* out, int N, double L, int nlayers, const double* h,
+                                      const double* E, const double* nu, double Es, double nus, double dgamma,
+                                      const cb_plan_opts* o) {
+  if (!out) return cb_fail(CB_E_INVALID, "out is NULL");
+  *out = nullptr;
+  cb::LayerStack S;
+  if (int rc = check_stack(nlayers, h, E, nu, Es, nus, S)) return rc;
+  double H = 0.0;
+  for (double x : S.h) H += x;
+  if (int rc = check_params(N, L, H, E[0], nu[0], Es, nus, dgamma)) return rc;
+  return plan_create_impl(out, N, L, h[0], E[0], nu[0], Es, nus, dgamma, o, &S);
+}
+
+extern "C" int cb_transfer_table_layered(int N, double L, int nlayers, const double* h, const double* E,
+                                         const double* nu, double Es, double nus, int dc_mode, double* out,
+                                         double* k00_out) {
+  if (!out) return cb_fail(CB_E_INVALID, "null output");
+  cb::LayerStack S;
+  if (int rc = check_stack(nlayers, h, E, nu, Es, nus, S)) return rc;
+  if (int rc = check_params(N, L, h[0], E[0], nu[0], Es, nus, 0.0)) return rc;
+  if (dc_mode != CB_DC_BZ && dc_mode != CB_DC_ZERO) return cb_fail(CB_E_INVALID, "bad dc_mode");
+  std::vector<double> t;
+  double dc, k00;
+  build_table(N, L, h[0], E[0], nu[0], Es, nus, dc_mode, t, dc, k00, &S);
+  std::memcpy(out, t.data(), t.size() * sizeof(double));
+  if (k00_out) *k00_out = k00;
+  return CB_OK;
+}
+
+static int plan_create_impl(cb_plan* out, int N, double L, double h, double E1, double nu1, double E2, double nu2,
+                            double dgamma, const cb_plan_opts* o, const cb::LayerStack* S) {
   if (!out) return cb_fail(CB_E_INVALID, "out is NULL");
   *out = nullptr;
   if (int rc = check_params(N, L, h, E1, nu1, E2, nu2, dgamma)) return rc;
@@ -229,11 +374,19 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
   if (opts.autotune != 0 && opts.autotune != 1) return cb_fail(CB_E_INVALID, "autotune must be 0 or 1");
   if (opts.fft_variant < 0 || opts.fft_variant > cb::CB_FFT_VARIANTS)
     return cb_fail(CB_E_INVALID, "fft_variant must be 0 (automatic) or 1.." + std::to_string(cb::CB_FFT_VARIANTS));
+  if (opts.kernel_mode != CB_KERNEL_PADDED && opts.kernel_mode != CB_KERNEL_PERIODIC)
+    return cb_fail(CB_E_INVALID, "kernel_mode must be CB_KERNEL_PADDED or CB_KERNEL_PERIODIC");
+  if (opts.kernel_mode == CB_KERNEL_PERIODIC && dgamma > 0.0)
+    return cb_fail(CB_E_UNSUPPORTED, "adhesion needs a non-periodic kernel (Eq. 12 is derived for a non-periodic "
+                                     "system)");
 
   auto* P = new (std::nothrow) cb_plan_s();
   if (!P) return cb_fail(CB_E_NOMEM, "host allocation failed");
   P->N = N;
-  P->M = 2 * N;
+  P->kernel_mode = opts.kernel_mode;
+  const bool periodic = opts.kernel_mode == CB_KERNEL_PERIODIC;
+  P->M = periodic ? N : 2 * N;
+  P->table_n = periodic ? N / 2 + 1 : N + 1;
   P->log2n = 0;
   while ((1 << P->log2n) < N) P->log2n++;
   P->precision = opts.precision;
@@ -252,10 +405,22 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
   // Eq. 12
   P->sigma_c = dgamma > 0.0 ? std::sqrt(P->E1s * dgamma / (0.473201 * P->dx)) : 0.0;
   P->validity_warning = (dgamma > 0.0 && h < 5.0 * P->dx) ? 1 : 0;
+  P->layered = S ? 1 : 0;
+  P->H = h;
+  if (S) {
+    P->stack = *S;
+    P->H = 0.0;
+    for (double x : S->h) P->H += x;
+  }
 
-  // ---- FP64 transfer table on the quadrant a, b in [0, N] ----------------
+  // ---- FP64 transfer table on the quadrant a, b in [0, table_n) ----------
   const int M = P->M, NC = N + 1;
-  build_table(N, L, h, E1, nu1, E2, nu2, opts.dc_mode, P->table64, P->dc, P->k00);
+  if (periodic) {
+    build_periodic_table(N, L, h, E1, nu1, E2, nu2, P->table64, P->k00, S);
+    P->dc = 0.0;
+  } else {
+    build_table(N, L, h, E1, nu1, E2, nu2, opts.dc_mode, P->table64, P->dc, P->k00, S);
+  }
 
   // ---- device memory ---------------------------------------------------------
   const size_t es = P->precision == CB_FP64 ? 8 : 4;
@@ -276,19 +441,38 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
   const double invN = 1.0 / ((double)N * N);
   std::vector<double> pdev((size_t)NP * NP), qdev((size_t)NP * NP);
   {
-    const Coef cf = coefficients(E1, nu1, E2, nu2);
     const double dk = 2.0 * M_PI / L;
+    std::vector<double> cgrid;
+    if (S) {
+      // C(k) = E1* k K^ / 2 of the stack on the periodic grid (C(0) = E1*/Es*)
+      if (periodic) {
+        cgrid = P->table64;
+      } else {
+        cb::layered_compliance_grid(*S, dk, NP, cgrid);
+      }
+      for (int a = 0; a < NP; a++)
+        for (int b = 0; b < NP; b++) {
+          const double k = dk * std::sqrt((double)a * a + (double)b * b);
+          double& v = cgrid[(size_t)a * NP + b];
+          v = (a == 0 && b == 0) ? P->E1s / P->E2s : P->E1s * k * v / 2.0;
+        }
+    }
+    const Coef cf = coefficients(E1, nu1, E2, nu2);
     for (int a = 0; a < NP; a++)
       for (int b = 0; b < NP; b++) {
         const double k = dk * std::sqrt((double)a * a + (double)b * b);
-        pdev[(size_t)a * NP + b] = invN / shape(k * h, cf);
-        qdev[(size_t)a * NP + b] = invN / P->table64[(size_t)(2 * a) * NC + 2 * b];
+        pdev[(size_t)a * NP + b] = invN / (S ? cgrid[(size_t)a * NP + b] : shape(k * h, cf));
+        // a periodic plan has no DC value: its inverse symbol takes that
+        // of the first harmonic there (any positive value keeps M SPD)
+        qdev[(size_t)a * NP + b] =
+            periodic ? invN / P->table64[(a == 0 && b == 0) ? 1 : (size_t)a * NP + b]
+                     : invN / P->table64[(size_t)(2 * a) * NC + 2 * b];
       }
   }
   // automatic choice from a cold start: the layer multiplier for a coating
   // at least 3x stiffer than the substrate and thin relative to the domain,
   // else none (from a caller's guess the solver takes the inverse symbol)
-  P->precond_auto = (P->E1s >= 3.0 * P->E2s && h <= L / 16.0) ? 1 : 0;
+  P->precond_auto = (P->E1s >= 3.0 * P->E2s && P->H <= L / 16.0) ? 1 : 0;
 
   const size_t n2 = (size_t)N * N;
   int rc = CB_OK;
@@ -306,7 +490,8 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
     long long nb = (n + 1023) / 1024;
     P->nbr = (int)(nb < SOLVER_BLOCKS_MAX ? (nb < 1 ? 1 : nb) : SOLVER_BLOCKS_MAX);
   }
-  alloc(&P->d_table, (size_t)NC * NC * es);
+  const size_t ntab = (size_t)P->table_n * P->table_n;
+  alloc(&P->d_table, ntab * es);
   alloc(&P->d_ptable, (size_t)NP * NP * es);
   alloc(&P->d_pinv, (size_t)NP * NP * es);
   // the intermediate and the solver arrays are sized for FP64 in both
@@ -319,7 +504,7 @@ extern "C" int cb_plan_create(cb_plan* out, int N, double L, double h, double E1
   alloc(&P->d_g, n2 * 8);
   alloc(&P->d_pold, n2 * 8);
   alloc(&P->d_y, n2 * 8);
-  if (P->precision == CB_FP32) alloc(&P->d_table64, (size_t)NC * NC * 8);
+  if (P->precision == CB_FP32) alloc(&P->d_table64, ntab * 8);
   alloc((void**)&P->d_mask, n2);
   alloc((void**)&P->d_mask2, n2);
   alloc((void**)&P->d_det, n2);
@@ -414,6 +599,10 @@ extern "C" int cb_plan_get_info(cb_plan P, cb_plan_info* info) {
   I.workspace_bytes = P->workspace_bytes;
   I.fft_variant = P->variant[P->precision == CB_FP64 ? 0 : 1] + 1;
   I.tune_us = P->tune_us;
+  I.kernel_mode = P->kernel_mode;
+  I.table_n = P->table_n;
+  I.nlayers = P->layered ? (int)P->stack.h.size() : 1;
+  I.H = P->H;
   *info = I;
   return CB_OK;
 }

@@ -769,7 +769,7 @@ static hipError_t pk_enqueue_chunk(const Ctx& c, double* p, const double* f, boo
   const int* skip_done = &st->done;   // {done, zero}
   const int* skip_u = &st->skip_u;    // {skip_u, done}
   // blocks of the inverse row transforms that carry the step and z' sums
-  const int nb3d = rows_blocks(P, -1, false), nb3p = rows_blocks(P, -1, true);
+  const int nb3d = rows_blocks(P, -1, P->kernel_mode == CB_KERNEL_PERIODIC), nb3p = rows_blocks(P, -1, true);
   // the fused row-transform sums write 4 (step) or 2 (z') partials per block
   if (nb3d < 1 || nb3p < 1 || 4 * nb3d > REG_STRIDE - 8 || 2 * nb3p > REG_STRIDE - 8) return hipErrorInvalidValue;
   double* pgap = part + (size_t)(R_GAP0) * REG_STRIDE;
@@ -1041,7 +1041,6 @@ static int cold_start_force(const Ctx& c, const double* f, double fmin, double f
     double hist[2 * HB];
     CB_HIP(hipMemcpyAsync(hist, P->d_pold, sizeof(hist), hipMemcpyDeviceToHost, c.st));
     CB_HIP(hipStreamSynchronize(c.st));
-    const Coef cf = coefficients(P->E1, P->nu1, P->E2, P->nu2);
     const double emin = range / HSPAN, r = std::pow(HSPAN, 1.0 / (HB - 1));
     const double unit = range / 1099511627776.0;
     const double dA = P->dx * P->dx;
@@ -1051,7 +1050,7 @@ static int cold_start_force(const Ctx& c, const double* f, double fmin, double f
       S += hist[HB + b] * unit;
       if (C <= 0.0) continue;
       const double A = C * dA, dbar = edge - S / C, k = 2.0 / std::sqrt(A);
-      const double Fm = 1.1 * P->E1s / shape(k * P->h, cf) * std::sqrt(A) * dbar;
+      const double Fm = 1.1 * P->E1s / plan_shape(P, k) * std::sqrt(A) * dbar;
       if (Fm >= F) {
         d0 = fmin + 0.7 * edge;
         found = true;

@@ -65,7 +65,7 @@ def rough_surface(N, L, hurst=0.7, qr_factor=4.0, rms=None, seed=0):
     qL = 2.0 * np.pi / L
     qr = qr_factor * qL
     qs = np.pi / dx
-    C = np.where(q < qr, 1.0, (np.maximum(q, 1e-300) / qr) ** (-2.0 * (1.0 + hurst)))
+    C = np.where(q < qr, 1.0, (np.maximum(q, qr) / qr) ** (-2.0 * (1.0 + hurst)))
     C = np.where((q >= qL * (1 - 1e-12)) & (q <= qs * (1 + 1e-12)), C, 0.0)
     amp = np.sqrt(C) * (rng.standard_normal(q.shape) + 1j * rng.standard_normal(q.shape))
     z = np.fft.irfft2(amp, s=(N, N))
