@@ -136,6 +136,10 @@ typedef struct {
                         Adhesive solves (CG on the contact set): 0, 1 or 2,
                         automatic 2.  The converged pressure is the same;
                         other values: CB_E_INVALID. */
+  double preload_d;  /* adhesive cb_solve_force with F <= 0: rigid approach
+                        of the preload before the retraction; <= min f:
+                        automatic, the approach at which the non-adhesive
+                        solve carries max(4 |F|, pi dgamma L / 2) */
 } cb_solve_opts;
 
 /* Per-solve (or per-step) outcome, filled on the host. */
@@ -328,8 +332,22 @@ int cb_solve_indent(cb_plan plan, const double* f, double d, double* p_io,
  *   where a ring of cells detaches, and then several approaches carry F:
  *   the search returns the one its bracket closes on.  res->F is the force reached,
  *   p_io / mask_io the solve at res->d, res->iters and res->rounds the
- *   totals over all solves of the search.  F <= 0 on an adhesive plan:
- *   CB_E_UNSUPPORTED; no bracket within 60 doublings: CB_E_NOCONV.
+ *   totals over all solves of the search; no bracket within 60 doublings:
+ *   CB_E_NOCONV.
+ *   Adhesive plans, F <= 0 (pull-off under force control, Sec. 3.1, Eq. 19):
+ *   preload by the single adhesive solve at opts->preload_d, then the
+ *   paper's quasi-static retraction in displacement steps of
+ *   (preload_d - min f) / 32, each step carrying the contact set and the
+ *   pressure (as cb_sweep).  While the force keeps falling these are the
+ *   states a force-controlled unloading passes through; in the first step
+ *   whose force is at or below F the approach carrying F is found by
+ *   regula falsi over single steps from the state of the step before (to
+ *   1e-6 of max(|F|, 1e-3 x the preload force), or the nearer side of a
+ *   detachment jump).  If the contact is
+ *   lost first, F lies below the pull-off force: CB_E_NOCONV, with p_io /
+ *   mask_io / res the step of the lowest force met (res->F is the
+ *   force-controlled pull-off force to within one step).  Non-adhesive
+ *   plans need F >= 0.
  */
 int cb_solve_force(cb_plan plan, const double* f, double F, double* p_io,
                    unsigned char* mask_io, const cb_solve_opts* opts,
@@ -367,6 +385,21 @@ int cb_sweep(cb_plan plan, const double* f, const double* d_steps_host,
 int cb_solve_batch(int n, const cb_plan* plans, const double* const* f,
                    const double* target, const int* mode, double* const* p_io,
                    const cb_solve_opts* opts, int workers, cb_result* out_host);
+
+/*
+ * cb_sweep_batch -- n independent quasi-static sweeps (cb_sweep, Sec. 2 last
+ *   paragraph) run concurrently, each on its own plan's stream: problem i
+ *   uses plans[i] (adhesive; distinct plans required), f[i],
+ *   d_steps_host[i] (nsteps[i] approaches, host), its state
+ *   p_state[i] / mask_state[i] (device, carried in and out as in cb_sweep)
+ *   and per_step_host[i] (nsteps[i] results, host).  Up to `workers`
+ *   (<= 0: 16) sweeps are in flight, the largest N^2 x nsteps first.
+ *   Returns CB_OK if every sweep succeeded, else the first failing status
+ *   in problem order.  Blocks until all are done.
+ */
+int cb_sweep_batch(int n, const cb_plan* plans, const double* const* f, const double* const* d_steps_host,
+                   const int* nsteps, double* const* p_state, unsigned char* const* mask_state,
+                   const cb_solve_opts* opts, int workers, cb_result* const* per_step_host);
 
 /* ------------------------------------------------------------------------
  * Learned warm start (not part of the paper).  A small U-Net maps the

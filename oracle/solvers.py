@@ -326,3 +326,75 @@ def solve_nnls_force_singular(op, f, F, shift=None):
     p = solve(dp)
     return p, dp - c * float(p.sum())
 
+
+@dataclass
+class RetractionResult:
+    state: AdhesiveState
+    d: float
+    F: float
+    reached: bool
+    steps: list
+    before: AdhesiveState = None   # state of the last step above F (None if not reached)
+    d_before: float = 0.0
+
+
+def adhesive_force_retraction(op: Operator, f, F, d_pre, sigma_c, attach_tol, tol=1e-10,
+                              steps_per_depth=32, max_steps=4096, ftol=1e-6):
+    """Force-controlled retraction of an adhesive contact to a force F <= 0
+    (Sec. 2 last paragraph, Eq. 12; Sec. 3.1, Eq. 19 for the instability).
+
+    Preload: the single adhesive solve at the approach d_pre (overlap, then
+    Eq. 12 rounds).  Retraction: the quasi-static displacement steps of the
+    paper, d_k = d_pre - k (d_pre - min f) / steps_per_depth, each carrying
+    (S, p) from the step before.  As long as the force keeps falling these
+    are the equilibria a force-controlled unloading passes through; the
+    first step whose force is at or below F brackets the target, and the
+    approach in (d_k, d_{k-1}) carrying F is found by regula falsi over
+    single steps from the state at d_{k-1} (to ftol of |F|, or of 1e-3 of
+    the preload force when F is near zero).  If the contact is lost first,
+    the lowest force met is the force-controlled pull-off (the force
+    minimum of the retraction, Eq. 19 for a thin layer) and F is not
+    reached.
+    """
+    f = np.asarray(f, dtype=np.float64)
+    dA = op.dx ** 2
+    dd = (d_pre - float(f.min())) / steps_per_depth
+    st, _, _, _ = adhesive_solve(op, f, d_pre, sigma_c, attach_tol, tol=tol)
+    d, Fc = d_pre, dA * float(st.p.sum())
+    fabs_tol = ftol * max(abs(F), 1e-3 * abs(Fc))
+    steps = [(d, Fc)]
+    best = (Fc, d, st)
+    for _ in range(max_steps):
+        dn = d - dd
+        sn, _, _, _ = adhesive_step(op, f, dn, st, sigma_c, attach_tol, tol=tol)
+        Fn = dA * float(sn.p.sum())
+        steps.append((dn, Fn))
+        if Fn < best[0]:
+            best = (Fn, dn, sn)
+        if Fn <= F:
+            lo, hi, Flo, Fhi = dn, d, Fn, Fc
+            out = (sn, dn, Fn)
+            side = 0
+            for _ in range(200):
+                if abs(out[2] - F) <= fabs_tol or hi - lo <= 1e-13 * dd:
+                    break
+                x = hi - (Fhi - F) * (hi - lo) / (Fhi - Flo)
+                if not (lo < x < hi):
+                    x = 0.5 * (lo + hi)
+                sx, _, _, _ = adhesive_step(op, f, x, st, sigma_c, attach_tol, tol=tol)
+                Fx = dA * float(sx.p.sum())
+                if abs(Fx - F) < abs(out[2] - F):
+                    out = (sx, x, Fx)
+                if Fx < F:
+                    if side == -1:
+                        Fhi = F + 0.5 * (Fhi - F)
+                    lo, Flo, side = x, Fx, -1
+                else:
+                    if side == 1:
+                        Flo = F + 0.5 * (Flo - F)
+                    hi, Fhi, side = x, Fx, 1
+            return RetractionResult(out[0], out[1], out[2], True, steps, st, d)
+        if not sn.S.any():
+            return RetractionResult(best[2], best[1], best[0], False, steps)
+        st, d, Fc = sn, dn, Fn
+    return RetractionResult(best[2], best[1], best[0], False, steps)

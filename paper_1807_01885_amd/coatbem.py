@@ -51,7 +51,7 @@ class cb_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("chunk", ctypes.c_int), ("init", ctypes.c_int),
                 ("attach_tol", ctypes.c_double), ("max_rounds", ctypes.c_int),
-                ("precond", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("preload_d", ctypes.c_double)]
 
 
 class cb_result(ctypes.Structure):
@@ -111,6 +111,9 @@ _SIGS = {
     "cb_solve_batch": (_i, [_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_d),
                             ctypes.POINTER(_i), ctypes.POINTER(_vp), ctypes.POINTER(cb_solve_opts), _i,
                             ctypes.POINTER(cb_result)]),
+    "cb_sweep_batch": (_i, [_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i),
+                            ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(cb_solve_opts), _i,
+                            ctypes.POINTER(_vp)]),
     "cb_net_num_params": (_i, []),
     "cb_net_create": (_i, [ctypes.POINTER(_vp), _i, _i, _i, _vp]),
     "cb_net_destroy": (_i, [_vp]),
@@ -269,9 +272,9 @@ def _arr(plan: Plan, x, name, dtype=None):
     return ctypes.c_void_p(x.data_ptr())
 
 
-def _opts(tol=0.0, max_iter=0, chunk=0, init=0, attach_tol=-1.0, max_rounds=0, precond=-1):
+def _opts(tol=0.0, max_iter=0, chunk=0, init=0, attach_tol=-1.0, max_rounds=0, precond=-1, preload_d=-1e300):
     return cb_solve_opts(float(tol), int(max_iter), int(chunk), int(init),
-                         float(attach_tol), int(max_rounds), int(precond))
+                         float(attach_tol), int(max_rounds), int(precond), float(preload_d))
 
 
 def cb_apply_K(plan: Plan, p, u):
@@ -356,6 +359,25 @@ def cb_solve_batch(plans, fs, targets, modes, ps, workers=0, raise_on_error=True
     if raise_on_error:
         _check(rc)
     return [out[i].as_dict() for i in range(n)]
+
+
+def cb_sweep_batch(plans, fs, d_steps, p_states, mask_states, workers=0, raise_on_error=True, **opts):
+    """len(plans) independent sweeps concurrently; d_steps: one sequence of
+    approaches per problem.  Returns one list of per-step results per problem."""
+    n = len(plans)
+    steps = [(ctypes.c_double * max(len(s), 1))(*[float(x) for x in s]) for s in d_steps]
+    outs = [(cb_result * max(len(s), 1))() for s in d_steps]
+    hp = (_vp * n)(*[pl.handle for pl in plans])
+    hf = (_vp * n)(*[_arr(pl, f, "f", torch.float64).value for pl, f in zip(plans, fs)])
+    hs = (_vp * n)(*[ctypes.cast(s, _vp).value for s in steps])
+    hn = (_i * n)(*[len(s) for s in d_steps])
+    hpp = (_vp * n)(*[_arr(pl, p, "p_state", torch.float64).value for pl, p in zip(plans, p_states)])
+    hm = (_vp * n)(*[_arr(pl, m, "mask_state", torch.uint8).value for pl, m in zip(plans, mask_states)])
+    ho = (_vp * n)(*[ctypes.cast(o, _vp).value for o in outs])
+    rc = _lib.cb_sweep_batch(n, hp, hf, hs, hn, hpp, hm, ctypes.byref(_opts(**opts)), int(workers), ho)
+    if raise_on_error:
+        _check(rc)
+    return [[outs[i][k].as_dict() for k in range(len(d_steps[i]))] for i in range(n)]
 
 
 # ---------------------------------------------------------------------------

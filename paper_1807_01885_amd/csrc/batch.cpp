@@ -69,3 +69,45 @@ extern "C" int cb_solve_batch(int n, const cb_plan* plans, const double* const* 
     if (rc[i] != CB_OK) return cb_fail(rc[i], "problem " + std::to_string(i) + " of the batch failed");
   return CB_OK;
 }
+
+// Quasi-static sweeps of independent problems, concurrently (one cb_sweep
+// per problem on its plan's stream), the longest (N^2 x steps) first.
+extern "C" int cb_sweep_batch(int n, const cb_plan* plans, const double* const* f, const double* const* d_steps,
+                              const int* nsteps, double* const* p_state, unsigned char* const* mask_state,
+                              const cb_solve_opts* opts, int workers, cb_result* const* out) {
+  if (n < 0 || (n > 0 && (!plans || !f || !d_steps || !nsteps || !p_state || !mask_state || !out)))
+    return cb_fail(CB_E_INVALID, "null argument or negative count");
+  if (n == 0) return CB_OK;
+  std::set<const void*> seen;
+  for (int i = 0; i < n; i++) {
+    if (!plans[i] || !f[i] || !p_state[i] || !mask_state[i] || nsteps[i] < 0 || (nsteps[i] > 0 && (!d_steps[i] || !out[i])))
+      return cb_fail(CB_E_INVALID, "null plan, array or result in the batch, or a negative step count");
+    if (!seen.insert(plans[i]).second) return cb_fail(CB_E_INVALID, "a plan appears twice in the batch");
+  }
+  int device = 0;
+  CB_HIP(hipGetDevice(&device));
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (long long)plans[a]->N * plans[a]->N * nsteps[a] > (long long)plans[b]->N * plans[b]->N * nsteps[b];
+  });
+  const int nw = std::max(1, std::min(workers > 0 ? workers : 16, n));
+  std::atomic<int> next{0};
+  std::vector<int> rc(n, CB_OK);
+  auto work = [&]() {
+    (void)hipSetDevice(device);
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= n) break;
+      const int i = order[k];
+      rc[i] = cb_sweep(plans[i], f[i], d_steps[i], nsteps[i], p_state[i], mask_state[i], opts, out[i]);
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nw; w++) pool.emplace_back(work);
+  work();
+  for (auto& t : pool) t.join();
+  for (int i = 0; i < n; i++)
+    if (rc[i] != CB_OK) return cb_fail(rc[i], "sweep " + std::to_string(i) + " of the batch failed");
+  return CB_OK;
+}

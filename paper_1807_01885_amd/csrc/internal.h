@@ -134,6 +134,10 @@ struct cb_plan_s {
   unsigned char* d_mask = nullptr;   // scratch contact set (N*N)
   unsigned char* d_mask2 = nullptr;  // second contact-set buffer (N*N)
   unsigned char* d_det = nullptr;    // detached-in-this-step flags (N*N)
+  // adhesive plans: two saved states (p, contact set) of the force-controlled
+  // retraction (the step before the target, the best step)
+  double* d_save_p[2] = {nullptr, nullptr};
+  unsigned char* d_save_S[2] = {nullptr, nullptr};
   double* d_part = nullptr;          // partial-sum regions + scratch
   SolverState* d_state = nullptr;
   SolverState* h_state = nullptr;    // pinned host mirror (2 slots)

@@ -116,10 +116,20 @@ double brillouin_integral(double dx, double h, double E1s, const Coef& c) {
     return 16.0 / E1s * c0 * base;
   }
   const double TCUT = 40.0;
+  // Phi(T) over panels graded towards t = 0 (widths doubling from 1e-6 up to
+  // 0.25, then 0.25): on coatings much stiffer than the substrate C(t) has a
+  // narrow peak of height about E1*/E2* at t = 0, which uniform panels
+  // resolve only to about 1e-7 of the DC value
   auto phi = [&](double T) {
     const double top = T < TCUT ? T : TCUT;
-    const int panels = (int)std::ceil(top / 0.25) + 1;
-    return integrate([&](double t) { return shape_m1(t, c); }, 0.0, top, panels, x, w);
+    double s = 0.0, a = 0.0, b = 1e-6;
+    while (a < top) {
+      const double hi = b < top ? b : top;
+      s += integrate([&](double t) { return shape_m1(t, c); }, a, hi, 1, x, w);
+      a = hi;
+      b = a < 0.25 ? 2.0 * a : a + 0.25;
+    }
+    return s;
   };
   const double cth = M_PI * h / dx;
   double outer;
@@ -298,7 +308,8 @@ static void free_plan_memory(cb_plan_s* P) {
     if (e) (void)hipEventDestroy(e);
   if (P->istream) (void)hipStreamDestroy(P->istream);
   void* ptrs[] = {P->d_table, P->d_table64, P->d_ptable, P->d_pinv, P->d_y, P->d_S, P->d_u, P->d_t, P->d_r, P->d_g,
-                  P->d_pold, P->d_mask, P->d_mask2, P->d_det, P->d_part, P->d_state};
+                  P->d_pold, P->d_mask, P->d_mask2, P->d_det, P->d_part, P->d_state,
+                  P->d_save_p[0], P->d_save_p[1], P->d_save_S[0], P->d_save_S[1]};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   if (P->h_state) (void)hipHostFree(P->h_state);
@@ -508,6 +519,11 @@ static int plan_create_impl(cb_plan* out, int N, double L, double h, double E1, 
   alloc((void**)&P->d_mask, n2);
   alloc((void**)&P->d_mask2, n2);
   alloc((void**)&P->d_det, n2);
+  if (dgamma > 0.0)
+    for (int q = 0; q < 2; q++) {
+      alloc((void**)&P->d_save_p[q], n2 * 8);
+      alloc((void**)&P->d_save_S[q], n2);
+    }
   // partial-sum regions | 32 scratch doubles
   const size_t part_doubles = (size_t)SCRATCH_OFF + 32;
   alloc((void**)&P->d_part, part_doubles * sizeof(double));

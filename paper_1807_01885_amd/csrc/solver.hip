@@ -974,7 +974,7 @@ static int run_chunks(cb_plan_s* P, int kind, int kind1, const void* a, const vo
 }
 
 struct Opts {
-  double tol, atol;
+  double tol, atol, preload_d;
   int max_iter, chunk, init, max_rounds, precond;
 };
 
@@ -982,6 +982,7 @@ static Opts fill_opts(const cb_plan_s* P, const cb_solve_opts* o) {
   cb_solve_opts d{};
   d.precond = -1;
   d.attach_tol = -1.0;
+  d.preload_d = -HUGE_VAL;
   if (o) d = *o;
   Opts r;
   r.tol = d.tol > 0 ? d.tol : (P->precision == CB_FP64 ? 1e-10 : 1e-8);
@@ -993,6 +994,7 @@ static Opts fill_opts(const cb_plan_s* P, const cb_solve_opts* o) {
   r.atol = d.attach_tol >= 0 ? d.attach_tol : (P->precision == CB_FP64 ? 1e-12 : 1e-9) * P->L;
   r.max_rounds = d.max_rounds > 0 ? d.max_rounds : 10000;
   r.precond = d.precond;
+  r.preload_d = d.preload_d;
   return r;
 }
 
@@ -1288,7 +1290,6 @@ template <typename TD>
 static int adhesive_force(cb_plan_s* P, const double* f, double F, double* p, unsigned char* mask_io,
                           const cb_solve_opts* o, cb_result* res) {
   const auto t0 = std::chrono::steady_clock::now();
-  if (!(F > 0.0)) return cb_fail(CB_E_UNSUPPORTED, "force control of adhesive plans needs F > 0");
   int iters = 0, rounds = 0;
   cb_result r{};
   if (int rc = pk_solve<TD>(P, f, F, true, p, nullptr, o, &r)) return rc;
@@ -1367,6 +1368,136 @@ static int adhesive_force(cb_plan_s* P, const double* f, double F, double* p, un
   return CB_OK;
 }
 
+// Adhesive force control with F <= 0: the pull-off under force control
+// (Sec. 3.1, Eq. 19).  Preload by the single adhesive solve at d_pre, then
+// the quasi-static displacement steps of the paper's retraction, each
+// carrying the state; in the first step at or below F, regula falsi over
+// single steps from the state of the step before.  Contact lost first:
+// F lies below the pull-off force, the step of the lowest force is
+// returned with CB_E_NOCONV.
+template <typename TD>
+static int adhesive_retract(cb_plan_s* P, const double* f, double F, double* p, unsigned char* mask_io,
+                            const cb_solve_opts* o, cb_result* res) {
+  const auto t0 = std::chrono::steady_clock::now();
+  Ctx c = make_ctx(P);
+  Opts op = fill_opts(P, o);
+  *res = cb_result{};
+  if (op.precond < -1 || op.precond > 2) return cb_fail(CB_E_INVALID, "precond must be -1, 0, 1 or 2");
+  if (!P->d_save_p[0]) return cb_fail(CB_E_STATE, "adhesive plan without retraction buffers");
+  if (int rc = enter(P)) return rc;
+  hipLaunchKernelGGL(k_minmax, dim3(c.nb), dim3(RT), 0, c.st, f, nullptr, P->d_part, c.n);
+  hipLaunchKernelGGL(k_fold_misc<4>, dim3(1), dim3(RT), 0, c.st, P->d_part, c.nb, 15);
+  double mm[4];
+  if (int rc = read_scratch(c, mm, 4)) return rc;
+  if (mm[2] > 0.0) return cb_fail(CB_E_NONFINITE, "profile f contains NaN/Inf");
+  const double fmin = -mm[0];
+  int iters = 0, rounds = 0;
+  double d_pre = op.preload_d;
+  if (!(d_pre > fmin)) {
+    // the approach at which the non-adhesive solve carries the preload force
+    cb_solve_opts o2{};
+    if (o) o2 = *o;
+    o2.init = 0;
+    cb_result r{};
+    const double Fpre = std::max(4.0 * std::fabs(F), M_PI * P->dgamma * P->L / 2.0);
+    if (int rc = pk_solve<TD>(P, f, Fpre, true, p, nullptr, &o2, &r)) return rc;
+    iters += r.iters;
+    d_pre = r.d;
+  }
+  const size_t n8 = (size_t)c.n * 8;
+  double* sp[2] = {P->d_save_p[0], P->d_save_p[1]};   // 0: step before, 1: best
+  unsigned char* sS[2] = {P->d_save_S[0], P->d_save_S[1]};
+  unsigned char* S = P->d_mask;
+  unsigned char* Salt = P->d_mask2;
+  auto save = [&](int q) -> int {
+    CB_HIP(hipMemcpyAsync(sp[q], p, n8, hipMemcpyDeviceToDevice, c.st));
+    CB_HIP(hipMemcpyAsync(sS[q], S, c.n, hipMemcpyDeviceToDevice, c.st));
+    return CB_OK;
+  };
+  auto restore = [&](int q) -> int {
+    CB_HIP(hipMemcpyAsync(p, sp[q], n8, hipMemcpyDeviceToDevice, c.st));
+    CB_HIP(hipMemcpyAsync(S, sS[q], c.n, hipMemcpyDeviceToDevice, c.st));
+    return CB_OK;
+  };
+  auto step = [&](double d, bool from_overlap, cb_result* q) -> int {
+    if (from_overlap)
+      hipLaunchKernelGGL(k_mask_overlap, dim3(c.nb), dim3(RT), 0, c.st, f, d, S, P->d_det, p, c.n);
+    const int rc = adhesive_step<TD>(c, f, d, p, S, Salt, !from_overlap, op, q);
+    iters += q->iters;
+    rounds += q->rounds;
+    return rc;
+  };
+  cb_result q{}, best{};
+  if (int rc = step(d_pre, true, &q)) return cb_fail(rc, "adhesive preload did not converge");
+  best = q;
+  if (int rc = save(0)) return rc;
+  if (int rc = save(1)) return rc;
+  const double dd = (d_pre - fmin) / 32.0;
+  // force tolerance of the refinement: 1e-6 of |F|, or of 1e-3 of the
+  // preload force when F is near zero
+  const double ftol = 1e-6 * std::max(std::fabs(F), 1e-3 * std::fabs(q.F));
+  double d = d_pre, Fc = q.F;
+  int status = CB_E_NOCONV;
+  bool found = false;
+  for (int k = 0; k < 4096 && !found; k++) {
+    const double dn = d - dd;
+    if (int rc = step(dn, false, &q)) return cb_fail(rc, "adhesive retraction step did not converge");
+    if (q.F < best.F) {
+      best = q;
+      if (int rc = save(1)) return rc;
+    }
+    if (q.F <= F) {
+      // refine inside (dn, d) from the state of the step before; the best
+      // match so far is kept in slot 1
+      double lo = dn, hi = d, Flo = q.F, Fhi = Fc;
+      cb_result match = q;
+      if (int rc = save(1)) return rc;
+      int side = 0;
+      for (int it = 0; it < 200; it++) {
+        if (std::fabs(match.F - F) <= ftol || hi - lo <= 1e-13 * dd) break;
+        double x = hi - (Fhi - F) * (hi - lo) / (Fhi - Flo);
+        if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+        if (int rc = restore(0)) return rc;
+        if (int rc = step(x, false, &q)) return cb_fail(rc, "adhesive retraction step did not converge");
+        if (std::fabs(q.F - F) < std::fabs(match.F - F)) {
+          match = q;
+          if (int rc = save(1)) return rc;
+        }
+        if (q.F < F) {
+          if (side == -1) Fhi = F + 0.5 * (Fhi - F);
+          lo = x;
+          Flo = q.F;
+          side = -1;
+        } else {
+          if (side == 1) Flo = F + 0.5 * (Flo - F);
+          hi = x;
+          Fhi = q.F;
+          side = 1;
+        }
+      }
+      best = match;
+      status = CB_OK;
+      found = true;
+      break;
+    }
+    if (!(q.area > 0.0)) break;  // contact lost: F is below the pull-off force
+    if (int rc = save(0)) return rc;
+    d = dn;
+    Fc = q.F;
+  }
+  if (int rc = restore(1)) return rc;
+  if (mask_io) CB_HIP(hipMemcpyAsync(mask_io, S, c.n, hipMemcpyDeviceToDevice, c.st));
+  CB_HIP(hipStreamSynchronize(c.st));
+  *res = best;
+  res->status = status;
+  res->iters = iters;
+  res->rounds = rounds;
+  res->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (status != CB_OK)
+    return cb_fail(status, "pull-off before the force was reached: the lowest force of the retraction is above F");
+  return CB_OK;
+}
+
 template <typename TD>
 static int sweep_impl(cb_plan_s* P, const double* f, const double* dsteps, int nsteps, double* p,
                       unsigned char* mask, const cb_solve_opts* o, cb_result* out) {
@@ -1414,11 +1545,16 @@ extern "C" int cb_solve_force(cb_plan P, const double* f, double F, double* p_io
   if (!P || !f || !p_io || !res) return cb_fail(CB_E_INVALID, "null argument");
   if (!aligned16(f) || !aligned16(p_io) || (mask_io && !aligned16(mask_io)))
     return cb_fail(CB_E_INVALID, "f, p and mask must be 16-byte aligned");
-  if (!std::isfinite(F) || F < 0.0) return cb_fail(CB_E_INVALID, "F must be finite and >= 0");
+  if (!std::isfinite(F)) return cb_fail(CB_E_INVALID, "F must be finite");
   if (P->dgamma > 0.0) {
+    if (F <= 0.0) {
+      if (P->precision == CB_FP64) return adhesive_retract<double>(P, f, F, p_io, mask_io, o, res);
+      return adhesive_retract<float>(P, f, F, p_io, mask_io, o, res);
+    }
     if (P->precision == CB_FP64) return adhesive_force<double>(P, f, F, p_io, mask_io, o, res);
     return adhesive_force<float>(P, f, F, p_io, mask_io, o, res);
   }
+  if (F < 0.0) return cb_fail(CB_E_INVALID, "F must be >= 0 on a non-adhesive plan");
   if (P->precision == CB_FP64) return pk_solve<double>(P, f, F, true, p_io, mask_io, o, res);
   return pk_solve<float>(P, f, F, true, p_io, mask_io, o, res);
 }

@@ -70,6 +70,21 @@ def test_host_table_matches_oracle(lib, N, L, m):
     assert k00 == pytest.approx(self_influence(Operator(N, L, m)), rel=1e-12)
 
 
+@pytest.mark.parametrize("idx", [1, 4, 5, 65, 87])
+def test_host_table_dc_stiff_coatings(lib, idx):
+    """The Brillouin-zone DC value on the recipe's stiffest coatings (E1/E2 up
+    to 88, h/L down to 1e-3), where C(kh) has a narrow peak of height about
+    E1*/E2* at k = 0: library quadrature against the oracle's adaptive one."""
+    from paper_1807_01885_amd import inputs
+    from oracle.transfer import dc_bz
+    c = (inputs.batch_c4(n=64, seed=4) + inputs.headline_set())[idx]
+    N = min(c.N, 256)
+    m = Material(c.h, c.E1, c.nu1, c.E2, c.nu2)
+    rc, out, _ = _table(lib, N, c.L, m)
+    assert rc == 0
+    assert out[0, 0] == pytest.approx(dc_bz(N, c.L, m), rel=1e-12)
+
+
 def test_host_table_dc_zero(lib):
     m = Material(0.1, 10.0, 0.3, 1.0, 0.3)
     rc, out, _ = _table(lib, 32, 1.0, m, dc_mode=1)

@@ -51,3 +51,111 @@ def test_batch_rejects_duplicate_plans(lib):
     with pytest.raises(lib.CoatbemError) as e:
         lib.cb_solve_batch([plan, plan], [f, f], [1e-3, 1e-3], [0, 0], [p, p.clone()])
     assert e.value.status == lib.CB_E_INVALID
+
+
+def _conditions(op, p, f, d, S, tol):
+    g = op.apply(p) + f - d
+    scale = np.linalg.norm((d - f)[S])
+    on = np.linalg.norm(g[S]) / scale
+    pen = max(0.0, -g[~S].min()) / (scale / np.sqrt(S.sum())) if (~S).any() else 0.0
+    return on, pen, g
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_recipe_against_oracle(lib, prec):
+    """The first 24 problems of the batched recipe (seed 4: N from 128 to
+    1024, four indenter families, half adhesive) in one cb_solve_batch.
+    Non-adhesive members (unique solution): the contact conditions under
+    the FP64 oracle's operator within 10 x the residual target, and the
+    force.  Adhesive members up to N = 256: the oracle's adhesive_solve
+    (geometric overlap, then the Eq. 12 rounds): FP64 identical contact
+    set and pressure 1e-8; FP32 set agreement >= 0.999 and pressure 1e-4.
+    Larger adhesive members: the conditions the Eq. 12 procedure leaves
+    (gap zero on the set, no pressure off it, no boundary tension beyond
+    sigma_c, no penetration past the attach tolerance)."""
+    from oracle.solvers import adhesive_solve, contact_boundary
+    from oracle.transfer import critical_stress
+    print(f"batched recipe {prec}", flush=True)
+    cases = inputs.batch_c4(n=24, seed=4)
+    tol = 1e-10 if prec == "fp64" else 1e-8
+    atol_rel = 1e-12 if prec == "fp64" else 1e-9
+    plans = [lib.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, c.dgamma, prec) for c in cases]
+    fs = [torch.tensor(c.f, device="cuda") for c in cases]
+    ps = [torch.zeros_like(f) for f in fs]
+    modes = [1 if c.mode == "force" else 0 for c in cases]
+    res = lib.cb_solve_batch(plans, fs, [c.target for c in cases], modes, ps, tol=tol)
+    torch.cuda.synchronize()
+    for i, c in enumerate(cases):
+        mat = Material(c.h, c.E1, c.nu1, c.E2, c.nu2)
+        op = Operator(c.N, c.L, mat)
+        p = ps[i].cpu().numpy()
+        assert res[i]["status"] == 0
+        if c.dgamma == 0.0:
+            S = p > 0
+            on, pen, _ = _conditions(op, p, c.f, res[i]["d"], S, tol)
+            eF = abs(op.dx ** 2 * p.sum() - c.target) / c.target
+            print(f"  {i:2d} N={c.N} {c.shape:10s} force: gap on S {on:.1e} pen {pen:.1e} eF {eF:.1e}")
+            assert p.min() >= 0.0 and on <= 10 * tol and pen <= 10 * tol and eF <= 1e-10
+            continue
+        sc = critical_stress(mat, c.dgamma, c.L / c.N)
+        S = p != 0.0
+        if c.N <= 256:
+            st, rounds, _, conv = adhesive_solve(op, c.f, c.target, sc, atol_rel * c.L, tol=1e-10)
+            assert conv
+            e_p = np.linalg.norm(p - st.p) / np.linalg.norm(st.p)
+            agr = 1.0 - (S ^ st.S).sum() / max((S | st.S).sum(), 1)
+            print(f"  {i:2d} N={c.N} {c.shape:10s} adhesive: rounds {res[i]['rounds']} (oracle {rounds}) "
+                  f"e_p {e_p:.1e} agree {agr:.5f}")
+            if prec == "fp64":
+                assert np.array_equal(S, st.S) and e_p < 1e-8
+            else:
+                assert agr >= 0.999 and e_p < 1e-4
+        else:
+            on, pen, g = _conditions(op, p, c.f, c.target, S, tol)
+            bnd = contact_boundary(S)
+            low = (-p[bnd]).max() / sc if bnd.any() else 0.0
+            pen_abs = max(0.0, -g[~S].min()) if (~S).any() else 0.0
+            print(f"  {i:2d} N={c.N} {c.shape:10s} adhesive: gap on S {on:.1e} boundary tension/sigma_c {low:.3f} "
+                  f"penetration {pen_abs:.1e}")
+            assert on <= 10 * tol and low <= 1.0 + 1e-9 and pen_abs <= atol_rel * c.L * (1 + 1e-6) + 1e-3 * tol * c.L
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sweep_batch_matches_individual_and_oracle(lib, prec):
+    """Three adhesive sweeps of different grids and coatings in one
+    cb_sweep_batch: each equals its own cb_sweep bit for bit, and the N = 64
+    one matches the oracle's sweep step by step (FP64 identical areas, F to
+    1e-8 of its span; FP32 1% + 2 cells, 1e-3)."""
+    from oracle.solvers import sweep
+    from oracle.transfer import critical_stress
+    print(f"sweep batch {prec}", flush=True)
+    tol = 1e-10 if prec == "fp64" else 1e-8
+    probs = [(64, Material(0.05, 1.0, 0.3, 5.0, 0.3), 3e-4), (128, Material(0.1, 10.0, 0.3, 1.0, 0.3), 1e-3),
+             (256, Material(0.02, 0.5, 0.25, 1.0, 0.35), 2e-4)]
+    L, R = 1.0, 1.0
+    steps = [list(np.linspace(0, 0.01, 6)[1:]) + list(np.linspace(0.01, -0.01, 9)[1:]),
+             list(np.linspace(0, 0.015, 8)[1:]) + list(np.linspace(0.015, -0.005, 11)[1:]),
+             list(np.linspace(0, 0.008, 5)[1:]) + list(np.linspace(0.008, -0.004, 7)[1:])]
+    plans, fs, ps, ms = [], [], [], []
+    for (n, m, dg) in probs:
+        plans.append(lib.cb_plan_create(n, L, m.h, m.E1, m.nu1, m.E2, m.nu2, dg, prec))
+        fs.append(torch.tensor(inputs.paraboloid(n, L, R), device="cuda"))
+        ps.append(torch.zeros(n, n, dtype=torch.float64, device="cuda"))
+        ms.append(torch.zeros(n, n, dtype=torch.uint8, device="cuda"))
+    res = lib.cb_sweep_batch(plans, fs, steps, ps, ms, tol=tol)
+    for i, (n, m, dg) in enumerate(probs):
+        p1 = torch.zeros_like(ps[i])
+        m1 = torch.zeros_like(ms[i])
+        r1 = lib.cb_sweep(plans[i], fs[i], steps[i], p1, m1, tol=tol)
+        assert torch.equal(p1, ps[i]) and torch.equal(m1, ms[i])
+        assert [x["F"] for x in r1] == [x["F"] for x in res[i]]
+    n, m, dg = probs[0]
+    op = Operator(n, L, m)
+    out, _ = sweep(op, inputs.paraboloid(n, L, R), steps[0], critical_stress(m, dg, L / n), 1e-12 * L, dg, tol=1e-10)
+    span = max(abs(o["F"]) for o in out)
+    for o, r in zip(out, res[0]):
+        if prec == "fp64":
+            assert r["area"] == pytest.approx(o["area"], abs=1e-15) and abs(r["F"] - o["F"]) <= 1e-8 * span
+        else:
+            assert abs(r["area"] - o["area"]) <= 0.01 * o["area"] + 2 * (L / n) ** 2
+            assert abs(r["F"] - o["F"]) <= 1e-3 * span

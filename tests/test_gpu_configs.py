@@ -179,3 +179,43 @@ def test_n4096_force_solve_contact_conditions(lib):
     assert res["status"] == 0 and pn.min() >= 0.0
     assert abs(res["F"] - F) <= 1e-6 * F
     assert rel < 1e-6 and pen < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c2_sweep_against_oracle_golden(lib, prec):
+    """Config 2, sweep h = 0.1, E1/E2 = 10 (N = 512, 200 steps), step by step
+    against the FP64 oracle's sweep stored in tests/golden/ (written by
+    tests/golden/make_c2_sweep.py, which calls only the oracle): FP64
+    identical contact set (hash) and area at every step, F and U_el within
+    1e-8 of their spans; FP32 area within 1% + 2 cells, F and U_el within
+    1e-3 of their spans."""
+    import hashlib
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_sweep_h0.1_E10.json")))
+    c = inputs.adhesive_sweep_c2()[3]
+    steps = c.meta["d_steps"]
+    assert len(steps) == len(gold["steps"]) and c.N == gold["N"] and c.dgamma == gold["dgamma"]
+    print(f"C2 sweep against the oracle's golden, {prec}", flush=True)
+    plan = lib.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, c.dgamma, prec)
+    ft = torch.tensor(c.f, dtype=torch.float64, device="cuda")
+    p = torch.zeros_like(ft)
+    mask = torch.zeros(c.N, c.N, dtype=torch.uint8, device="cuda")
+    Fspan = max(abs(g["F"]) for g in gold["steps"])
+    Uspan = max(abs(g["U_el"]) for g in gold["steps"])
+    cell = (c.L / c.N) ** 2
+    worst = [0.0, 0.0, 0.0]
+    for k, (d, g) in enumerate(zip(steps, gold["steps"])):
+        assert d == pytest.approx(g["d"], rel=0, abs=1e-18)
+        r = lib.cb_sweep(plan, ft, [d], p, mask, tol=TOL[prec])[0]
+        eF = abs(r["F"] - g["F"]) / Fspan
+        eU = abs(r["U_el"] - g["U_el"]) / Uspan
+        eA = abs(r["area"] - g["area"])
+        worst = [max(worst[0], eF), max(worst[1], eU), max(worst[2], eA / cell)]
+        if prec == "fp64":
+            h = hashlib.sha256(np.packbits(mask.cpu().numpy().astype(bool)).tobytes()).hexdigest()[:16]
+            assert h == g["mask"], f"step {k}: contact set differs from the oracle's"
+            assert r["area"] == g["area"] and eF <= 1e-8 and eU <= 1e-8, (k, eF, eU)
+        else:
+            assert eA <= 0.01 * g["area"] + 2 * cell and eF <= 1e-3 and eU <= 1e-3, (k, eA, eF, eU)
+    print(f"  worst: F {worst[0]:.1e} of span, U_el {worst[1]:.1e} of span, area {worst[2]:.1f} cells", flush=True)

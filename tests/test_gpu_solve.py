@@ -145,9 +145,10 @@ def test_adhesive_force_control(lib, prec):
     print(f"  oracle at d found: F {F2:.9e} e_p {e_p:.2e}")
     assert abs(F2 - F) <= (1e-6 if prec == "fp64" else 1e-4) * F
     assert e_p < (1e-8 if prec == "fp64" else 1e-4)
-    with pytest.raises(lib.CoatbemError) as e:
-        lib.cb_solve_force(plan, ft, 0.0, p, mask, tol=tol)
-    assert e.value.status == lib.CB_E_UNSUPPORTED
+    # F <= 0 is the force-controlled retraction (tests/test_gpu_pulloff.py);
+    # F = 0 on this grid lies on its stable branch and is reached
+    r0 = lib.cb_solve_force(plan, ft, 0.0, p, mask, tol=tol)
+    assert r0["status"] == 0 and abs(r0["F"]) <= 1e-4 * F and r0["area"] > 0
 
 
 def test_adhesive_force_control_jkr(lib):

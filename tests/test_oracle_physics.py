@@ -309,3 +309,35 @@ def test_critical_separation_eq13_intermediate_layer():
     first_loss = [o for o in out[3:] if o["area"] < 0.999 * A0][0]
     assert -first_loss["d"] / dc13 == pytest.approx(1.0, abs=0.06)
     assert out[-1]["area"] == 0.0
+
+
+def test_force_controlled_pulloff_homogeneous_jkr():
+    """Force-controlled retraction (Sec. 3.1: the instability under force
+    control) on the homogeneous half-space, a_min/D ~ 13: a target of 0.8
+    of the JKR pull-off force -3/2 pi R dgamma is reached exactly, on the
+    stable branch (contact radius within 5% of JKR's larger root, measured
+    1%), with the Eq. 12 conditions satisfied (no boundary tension beyond
+    sigma_c, no penetration outside the contact); a target of 1.5 times it
+    is not reached, and the lowest force of the retraction is the JKR
+    pull-off force within 10% (measured 4.5%)."""
+    import scipy.optimize
+    from oracle.solvers import adhesive_force_retraction, contact_boundary
+    N, L, R = 64, 1.0, 1.0
+    mat = Material(0.0, 0.91, 0.3, 0.91, 0.3)      # E* = 1
+    op = Operator(N, L, mat)
+    dg = 2.26e-3
+    sc = critical_stress(mat, dg, L / N)
+    f = inputs.paraboloid(N, L, R)
+    Fj = -1.5 * math.pi * R * dg
+    d_pre = solve_pk(op, f, 4 * abs(Fj), mode="force", tol=1e-10).d
+    r = adhesive_force_retraction(op, f, 0.8 * Fj, d_pre, sc, 1e-12 * L, tol=1e-10)
+    assert r.reached and r.F == pytest.approx(0.8 * Fj, rel=1e-6)
+    amin = (9 * math.pi * dg * R * R / (8 * mat.E1s)) ** (1 / 3)
+    aj = scipy.optimize.brentq(lambda x: an.jkr(x, R, mat.E1s, dg)[0] - 0.8 * Fj, amin, 0.5)
+    assert math.sqrt(r.state.S.sum() * op.dx ** 2 / math.pi) == pytest.approx(aj, rel=5e-2)
+    g = op.apply(r.state.p) + f - r.d
+    assert r.state.p[contact_boundary(r.state.S)].min() >= -sc
+    assert g[~r.state.S].min() >= -1e-12 * L
+    r2 = adhesive_force_retraction(op, f, 1.5 * Fj, d_pre, sc, 1e-12 * L, tol=1e-10)
+    assert not r2.reached
+    assert r2.F / Fj == pytest.approx(1.0, abs=0.1)
