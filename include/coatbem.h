@@ -264,6 +264,20 @@ int cb_plan_set_stream(cb_plan plan, void* stream);
 int cb_apply_K(cb_plan plan, const void* p, void* u);
 
 /*
+ * cb_apply_K_batch -- u_i = K_i p_i for n problems (Eq. 1 as Eq. 11 on the
+ *   2N-padded grid, as cb_apply_K), packed into one launch per transform
+ *   stage (up to 32 problems per launch; more are launched in groups): for
+ *   small grids one convolution is set by launch latency, not by its
+ *   bytes.  plans[i]: distinct padded plans sharing N, precision, launch
+ *   shape and device (materials may differ: each problem multiplies by its
+ *   own transfer table and uses its own plan's intermediate).  p[i], u[i]:
+ *   device N*N arrays of the plan type, u[i] not aliasing p[i].  Enqueued
+ *   on plans[0]'s stream (asynchronous); the caller orders the other plans'
+ *   work against it.
+ */
+int cb_apply_K_batch(int n, const cb_plan* plans, const void* const* p, void* const* u);
+
+/*
  * cb_apply_K_noalloc -- cb_apply_K for callers that cannot allocate device
  *   memory: code under HIP graph capture, tight serving loops, harnesses
  *   that forbid hipMalloc.  No plan: the caller passes the transfer table.

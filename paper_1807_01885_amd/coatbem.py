@@ -100,6 +100,7 @@ _SIGS = {
     "cb_transfer_table": (_i, [_i, _d, _d, _d, _d, _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "cb_apply_K": (_i, [_vp, _vp, _vp]),
     "cb_apply_K_stages": (_i, [_vp, _vp, _vp, _i]),
+    "cb_apply_K_batch": (_i, [_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
     "cb_apply_K_noalloc": (_i, [_i, _i, _vp, _vp, _vp, _vp]),
     "cb_apply_precond": (_i, [_vp, _i, _vp, _vp]),
     "cb_solve_indent": (_i, [_vp, _vp, _d, _vp, _vp, ctypes.POINTER(cb_solve_opts),
@@ -295,6 +296,16 @@ def cb_apply_K_noalloc(N, precision, table, p, u, stream=None):
                                    ctypes.c_void_p(table.data_ptr()), ctypes.c_void_p(p.data_ptr()),
                                    ctypes.c_void_p(u.data_ptr()), _stream_ptr(stream)))
     return u
+
+
+def cb_apply_K_batch(plans, ps, us):
+    """u_i = K_i p_i for several plans of one size and precision in one launch per stage."""
+    n = len(plans)
+    hp = (_vp * n)(*[pl.handle for pl in plans])
+    hx = (_vp * n)(*[_arr(pl, p, "p").value for pl, p in zip(plans, ps)])
+    hy = (_vp * n)(*[_arr(pl, u, "u").value for pl, u in zip(plans, us)])
+    _check(_lib.cb_apply_K_batch(n, hp, hx, hy))
+    return us
 
 
 def cb_apply_precond(plan: Plan, which, x, y):

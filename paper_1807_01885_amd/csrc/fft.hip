@@ -55,10 +55,10 @@ constexpr int PS = 4;  // LDS padding shift
 // K1: forward row transform
 // ---------------------------------------------------------------------------
 // PRO: the input EpiArgs `pro` mode PRO forms (0: p as given).
+// `bid`: the block's index within its problem.
 template <typename T, int LOG2N, bool PAD, int RB, int NT1, int G, int PRO = 0>
-__global__ void __launch_bounds__(G * RB * NT1)
-k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restrict__ tw_g,
-           const int* __restrict__ skip, EpiArgs ea) {
+__device__ __forceinline__ void rows_fwd_body(int bid, const T* __restrict__ p, cx<T>* __restrict__ S,
+                                              const int* __restrict__ skip, const EpiArgs& ea) {
   if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
   // real transform length M, packed complex line L = M / 2
@@ -72,7 +72,7 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
 
   const int tid = threadIdx.x;
   const int lrow = tid / NT1, t = tid % NT1;
-  const int row0 = blockIdx.x * ROWS;
+  const int row0 = bid * ROWS;
   C* line = buf + lrow * LP;
 
   // first pass (Ls = 1): packed inputs z[n], n < N/2, from global (with
@@ -166,7 +166,7 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
   // X[k] = (Z[k] + conj Z[L-k])/2 - i/2 W^k (Z[k] - conj Z[L-k]),
   // W = exp(-2 pi i / M), k in [0, L]; items in tile order (k major, rr minor)
   constexpr int ITEMS = G * NC * RB;
-  C* out = S + (size_t)blockIdx.x * ITEMS;
+  C* out = S + (size_t)bid * ITEMS;
 #pragma unroll
   for (int it = 0; it < (ITEMS + NTH - 1) / NTH; it++) {
     const int q = tid + it * NTH;
@@ -194,13 +194,28 @@ k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const cx<T>* __restri
   }
 }
 
+template <typename T, int LOG2N, bool PAD, int RB, int NT1, int G, int PRO = 0>
+__global__ void __launch_bounds__(G * RB * NT1)
+k_rows_fwd(const T* __restrict__ p, cx<T>* __restrict__ S, const int* __restrict__ skip, EpiArgs ea) {
+  rows_fwd_body<T, LOG2N, PAD, RB, NT1, G, PRO>(blockIdx.x, p, S, skip, ea);
+}
+
+// Several padded problems of one size in one launch: blocks
+// [q nb, (q + 1) nb) transform problem q.
+template <typename T, int LOG2N, int RB, int NT1, int G>
+__global__ void __launch_bounds__(G * RB * NT1) k_rows_fwd_batch(ApplyBatch ba) {
+  const int q = blockIdx.x / ba.nb;
+  rows_fwd_body<T, LOG2N, true, RB, NT1, G, 0>(blockIdx.x - q * ba.nb, static_cast<const T*>(ba.p[q]),
+                                                static_cast<cx<T>*>(ba.S[q]), nullptr, EpiArgs{});
+}
+
 // ---------------------------------------------------------------------------
 // K2: column transform, transfer multiply, inverse column transform
 // ---------------------------------------------------------------------------
+// `tile`: the block's column tile within its problem.
 template <typename T, int LOG2N, bool PAD, int RB, int NT2, int CB>
-__global__ void __launch_bounds__(CB * NT2)
-k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict__ tw_g,
-       const int* __restrict__ skip) {
+__device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const T* __restrict__ Tq,
+                                          const int* __restrict__ skip) {
   if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
   // NC half-spectrum columns; column 0 carries the DC and Nyquist columns
@@ -217,7 +232,6 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
   const int tid = threadIdx.x;
   const TW tw{tws, tws + TW::NLO};
   const int lc = tid / NT2, t = tid % NT2;
-  const int tile = xcd_block(blockIdx.x, NBLK);
   const int kx = tile * CB + lc;
   const bool active = kx < NW;
   C* line = buf + lc * LP;
@@ -348,14 +362,36 @@ k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const cx<T>* __restrict_
   }
 }
 
+// column tiles of one problem (the DC and Nyquist columns packed)
+template <int LOG2N, bool PAD, int CB>
+__host__ __device__ constexpr int col_tiles() {
+  return (((PAD ? 2 : 1) << LOG2N) / 2 + CB - 1) / CB;
+}
+
+template <typename T, int LOG2N, bool PAD, int RB, int NT2, int CB>
+__global__ void __launch_bounds__(CB * NT2)
+k_cols(cx<T>* __restrict__ S, const T* __restrict__ Tq, const int* __restrict__ skip) {
+  cols_body<T, LOG2N, PAD, RB, NT2, CB>(xcd_block(blockIdx.x, col_tiles<LOG2N, PAD, CB>()), S, Tq, skip);
+}
+
+// Several padded problems: the tiles of all problems are dealt to the XCDs
+// as one range, so neighbouring tiles of a problem share an L2.
+template <typename T, int LOG2N, int RB, int NT2, int CB>
+__global__ void __launch_bounds__(CB * NT2) k_cols_batch(ApplyBatch ba) {
+  constexpr int NB = col_tiles<LOG2N, true, CB>();
+  const int g = xcd_block(blockIdx.x, NB * ba.n);
+  const int q = g / NB;
+  cols_body<T, LOG2N, true, RB, NT2, CB>(g - q * NB, static_cast<cx<T>*>(ba.S[q]), static_cast<const T*>(ba.T[q]),
+                                        nullptr);
+}
+
 // ---------------------------------------------------------------------------
 // K3: inverse row transform (half spectrum -> first N real outputs)
 // ---------------------------------------------------------------------------
 // EPI: the reduction of EpiArgs mode EPI (0: none) over the cells written.
 template <typename T, int LOG2N, bool PAD, int RB, int NT1, int G, int EPI = 0>
-__global__ void __launch_bounds__(G * RB * NT1)
-k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restrict__ tw_g,
-           const int* __restrict__ skip, EpiArgs ea) {
+__device__ __forceinline__ void rows_inv_body(int bid, const cx<T>* __restrict__ S, T* __restrict__ u,
+                                              const int* __restrict__ skip, const EpiArgs& ea) {
   if (skip && (skip[0] | skip[1])) return;
   using C = cx<T>;
   constexpr int N = 1 << LOG2N, M = PAD ? 2 * N : N, L = M / 2, NC = L + 1;
@@ -370,14 +406,14 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
   const TW tw{tws, tws + TW::NLO};
   constexpr int ITEMS = G * NC * RB;
   constexpr int NIT = (ITEMS + NTH - 1) / NTH;
-  const C* in = S + (size_t)blockIdx.x * ITEMS;
+  const C* in = S + (size_t)bid * ITEMS;
   // The operands of the EPI sums (the cells this thread writes in the last
   // pass) are loaded first, so that their latency overlaps the transform.
   constexpr int RL = last_radix(L, E);
   constexpr int NBL = L / (RL * NT1);
   constexpr int RHL = PAD ? RL / 2 : RL;  // outputs kept per butterfly
   const int lrow = tid / NT1, t = tid % NT1;
-  const size_t row = (size_t)blockIdx.x * ROWS + lrow;
+  const size_t row = (size_t)bid * ROWS + lrow;
   uchar2 e_act[NBL][RHL];
   C e_g[NBL][RHL], e_t[NBL][RHL];
   if constexpr (EPI != 0) {
@@ -449,7 +485,7 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
   MidPasses<T, L, M, NT1, -1, PS, 1, L / RL>::run(line, t, tw);
   {
     constexpr int NB = NBL;
-    C* zo = reinterpret_cast<C*>(u + (size_t)(blockIdx.x * ROWS + lrow) * N);
+    C* zo = reinterpret_cast<C*>(u + (size_t)(bid * ROWS + lrow) * N);
     C a[NB][RL];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
@@ -521,10 +557,23 @@ k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const cx<T>* __restri
       }
       if (tid == 0) {
 #pragma unroll
-        for (int q = 0; q < Q; q++) ea.region[8 + blockIdx.x * Q + q] = red[q * NTH];
+        for (int q = 0; q < Q; q++) ea.region[8 + bid * Q + q] = red[q * NTH];
       }
     }
   }
+}
+
+template <typename T, int LOG2N, bool PAD, int RB, int NT1, int G, int EPI = 0>
+__global__ void __launch_bounds__(G * RB * NT1)
+k_rows_inv(const cx<T>* __restrict__ S, T* __restrict__ u, const int* __restrict__ skip, EpiArgs ea) {
+  rows_inv_body<T, LOG2N, PAD, RB, NT1, G, EPI>(blockIdx.x, S, u, skip, ea);
+}
+
+template <typename T, int LOG2N, int RB, int NT1, int G>
+__global__ void __launch_bounds__(G * RB * NT1) k_rows_inv_batch(ApplyBatch ba) {
+  const int q = blockIdx.x / ba.nb;
+  rows_inv_body<T, LOG2N, true, RB, NT1, G, 0>(blockIdx.x - q * ba.nb, static_cast<const cx<T>*>(ba.S[q]),
+                                               static_cast<T*>(ba.u[q]), nullptr, EpiArgs{});
 }
 
 // ---------------------------------------------------------------------------
@@ -627,17 +676,50 @@ static hipError_t apply_impl(int stages, const int* skip, const T* p, T* u, cx<T
   const dim3 grows(nb_rows), brows(G * RB * SH::NT1);
   if (stages & 1) {
     const int pro = epi ? epi->pro : 0;
-    if (pro == 2) hipLaunchKernelGGL(k1d, grows, brows, lr, st, p, S, tw, skip, *epi);
-    else if (pro == 1) hipLaunchKernelGGL(k1p, grows, brows, lr, st, p, S, tw, skip, *epi);
-    else hipLaunchKernelGGL(k1, grows, brows, lr, st, p, S, tw, skip, EpiArgs{});
+    if (pro == 2) hipLaunchKernelGGL(k1d, grows, brows, lr, st, p, S, skip, *epi);
+    else if (pro == 1) hipLaunchKernelGGL(k1p, grows, brows, lr, st, p, S, skip, *epi);
+    else hipLaunchKernelGGL(k1, grows, brows, lr, st, p, S, skip, EpiArgs{});
   }
-  if (stages & 2) hipLaunchKernelGGL(k2, dim3(nb_cols), dim3(SH::CB * SH::NT2), lc, st, S, Tq, tw, skip);
+  if (stages & 2) hipLaunchKernelGGL(k2, dim3(nb_cols), dim3(SH::CB * SH::NT2), lc, st, S, Tq, skip);
   if (stages & 4) {
     const int mode = epi ? epi->mode : 0;
-    if (mode == 1) hipLaunchKernelGGL(k3d, grows, brows, lr, st, (const cx<T>*)S, u, tw, skip, *epi);
-    else if (mode == 2) hipLaunchKernelGGL(k3p, grows, brows, lr, st, (const cx<T>*)S, u, tw, skip, *epi);
-    else hipLaunchKernelGGL(k3, grows, brows, lr, st, (const cx<T>*)S, u, tw, skip, EpiArgs{});
+    if (mode == 1) hipLaunchKernelGGL(k3d, grows, brows, lr, st, (const cx<T>*)S, u, skip, *epi);
+    else if (mode == 2) hipLaunchKernelGGL(k3p, grows, brows, lr, st, (const cx<T>*)S, u, skip, *epi);
+    else hipLaunchKernelGGL(k3, grows, brows, lr, st, (const cx<T>*)S, u, skip, EpiArgs{});
   }
+  return hipGetLastError();
+}
+
+// The padded convolution of ba.n problems: one launch per stage, the blocks
+// of problem q after those of problems 0..q-1.  n = 0 only sets the
+// kernels' dynamic-LDS attributes.
+template <typename T, int LOG2N>
+static hipError_t apply_batch_impl(const ApplyBatch& ba, hipStream_t st) {
+  using SH = Shape<LOG2N, true>;
+  constexpr int N = SH::N, RB = row_tile<T>();
+  constexpr int G = tiles_per_block<T, LOG2N, true>();
+  const size_t lr = lds_rows<T, LOG2N, true>(G), lc = lds_cols<T, LOG2N, true>(SH::CB);
+  auto k1 = k_rows_fwd_batch<T, LOG2N, RB, SH::NT1, G>;
+  auto k2 = k_cols_batch<T, LOG2N, RB, SH::NT2, SH::CB>;
+  auto k3 = k_rows_inv_batch<T, LOG2N, RB, SH::NT1, G>;
+  static std::atomic<bool> attr{false};
+  if (!attr.load(std::memory_order_acquire)) {
+    hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
+    hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc);
+    hipFuncSetAttribute((const void*)k3, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lr);
+    attr.store(true, std::memory_order_release);
+  }
+  if (ba.n <= 0) return hipSuccess;
+  if (ba.n > CB_BATCH_MAX) return hipErrorInvalidValue;
+  const int nb_rows = N / (RB * G);
+  const int nb_cols = col_tiles<LOG2N, true, SH::CB>();
+  ApplyBatch b = ba;
+  b.nb = nb_rows;
+  hipLaunchKernelGGL(k1, dim3(nb_rows * ba.n), dim3(G * RB * SH::NT1), lr, st, b);
+  b.nb = nb_cols;
+  hipLaunchKernelGGL(k2, dim3(nb_cols * ba.n), dim3(SH::CB * SH::NT2), lc, st, b);
+  b.nb = nb_rows;
+  hipLaunchKernelGGL(k3, dim3(nb_rows * ba.n), dim3(G * RB * SH::NT1), lr, st, b);
   return hipGetLastError();
 }
 
@@ -704,8 +786,22 @@ static void prepare_n() {
   (void)apply_impl<double, LOG2N, true>(0, nullptr, nd, nd, nullptr, nullptr, nullptr, nullptr);
   (void)apply_impl<float, LOG2N, false>(0, nullptr, nf, nf, nullptr, nullptr, nullptr, nullptr);
   (void)apply_impl<double, LOG2N, false>(0, nullptr, nd, nd, nullptr, nullptr, nullptr, nullptr);
+  (void)apply_batch_impl<float, LOG2N>(ApplyBatch{}, nullptr);
+  (void)apply_batch_impl<double, LOG2N>(ApplyBatch{}, nullptr);
 }
 }  // namespace fftv<variant>
+
+hipError_t CB_CAT(launch_apply_batch_v, CB_FFT_VARIANT)(int log2n, int prec, const ApplyBatch& ba, hipStream_t st) {
+  using namespace CB_CAT(fftv, CB_FFT_VARIANT);
+  switch (log2n) {
+#define CB_BATCH_CASE(k) \
+  case k: return prec == 0 ? apply_batch_impl<double, k>(ba, st) : apply_batch_impl<float, k>(ba, st);
+    CB_BATCH_CASE(4) CB_BATCH_CASE(5) CB_BATCH_CASE(6) CB_BATCH_CASE(7)
+    CB_BATCH_CASE(8) CB_BATCH_CASE(9) CB_BATCH_CASE(10) CB_BATCH_CASE(11) CB_BATCH_CASE(12)
+#undef CB_BATCH_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
 
 int CB_CAT(rows_blocks_v, CB_FFT_VARIANT)(int log2n, int prec, int periodic) {
   using namespace CB_CAT(fftv, CB_FFT_VARIANT);

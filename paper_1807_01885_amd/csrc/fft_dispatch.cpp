@@ -33,6 +33,15 @@ hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t 
   return kApply[v](P, p, u, st, stages, skip, table, prec, epi);
 }
 
+using BatchFn = hipError_t (*)(int, int, const ApplyBatch&, hipStream_t);
+static const BatchFn kBatch[CB_FFT_VARIANTS] = {launch_apply_batch_v0, launch_apply_batch_v1, launch_apply_batch_v2,
+                                                launch_apply_batch_v3, launch_apply_batch_v4, launch_apply_batch_v5};
+
+hipError_t launch_apply_batch(const cb_plan_s* P0, const ApplyBatch& ba, hipStream_t st) {
+  const int prec = P0->precision == CB_FP64 ? 0 : 1;
+  return kBatch[P0->variant[prec]](P0->log2n, prec, ba, st);
+}
+
 int rows_blocks(const cb_plan_s* P, int prec, bool periodic) {
   if (prec < 0) prec = P->precision;
   const int v = P->variant[prec == 0 ? 0 : 1];

@@ -221,6 +221,20 @@ struct EpiArgs {
   int plain0 = 0;  // the first (or only) phase uses the plain direction
   int two = 0;     // two-phase solve
 };
+// Several padded problems of one size and precision in one launch per
+// stage: problem q's input, intermediate, table (1/M^2 folded) and output.
+constexpr int CB_BATCH_MAX = 32;
+struct ApplyBatch {
+  int n = 0;   // problems in this launch (<= CB_BATCH_MAX)
+  int nb = 0;  // blocks per problem of the stage being launched
+  const void* p[CB_BATCH_MAX];
+  void* S[CB_BATCH_MAX];
+  const void* T[CB_BATCH_MAX];
+  void* u[CB_BATCH_MAX];
+};
+// one launch per stage for ba.n problems with plan P0's size, precision and
+// launch shape
+hipError_t launch_apply_batch(const cb_plan_s* P0, const ApplyBatch& ba, hipStream_t st);
 hipError_t launch_apply(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages = 7,
                         const int* skip = nullptr, const void* table = nullptr, int prec = -1,
                         const EpiArgs* epi = nullptr);
@@ -234,6 +248,7 @@ void prepare_apply(int log2n);
   hipError_t launch_apply_v##k(const cb_plan_s* P, const void* p, void* u, hipStream_t st, int stages,   \
                                const int* skip, const void* table, int prec, const EpiArgs* epi);       \
   int rows_blocks_v##k(int log2n, int prec, int periodic);                                               \
+  hipError_t launch_apply_batch_v##k(int log2n, int prec, const ApplyBatch& ba, hipStream_t st);          \
   void prepare_apply_v##k(int log2n);                                                                    \
   size_t lds_bytes_v##k(int log2n, int prec);
 CB_DECLARE_FFT_VARIANT(0)

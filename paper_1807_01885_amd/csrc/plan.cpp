@@ -1,5 +1,6 @@
 // Plan construction: parameter checks, the FP64 transfer table of Eq. 9-11
 // with its DC value, twiddle tables, device workspace.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -641,6 +642,38 @@ extern "C" int cb_apply_K(cb_plan P, const void* p, void* u) {
   if (p == u) return cb_fail(CB_E_INVALID, "u must not alias p");
   if (!cb::aligned16(p) || !cb::aligned16(u)) return cb_fail(CB_E_INVALID, "p and u must be 16-byte aligned");
   CB_HIP(cb::launch_apply(P, p, u, P->stream));
+  return CB_OK;
+}
+
+extern "C" int cb_apply_K_batch(int n, const cb_plan* plans, const void* const* p, void* const* u) {
+  if (n < 0 || (n > 0 && (!plans || !p || !u))) return cb_fail(CB_E_INVALID, "null argument or negative count");
+  if (n == 0) return CB_OK;
+  const cb_plan_s* P0 = plans[0];
+  if (!P0) return cb_fail(CB_E_INVALID, "null plan");
+  const int prec = P0->precision == CB_FP64 ? 0 : 1;
+  for (int i = 0; i < n; i++) {
+    const cb_plan_s* P = plans[i];
+    if (!P || !p[i] || !u[i]) return cb_fail(CB_E_INVALID, "null plan or array in the batch");
+    if (P->N != P0->N || P->precision != P0->precision || P->kernel_mode != CB_KERNEL_PADDED ||
+        P->variant[prec] != P0->variant[prec] || P->device != P0->device)
+      return cb_fail(CB_E_INVALID, "batched plans must share N, precision, launch shape and device, padded kernel");
+    if (p[i] == u[i]) return cb_fail(CB_E_INVALID, "u must not alias p");
+    if (!cb::aligned16(p[i]) || !cb::aligned16(u[i])) return cb_fail(CB_E_INVALID, "arrays must be 16-byte aligned");
+    for (int k = 0; k < i; k++)
+      if (plans[k] == P) return cb_fail(CB_E_INVALID, "a plan appears twice in the batch");
+  }
+  for (int i0 = 0; i0 < n; i0 += cb::CB_BATCH_MAX) {
+    cb::ApplyBatch ba;
+    ba.n = std::min(cb::CB_BATCH_MAX, n - i0);
+    for (int q = 0; q < ba.n; q++) {
+      const cb_plan_s* P = plans[i0 + q];
+      ba.p[q] = p[i0 + q];
+      ba.S[q] = P->d_S;
+      ba.T[q] = P->d_table;
+      ba.u[q] = u[i0 + q];
+    }
+    CB_HIP(cb::launch_apply_batch(P0, ba, P0->stream));
+  }
   return CB_OK;
 }
 

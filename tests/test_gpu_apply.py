@@ -110,3 +110,45 @@ def test_plan_table_matches_oracle(lib):
     info = lib.cb_plan_get_info(plan)
     assert info["sigma_c"] == pytest.approx(critical_stress(LAYER, 1e-3, L / N), rel=1e-14)
     assert info["M"] == 2 * N and info["precision"] == 1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("N,n", [(64, 40), (256, 9), (1024, 3)])
+def test_apply_batch_equals_individual(lib, N, n, prec):
+    """cb_apply_K_batch packs n problems (different coatings, one size) into
+    one launch per stage (groups of 32): each output equals the problem's
+    own cb_apply_K bit for bit (same kernels, tables and arithmetic), and
+    the first matches the oracle (1e-12 FP64, 3e-6 FP32 of max |u|)."""
+    print(f"apply batch N={N} n={n} {prec}", flush=True)
+    from oracle.operator import Operator
+    from oracle.transfer import Material
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rng = np.random.default_rng(N + n)
+    mats = [Material(float(rng.uniform(0.01, 0.2)), float(rng.uniform(0.05, 50.0)), 0.3, 1.0,
+                     float(rng.uniform(0.2, 0.45))) for _ in range(n)]
+    plans = [lib.cb_plan_create(N, 1.0, m.h, m.E1, m.nu1, m.E2, m.nu2, 0.0, prec) for m in mats]
+    ps = [torch.tensor(rng.standard_normal((N, N)), dtype=dt, device="cuda") for _ in range(n)]
+    us = [torch.full((N, N), float("nan"), dtype=dt, device="cuda") for _ in range(n)]
+    lib.cb_apply_K_batch(plans, ps, us)
+    torch.cuda.synchronize()
+    for i in range(n):
+        u1 = torch.empty_like(ps[i])
+        lib.cb_apply_K(plans[i], ps[i], u1)
+        torch.cuda.synchronize()
+        assert torch.equal(u1, us[i]), f"problem {i} differs from its own apply"
+    op = Operator(N, 1.0, mats[0])
+    ref = op.apply(ps[0].double().cpu().numpy())
+    err = np.abs(us[0].double().cpu().numpy() - ref).max() / np.abs(ref).max()
+    assert err <= (1e-12 if prec == "fp64" else 3e-6)
+
+
+def test_apply_batch_rejects_mixed(lib):
+    a = lib.cb_plan_create(64, 1.0, 0.1, 1.0, 0.3, 1.0, 0.3, 0.0, "fp64")
+    b = lib.cb_plan_create(128, 1.0, 0.1, 1.0, 0.3, 1.0, 0.3, 0.0, "fp64")
+    c = lib.cb_plan_create(64, 1.0, 0.1, 1.0, 0.3, 1.0, 0.3, 0.0, "fp64", kernel_mode="periodic")
+    p64 = torch.zeros(64, 64, dtype=torch.float64, device="cuda")
+    p128 = torch.zeros(128, 128, dtype=torch.float64, device="cuda")
+    for plans, ps in (([a, b], [p64, p128]), ([a, c], [p64, p64.clone()])):
+        with pytest.raises(lib.CoatbemError) as e:
+            lib.cb_apply_K_batch(plans, ps, [torch.empty_like(x) for x in ps])
+        assert e.value.status == lib.CB_E_INVALID
