@@ -1171,8 +1171,13 @@ static int pk_solve(cb_plan_s* P, const double* f, double target, bool force, do
 // restart is CB_E_NOCONV.
 constexpr int SET_REFINE = 4;
 template <typename TD>
+// `pending` (nullable): host copy of the previous round's detach/attach
+// counts, read with this call's first state read; if both are zero that
+// round changed nothing and the call stops there (*unchanged = true) with
+// u = K x of the unchanged state.  On CB_OK, u = K x (the final check).
 static int set_solve(const Ctx& c, const double* f, double d, const unsigned char* S, double* x, double tol,
-                     int max_iter, int chunk, int pk, int& iters, double& resid) {
+                     int max_iter, int chunk, int pk, int& iters, double& resid, const double* pending = nullptr,
+                     bool* unchanged = nullptr) {
   cb_plan_s* P = c.P;
   double* u = (double*)P->d_u;
   double* r = (double*)P->d_g;
@@ -1187,6 +1192,10 @@ static int set_solve(const Ctx& c, const double* f, double d, const unsigned cha
     hipLaunchKernelGGL(k_mcg_init_fin, dim3(1), blk, 0, c.st, P->d_state, P->d_part, c.nb);
     SolverState s;
     if (int rc = read_state(P, &s)) return rc;
+    if (attempt == 0 && pending && pending[0] == 0.0 && pending[1] == 0.0) {
+      *unchanged = true;
+      return CB_OK;
+    }
     if (s.nonfinite) return CB_E_NONFINITE;
     resid = s.resid;
     // converged on the true residual; or out of refinement restarts or
@@ -1223,22 +1232,35 @@ static int adhesive_step(const Ctx& c, const double* f, double d, double* p, uns
     CB_HIP(apply64(c, p, u, nullptr));
     hipLaunchKernelGGL(k_attach_start, grid, blk, 0, c.st, f, (const double*)u, d, S, P->d_det, p, c.n);
   }
-  while (rounds < op.max_rounds) {
-    rounds++;
+  // Each round: the fixed-set solve (its final check leaves u = K p), then
+  // the Eq. 12 detachment and attachment.  The round's counts are not read
+  // on their own: they travel with the next solve's first state read, and a
+  // round that changed nothing ends the step there (that solve's start
+  // only recomputes u of the unchanged state).
+  double* pending = reinterpret_cast<double*>(&P->h_state[1]);
+  bool have_pending = false;
+  while (true) {
     // fixed-set CG: automatic = preconditioned by the inverse symbol (on a
     // fixed set it needs 3-7x fewer iterations than plain CG)
     const int pk = op.precond >= 0 ? op.precond : 2;
-    const int rc = set_solve<TD>(c, f, d, S, p, op.tol, op.max_iter, op.chunk, pk, iters, resid);
+    bool unchanged = false;
+    const int rc = set_solve<TD>(c, f, d, S, p, op.tol, op.max_iter, op.chunk, pk, iters, resid,
+                                 have_pending ? pending : nullptr, &unchanged);
     if (rc != CB_OK) { status = rc; break; }
-    CB_HIP(apply64(c, p, u, nullptr));
+    if (unchanged) break;
+    rounds++;
     hipLaunchKernelGGL(k_detach_attach, grid, blk, 0, c.st, f, (const double*)u, p, (const unsigned char*)S, Salt,
                        P->d_det, P->N, d, P->sigma_c, op.atol, P->d_part);
     hipLaunchKernelGGL(k_fold_misc<2>, dim3(1), blk, 0, c.st, P->d_part, c.nb, 0);
-    double ch[2];
-    if (int e = read_scratch(c, ch, 2)) return e;
     std::swap(S, Salt);
-    if (ch[0] == 0.0 && ch[1] == 0.0) break;
-    if (rounds == op.max_rounds) status = CB_E_NOCONV;
+    if (rounds == op.max_rounds) {
+      double ch[2];
+      if (int e = read_scratch(c, ch, 2)) return e;
+      if (ch[0] != 0.0 || ch[1] != 0.0) status = CB_E_NOCONV;
+      break;
+    }
+    CB_HIP(hipMemcpyAsync(pending, P->d_part + SCRATCH_OFF, 2 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    have_pending = true;
   }
   hipLaunchKernelGGL(k_stats, grid, blk, 0, c.st, (const double*)p, (const double*)u, (const unsigned char*)S,
                      P->d_part, c.n);
