@@ -153,7 +153,8 @@ __device__ __forceinline__ void rows_fwd_body(int bid, const T* __restrict__ p, 
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = t + b * NT1;
-      dft<T, R, 1>(a[b]);
+      if constexpr (PAD) dft_half_in<T, R, 1>(a[b]);  // the upper half of the inputs is padding
+      else dft<T, R, 1>(a[b]);
 #pragma unroll
       for (int i = 0; i < R; i++) line[padi<PS>(out_index<R, 1>(j, i))] = a[b][i];
     }
@@ -258,7 +259,8 @@ __device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = t + b * NT2;
-      dft<T, R0, 1>(a[b]);
+      if constexpr (PAD) dft_half_in<T, R0, 1>(a[b]);  // rows N..M-1 are padding
+      else dft<T, R0, 1>(a[b]);
 #pragma unroll
       for (int i = 0; i < R0; i++) line[padi<PS>(out_index<R0, 1>(j, i))] = a[b][i];
     }
@@ -350,7 +352,7 @@ __device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = t + b * NT2;
-      butterfly<T, L, M, RIL, L / RIL, -1>(a[b], j, tw);
+      butterfly<T, L, M, RIL, L / RIL, -1, PAD>(a[b], j, tw);  // padded: only rows n < N are kept
       if (active) {
 #pragma unroll
         for (int i = 0; i < (PAD ? RIL / 2 : RIL); i++) {
@@ -502,7 +504,7 @@ __device__ __forceinline__ void rows_inv_body(int bid, const cx<T>* __restrict__
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = t + b * NT1;
-      butterfly<T, L, M, RL, L / RL, -1>(a[b], j, tw);
+      butterfly<T, L, M, RL, L / RL, -1, PAD>(a[b], j, tw);  // padded: only columns c < N are kept
 #pragma unroll
       for (int i = 0; i < (PAD ? RL / 2 : RL); i++) {
         const int c = j + i * (L / RL);

@@ -83,6 +83,68 @@ __device__ __forceinline__ void dft(cx<T>* a) {
   }
 }
 
+// x * exp(-DIR 2 pi i n / R) for 0 <= n < R/2, R <= 16 (a constant root).
+template <typename T, int R, int DIR>
+__device__ __forceinline__ cx<T> rot_root(cx<T> x, int n) {
+  const int m = n * (16 / R);
+  if (m == 0) return x;
+  if (m == 4) return mul_mi<DIR>(x);
+  return cmul(x, root16<T, DIR>(m));
+}
+
+// DFT of length R whose upper half of inputs a[R/2..R-1] is zero (not
+// read): X[2m] is the length-R/2 DFT of a, X[2m+1] that of a[n] w^n.
+// Natural-order outputs in a[0..R-1].
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void dft_half_in(cx<T>* a) {
+  using C = cx<T>;
+  if constexpr (R == 1) {
+    return;
+  } else if constexpr (R == 2) {
+    a[1] = a[0];
+  } else {
+    constexpr int H = R / 2;
+    C e[H], o[H];
+#pragma unroll
+    for (int n = 0; n < H; n++) {
+      e[n] = a[n];
+      o[n] = rot_root<T, R, DIR>(a[n], n);
+    }
+    dft<T, H, DIR>(e);
+    dft<T, H, DIR>(o);
+#pragma unroll
+    for (int m = 0; m < H; m++) {
+      a[2 * m] = e[m];
+      a[2 * m + 1] = o[m];
+    }
+  }
+}
+
+// DFT of length R of which only the lower half of the outputs is formed:
+// X[k] = E[k] + w^k O[k], k < R/2, E and O the length-R/2 DFTs of the even
+// and odd inputs; written to a[0..R/2-1] (the upper half is left undefined).
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void dft_half_out(cx<T>* a) {
+  using C = cx<T>;
+  if constexpr (R == 1) {
+    return;
+  } else if constexpr (R == 2) {
+    a[0] = cadd(a[0], a[1]);
+  } else {
+    constexpr int H = R / 2;
+    C e[H], o[H];
+#pragma unroll
+    for (int n = 0; n < H; n++) {
+      e[n] = a[2 * n];
+      o[n] = a[2 * n + 1];
+    }
+    dft<T, H, DIR>(e);
+    dft<T, H, DIR>(o);
+#pragma unroll
+    for (int k = 0; k < H; k++) a[k] = cadd(e[k], rot_root<T, R, DIR>(o[k], k));
+  }
+}
+
 // Two-level twiddle table for a transform length LT (power of two):
 // w(e) = exp(-2 pi i e / LT) = hi[e >> 6] * lo[e & 63] (LT > 64), lo[e] else.
 template <typename T, int LT>
@@ -133,7 +195,8 @@ __host__ __device__ constexpr int last_radix(int L, int E) { return last_radix_f
 // w, w^4 and (R = 16) w^8 and products of at most two further factors, so
 // that each is within a few roundings of exact while most lookups (two LDS
 // reads, index arithmetic and a product each) are saved.
-template <typename T, int L, int LT, int R, int Ls, int DIR>
+// HALF_OUT: only the lower half of the butterfly's outputs is formed.
+template <typename T, int L, int LT, int R, int Ls, int DIR, bool HALF_OUT = false>
 __device__ __forceinline__ void butterfly(cx<T>* a, int j, const Tw<T, LT>& tw) {
   if constexpr (Ls > 1) {
     const int k = j & (Ls - 1);
@@ -165,7 +228,8 @@ __device__ __forceinline__ void butterfly(cx<T>* a, int j, const Tw<T, LT>& tw) 
       a[i] = cmul(a[i], w[i]);
     }
   }
-  dft<T, R, DIR>(a);
+  if constexpr (HALF_OUT) dft_half_out<T, R, DIR>(a);
+  else dft<T, R, DIR>(a);
 }
 
 template <int R, int Ls>
