@@ -62,7 +62,7 @@ enum {
                              Eq. 11 evaluated so that it equals the
                              non-periodic sum of Eq. 1 over the patch, with
                              point-sampled K^ and the DC value of dc_mode */
-  CB_KERNEL_PERIODIC = 1  /* Eq. 11 literally: the surface is L-periodic, the
+  CB_KERNEL_PERIODIC = 1, /* Eq. 11 literally: the surface is L-periodic, the
                              transforms have length N (no padding) and the
                              pressure has no DC component (K^(0) = 0: a
                              uniform pressure produces no displacement and u
@@ -71,6 +71,20 @@ enum {
                              d it returns is relative to the mean surface.
                              Non-adhesive only (Eq. 12 is derived for a
                              non-periodic system) */
+  CB_KERNEL_EXACT = 2     /* the non-periodic sum of Eq. 1 with each cell
+                             carrying a uniform pressure: K[i][j] is the exact
+                             displacement at the centre of cell i due to unit
+                             pressure over cell j, the cell integral of the
+                             inverse Fourier transform of K^ (Eq. 2-3, 9-11),
+                             evaluated by the same 2N-padded convolution with
+                             the table of those coefficients (their DFT,
+                             cb_transfer_table_exact).  No DC choice and no
+                             images: the patch sum is exact up to the
+                             coefficients' quadrature (about 1e-12).  Needs a
+                             top layer at least Delta/8 thick (thinner:
+                             CB_E_UNSUPPORTED); h = 0 or a coating of the
+                             substrate's material is the half-space (Love's
+                             coefficients) */
 };
 
 /* Plan options; a NULL pointer selects every default. */
@@ -100,7 +114,8 @@ typedef struct {
                       2 (16, 8, 1x), 3 (8, 16, 1x), 4 (16, 16, 2x),
                       5 (16, 32, 1x), 6 (8, 8, 2x).  All give the same
                       transform up to rounding order. */
-  int kernel_mode; /* CB_KERNEL_PADDED (default) or CB_KERNEL_PERIODIC */
+  int kernel_mode; /* CB_KERNEL_PADDED (default), CB_KERNEL_PERIODIC or
+                      CB_KERNEL_EXACT (dc_mode is then ignored) */
 } cb_plan_opts;
 
 /* Solve options; a NULL pointer selects every default. */
@@ -239,7 +254,8 @@ int cb_plan_get_info(cb_plan plan, cb_plan_info* info);
  * a, b in [0, n), n = cb_plan_info.table_n (host memory, row-major), DC at
  * [0][0], WITHOUT the inverse-FFT factor the device copy carries.  Padded
  * plans: n = N + 1, Delta_k = 2 pi / (2 N Delta); periodic plans:
- * n = N/2 + 1, Delta_k = 2 pi / L, T[0][0] = 0. */
+ * n = N/2 + 1, Delta_k = 2 pi / L, T[0][0] = 0; exact plans: n = N + 1,
+ * the table of cb_transfer_table_exact. */
 int cb_plan_get_table(cb_plan plan, double* table_host);
 
 /*
@@ -251,6 +267,29 @@ int cb_plan_get_table(cb_plan plan, double* table_host);
 int cb_transfer_table(int N, double L, double h, double E1, double nu1,
                       double E2, double nu2, int dc_mode, double* table_host,
                       double* k00_host);
+
+/*
+ * cb_transfer_table_exact -- exact influence coefficients of uniformly
+ *   loaded square cells and the table of the CB_KERNEL_EXACT plans, on the
+ *   host (no device, no plan).  Eq. 1 with piecewise-constant pressure; the
+ *   displacement due to a load is the inverse Fourier transform of K^ times
+ *   the load's transform (Eq. 2-3, 11), K^ of Eq. 9-10.
+ *   D_host (nullable): (N+1)^2 doubles, D[m][q] = displacement at the cell
+ *   offset (m Delta, q Delta), m, q in [0, N], due to unit pressure over one
+ *   cell (symmetric in m, q).  table_host (nullable): (N+1)^2 doubles, the
+ *   2-D DFT of the 2N-periodic embedding D_circ[m] = D[|m|] (|m| < N),
+ *   D_circ[N] = D[N], i.e. T[a][b] = sum_{m,q} w_m w_q D[m][q]
+ *   cos(pi a m/N) cos(pi b q/N), w = 1 at 0 and N, 2 between.  At least one
+ *   output.  Arguments as cb_plan_create; a top layer thinner than Delta/8
+ *   (h > 0): CB_E_UNSUPPORTED.  Runs on up to 16 host threads.
+ */
+int cb_transfer_table_exact(int N, double L, double h, double E1, double nu1, double E2, double nu2,
+                            double* table_host, double* D_host);
+
+/* The same for a layered stack (arguments as cb_plan_create_layered). */
+int cb_transfer_table_exact_layered(int N, double L, int nlayers, const double* h_host, const double* E_host,
+                                    const double* nu_host, double Es, double nus, double* table_host,
+                                    double* D_host);
 
 /* Change the stream later calls are enqueued on (hipStream_t). */
 int cb_plan_set_stream(cb_plan plan, void* stream);
@@ -268,7 +307,7 @@ int cb_apply_K(cb_plan plan, const void* p, void* u);
  *   2N-padded grid, as cb_apply_K), packed into one launch per transform
  *   stage (up to 32 problems per launch; more are launched in groups): for
  *   small grids one convolution is set by launch latency, not by its
- *   bytes.  plans[i]: distinct padded plans sharing N, precision, launch
+ *   bytes.  plans[i]: distinct padded or exact plans (not periodic) sharing N, precision, launch
  *   shape and device (materials may differ: each problem multiplies by its
  *   own transfer table and uses its own plan's intermediate).  p[i], u[i]:
  *   device N*N arrays of the plan type, u[i] not aliasing p[i].  Enqueued

@@ -22,7 +22,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 FFT_VARIANTS = 6
 SOURCES = ([("plan.cpp", "plan", []), ("fft_dispatch.cpp", "fft_dispatch", []),
             ("solver.hip", "solver", []), ("batch.cpp", "batch", []), ("net.hip", "net", []),
-             ("noalloc.hip", "noalloc", []), ("layers.cpp", "layers", [])]
+             ("noalloc.hip", "noalloc", []), ("layers.cpp", "layers", []),
+             ("exact.cpp", "exact", [])]
            + [("fft.hip", f"fft_v{k}", [f"-DCB_FFT_VARIANT={k}"]) for k in range(FFT_VARIANTS)])
 ARCH = os.environ.get("COATBEM_ARCH", "gfx950")
 

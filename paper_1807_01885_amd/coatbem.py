@@ -37,7 +37,8 @@ CB_DC_BZ = 0
 CB_DC_ZERO = 1
 CB_KERNEL_PADDED = 0
 CB_KERNEL_PERIODIC = 1
-_KERNEL_MODES = {"padded": CB_KERNEL_PADDED, "periodic": CB_KERNEL_PERIODIC}
+CB_KERNEL_EXACT = 2
+_KERNEL_MODES = {"padded": CB_KERNEL_PADDED, "periodic": CB_KERNEL_PERIODIC, "exact": CB_KERNEL_EXACT}
 
 
 class cb_plan_opts(ctypes.Structure):
@@ -98,6 +99,9 @@ _SIGS = {
     "cb_plan_get_table": (_i, [_vp, ctypes.POINTER(_d)]),
     "cb_plan_set_stream": (_i, [_vp, _vp]),
     "cb_transfer_table": (_i, [_i, _d, _d, _d, _d, _d, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+    "cb_transfer_table_exact": (_i, [_i, _d, _d, _d, _d, _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+    "cb_transfer_table_exact_layered": (_i, [_i, _d, _i, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
+                                             _d, _d, ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "cb_apply_K": (_i, [_vp, _vp, _vp]),
     "cb_apply_K_stages": (_i, [_vp, _vp, _vp, _i]),
     "cb_apply_K_batch": (_i, [_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
@@ -254,6 +258,29 @@ def cb_transfer_table(N, L, h, E1, nu1, E2, nu2, dc_mode="bz"):
                                   float(nu2), CB_DC_BZ if dc_mode == "bz" else CB_DC_ZERO,
                                   out.ctypes.data_as(ctypes.POINTER(_d)), ctypes.byref(k00)))
     return out, k00.value
+
+
+def cb_transfer_table_exact(N, L, h, E1, nu1, E2, nu2):
+    """Host-computed exact cell coefficients and their table: (T, D), both (N+1)^2."""
+    import numpy as np
+    T = np.empty((N + 1, N + 1), dtype=np.float64)
+    D = np.empty((N + 1, N + 1), dtype=np.float64)
+    _check(_lib.cb_transfer_table_exact(int(N), float(L), float(h), float(E1), float(nu1), float(E2), float(nu2),
+                                        T.ctypes.data_as(ctypes.POINTER(_d)), D.ctypes.data_as(ctypes.POINTER(_d))))
+    return T, D
+
+
+def cb_transfer_table_exact_layered(N, L, layers, Es, nus):
+    """As cb_transfer_table_exact for a stack (h, E, nu), top layer first."""
+    import numpy as np
+    n = len(layers)
+    arr = lambda k: (_d * max(n, 1))(*[float(l[k]) for l in layers])
+    T = np.empty((N + 1, N + 1), dtype=np.float64)
+    D = np.empty((N + 1, N + 1), dtype=np.float64)
+    _check(_lib.cb_transfer_table_exact_layered(int(N), float(L), n, arr(0), arr(1), arr(2), float(Es), float(nus),
+                                                T.ctypes.data_as(ctypes.POINTER(_d)),
+                                                D.ctypes.data_as(ctypes.POINTER(_d))))
+    return T, D
 
 
 def cb_plan_set_stream(plan: Plan, stream=None):

@@ -101,11 +101,20 @@ struct LayerStack {
 double layered_compliance(double k, const LayerStack& S);
 // out[a][b] = K^(dk sqrt(a^2 + b^2)) for a, b in [0, n) (out[0][0] = 0)
 void layered_compliance_grid(const LayerStack& S, double dk, int n, std::vector<double>& out);
+// n-point Gauss-Legendre nodes and weights on [-1, 1]
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+// Exact influence coefficients of uniformly loaded square cells of the
+// stack S (no layers: the half-space alone), D[m][q] for cell offsets
+// m, q in [0, N] ((N+1)^2 row-major), and the DFT of their 2N-periodic
+// embedding, T (same layout).  CB_E_UNSUPPORTED when a coating's top layer
+// is thinner than Delta/8.
+int exact_influence(int N, double L, const LayerStack& S, std::vector<double>& D, std::vector<double>& T);
 }  // namespace cb
 
 struct cb_plan_s {
   int N = 0, M = 0, log2n = 0, precision = 0, dc_mode = 0;
-  int kernel_mode = CB_KERNEL_PADDED;  // CB_KERNEL_PERIODIC: N-periodic operator, no DC
+  int kernel_mode = CB_KERNEL_PADDED;  // CB_KERNEL_PERIODIC: N-periodic operator, no DC;
+                                       // CB_KERNEL_EXACT: padded, table from exact cell coefficients
   int table_n = 0;                     // side of the transfer quadrant (N+1 or N/2+1)
   int layered = 0;                     // 1: transfer function of `stack` (any number of layers)
   cb::LayerStack stack;                // layers (top first) and half-space of a layered plan

@@ -54,9 +54,11 @@ inline double shape_m1(double t, const Coef& c) {
   return num / den;
 }
 
+}  // namespace
+
 // n-point Gauss-Legendre nodes/weights on [-1, 1] by Newton's method on
 // P_n (three-term recurrence).
-void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+void cb::gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   x.assign(n, 0.0);
   w.assign(n, 0.0);
   for (int i = 0; i < (n + 1) / 2; i++) {
@@ -87,6 +89,10 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
     w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
   }
 }
+
+namespace {
+
+using cb::gauss_legendre;
 
 // Composite Gauss-Legendre integral of f over [a, b] with `panels` panels.
 template <class F>
@@ -285,6 +291,36 @@ extern "C" int cb_transfer_table(int N, double L, double h, double E1, double nu
   return CB_OK;
 }
 
+// The stack of a one-layer plan (h = 0: the half-space alone).
+static cb::LayerStack one_layer(double h, double E1, double nu1, double E2, double nu2) {
+  cb::LayerStack S;
+  if (h > 0.0) {
+    S.h.push_back(h);
+    S.E.push_back(E1);
+    S.nu.push_back(nu1);
+  }
+  S.Es = E2;
+  S.nus = nu2;
+  return S;
+}
+
+static int exact_out(int rc, const std::vector<double>& T, const std::vector<double>& D, double* table_out,
+                     double* D_out) {
+  if (rc != CB_OK) return rc;
+  if (table_out) std::memcpy(table_out, T.data(), T.size() * sizeof(double));
+  if (D_out) std::memcpy(D_out, D.data(), D.size() * sizeof(double));
+  return CB_OK;
+}
+
+extern "C" int cb_transfer_table_exact(int N, double L, double h, double E1, double nu1, double E2, double nu2,
+                                       double* table_out, double* D_out) {
+  if (!table_out && !D_out) return cb_fail(CB_E_INVALID, "null outputs");
+  if (int rc = check_params(N, L, h, E1, nu1, E2, nu2, 0.0)) return rc;
+  std::vector<double> D, T;
+  const int rc = cb::exact_influence(N, L, one_layer(h, E1, nu1, E2, nu2), D, T);
+  return exact_out(rc, T, D, table_out, D_out);
+}
+
 double cb::plan_shape(const cb_plan_s* P, double k) {
   if (!P->layered) return shape(k * P->h, coefficients(P->E1, P->nu1, P->E2, P->nu2));
   if (!(k > 0.0)) return P->E1s / P->E2s;
@@ -356,6 +392,18 @@ extern "C" int cb_plan_create_layered(cb_plan* out, int N, double L, int nlayers
   return plan_create_impl(out, N, L, h[0], E[0], nu[0], Es, nus, dgamma, o, &S);
 }
 
+extern "C" int cb_transfer_table_exact_layered(int N, double L, int nlayers, const double* h, const double* E,
+                                               const double* nu, double Es, double nus, double* table_out,
+                                               double* D_out) {
+  if (!table_out && !D_out) return cb_fail(CB_E_INVALID, "null outputs");
+  cb::LayerStack S;
+  if (int rc = check_stack(nlayers, h, E, nu, Es, nus, S)) return rc;
+  if (int rc = check_params(N, L, h[0], E[0], nu[0], Es, nus, 0.0)) return rc;
+  std::vector<double> D, T;
+  const int rc = cb::exact_influence(N, L, S, D, T);
+  return exact_out(rc, T, D, table_out, D_out);
+}
+
 extern "C" int cb_transfer_table_layered(int N, double L, int nlayers, const double* h, const double* E,
                                          const double* nu, double Es, double nus, int dc_mode, double* out,
                                          double* k00_out) {
@@ -386,8 +434,9 @@ static int plan_create_impl(cb_plan* out, int N, double L, double h, double E1, 
   if (opts.autotune != 0 && opts.autotune != 1) return cb_fail(CB_E_INVALID, "autotune must be 0 or 1");
   if (opts.fft_variant < 0 || opts.fft_variant > cb::CB_FFT_VARIANTS)
     return cb_fail(CB_E_INVALID, "fft_variant must be 0 (automatic) or 1.." + std::to_string(cb::CB_FFT_VARIANTS));
-  if (opts.kernel_mode != CB_KERNEL_PADDED && opts.kernel_mode != CB_KERNEL_PERIODIC)
-    return cb_fail(CB_E_INVALID, "kernel_mode must be CB_KERNEL_PADDED or CB_KERNEL_PERIODIC");
+  if (opts.kernel_mode != CB_KERNEL_PADDED && opts.kernel_mode != CB_KERNEL_PERIODIC &&
+      opts.kernel_mode != CB_KERNEL_EXACT)
+    return cb_fail(CB_E_INVALID, "kernel_mode must be CB_KERNEL_PADDED, CB_KERNEL_PERIODIC or CB_KERNEL_EXACT");
   if (opts.kernel_mode == CB_KERNEL_PERIODIC && dgamma > 0.0)
     return cb_fail(CB_E_UNSUPPORTED, "adhesion needs a non-periodic kernel (Eq. 12 is derived for a non-periodic "
                                      "system)");
@@ -427,12 +476,28 @@ static int plan_create_impl(cb_plan* out, int N, double L, double h, double E1, 
 
   // ---- FP64 transfer table on the quadrant a, b in [0, table_n) ----------
   const int M = P->M, NC = N + 1;
+  // exact plans: the table of the cell coefficients; the preconditioner's
+  // inverse symbol still samples K^ (ksym: positive at every wavenumber,
+  // which the transform of a truncated embedding need not be)
+  std::vector<double> ksym;
   if (periodic) {
     build_periodic_table(N, L, h, E1, nu1, E2, nu2, P->table64, P->k00, S);
     P->dc = 0.0;
+  } else if (opts.kernel_mode == CB_KERNEL_EXACT) {
+    std::vector<double> D;
+    const int rc = cb::exact_influence(N, L, S ? *S : one_layer(h, E1, nu1, E2, nu2), D, P->table64);
+    if (rc != CB_OK) {
+      delete P;
+      return rc;
+    }
+    P->dc = P->table64[0];
+    P->k00 = D[0];
+    double dc_s, k00_s;
+    build_table(N, L, h, E1, nu1, E2, nu2, CB_DC_BZ, ksym, dc_s, k00_s, S);
   } else {
     build_table(N, L, h, E1, nu1, E2, nu2, opts.dc_mode, P->table64, P->dc, P->k00, S);
   }
+  const std::vector<double>& qsym = ksym.empty() ? P->table64 : ksym;
 
   // ---- device memory ---------------------------------------------------------
   const size_t es = P->precision == CB_FP64 ? 8 : 4;
@@ -478,7 +543,7 @@ static int plan_create_impl(cb_plan* out, int N, double L, double h, double E1, 
         // of the first harmonic there (any positive value keeps M SPD)
         qdev[(size_t)a * NP + b] =
             periodic ? invN / P->table64[(a == 0 && b == 0) ? 1 : (size_t)a * NP + b]
-                     : invN / P->table64[(size_t)(2 * a) * NC + 2 * b];
+                     : invN / qsym[(size_t)(2 * a) * NC + 2 * b];
       }
   }
   // automatic choice from a cold start: the layer multiplier for a coating
@@ -654,7 +719,7 @@ extern "C" int cb_apply_K_batch(int n, const cb_plan* plans, const void* const* 
   for (int i = 0; i < n; i++) {
     const cb_plan_s* P = plans[i];
     if (!P || !p[i] || !u[i]) return cb_fail(CB_E_INVALID, "null plan or array in the batch");
-    if (P->N != P0->N || P->precision != P0->precision || P->kernel_mode != CB_KERNEL_PADDED ||
+    if (P->N != P0->N || P->precision != P0->precision || P->kernel_mode == CB_KERNEL_PERIODIC ||
         P->variant[prec] != P0->variant[prec] || P->device != P0->device)
       return cb_fail(CB_E_INVALID, "batched plans must share N, precision, launch shape and device, padded kernel");
     if (p[i] == u[i]) return cb_fail(CB_E_INVALID, "u must not alias p");
