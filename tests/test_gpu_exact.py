@@ -1,0 +1,187 @@
+"""GPU parity of exact-kernel plans (CB_KERNEL_EXACT: the patch sum of Eq. 1
+with the exact coefficients of uniformly loaded cells, evaluated by the same
+2N-padded convolution kernels) against oracle/exact.py.
+
+Bars: the plan's table equals the host function's bit for bit; apply FP64
+1e-12 and FP32 3e-6 of max |u| against the oracle's operator (the two sets
+of coefficients agree to 1e-12); at N = 1024 the response to unit pressure
+on one cell, at sampled cells, against the oracle's coefficients computed
+one by one (FP64 1e-10 relative); a loaded block of a homogeneous half-space
+against Love's formula (1e-12); solves FP64 pressure 1e-8 with identical
+contact sets, FP32 1e-4 and >= 0.999.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle.exact import Coating, ExactOperator, influence_points, love_rect
+from oracle.solvers import adhesive_solve, solve_pk
+from oracle.transfer import Material, critical_stress
+from paper_1807_01885_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DT = {"fp64": torch.float64, "fp32": torch.float32}
+STIFF = Material(0.05, 10.0, 0.3, 1.0, 0.3)
+SOFT = Material(0.1, 0.2, 0.45, 1.0, 0.25)
+STACK = ([(0.02, 5.0, 0.3), (0.05, 0.5, 0.25)], 1.0, 0.3)
+
+
+def agreement(a, b):
+    u = (a | b).sum()
+    return 1.0 if u == 0 else 1.0 - (a ^ b).sum() / u
+
+
+def _plan(lib, N, L, m, prec, dgamma=0.0):
+    return lib.cb_plan_create(N, L, m.h, m.E1, m.nu1, m.E2, m.nu2, dgamma, prec, kernel_mode="exact")
+
+
+def test_exact_plan_table(lib):
+    print("exact plan table", flush=True)
+    N, L, m = 64, 1.0, STIFF
+    plan = _plan(lib, N, L, m, "fp64")
+    info = lib.cb_plan_get_info(plan)
+    T, D = lib.cb_transfer_table_exact(N, L, m.h, m.E1, m.nu1, m.E2, m.nu2)
+    assert info["kernel_mode"] == lib.CB_KERNEL_EXACT and info["table_n"] == N + 1 and info["M"] == 2 * N
+    np.testing.assert_array_equal(lib.cb_plan_get_table(plan), T)
+    assert info["k00"] == D[0, 0] and info["dc"] == T[0, 0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("N,m", [(16, STIFF), (64, SOFT), (128, STIFF), (64, "stack")])
+def test_exact_apply(lib, N, m, prec):
+    print(f"exact apply N={N} {m} {prec}", flush=True)
+    L = 1.0
+    if m == "stack":
+        layers, Es, nus = STACK
+        plan = lib.cb_plan_create_layered(N, L, layers, Es, nus, 0.0, prec, kernel_mode="exact")
+        op = ExactOperator(N, L, layers=layers, Es=Es, nus=nus)
+    else:
+        plan = _plan(lib, N, L, m, prec)
+        op = ExactOperator(N, L, m)
+    p = np.random.default_rng(N).standard_normal((N, N))
+    u = torch.empty(N, N, dtype=DT[prec], device="cuda")
+    lib.cb_apply_K(plan, torch.tensor(p, dtype=DT[prec], device="cuda"), u)
+    torch.cuda.synchronize()
+    ref = op.apply(p.astype(np.float32).astype(np.float64) if prec == "fp32" else p)
+    err = np.abs(u.double().cpu().numpy() - ref).max() / np.abs(ref).max()
+    print(f"  max rel err {err:.2e}")
+    assert err <= (1e-12 if prec == "fp64" else 3e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_exact_unit_load_full_size(lib, prec):
+    """N = 1024: u = K e_j is column j of Eq. 1's matrix, u_i = D[|i - j|]."""
+    print(f"exact unit load N=1024 {prec}", flush=True)
+    N, L, m = 1024, 1.0, STIFF
+    plan = _plan(lib, N, L, m, prec)
+    j = (300, 700)
+    p = torch.zeros(N, N, dtype=DT[prec], device="cuda")
+    p[j] = 1.0
+    u = torch.empty_like(p)
+    lib.cb_apply_K(plan, p, u)
+    torch.cuda.synchronize()
+    u = u.double().cpu().numpy()
+    rng = np.random.default_rng(7)
+    ii = np.concatenate([[300, 301, 299, 0, 1023, 1023], rng.integers(0, N, 30)])
+    kk = np.concatenate([[700, 700, 702, 0, 0, 1023], rng.integers(0, N, 30)])
+    ref = influence_points(np.abs(ii - j[0]), np.abs(kk - j[1]), L / N, Coating(m))
+    got = u[ii, kk]
+    if prec == "fp64":
+        err = np.max(np.abs(got - ref) / np.abs(ref))
+        print(f"  max rel err {err:.2e}")
+        assert err <= 1e-10
+    else:
+        err = np.max(np.abs(got - ref)) / np.abs(u).max()
+        print(f"  max err / max u {err:.2e}")
+        assert err <= 3e-6
+
+
+def test_exact_loaded_block_is_love(lib):
+    """Homogeneous half-space, unit pressure on a block of cells: u at every
+    cell centre is Love's formula for the block (the exact kernel's
+    defining property; the padded point-sampled kernel misses it by its
+    image and DC error, printed for comparison)."""
+    print("exact loaded block", flush=True)
+    N, L = 256, 1.0
+    m = Material(0.1, 1.0, 0.3, 1.0, 0.3)
+    dx = L / N
+    p = np.zeros((N, N))
+    p[60:124, 100:140] = 1.0
+    c = (np.arange(N) + 0.5) * dx
+    X, Y = np.meshgrid(c, c, indexing="ij")
+    ref = love_rect(X - 92 * dx, Y - 120 * dx, 32 * dx, 20 * dx, m.E1s)
+    errs = {}
+    for mode in ("exact", "padded"):
+        plan = lib.cb_plan_create(N, L, m.h, m.E1, m.nu1, m.E2, m.nu2, 0.0, "fp64", kernel_mode=mode)
+        u = torch.empty(N, N, dtype=torch.float64, device="cuda")
+        lib.cb_apply_K(plan, torch.tensor(p, device="cuda"), u)
+        torch.cuda.synchronize()
+        errs[mode] = np.max(np.abs(u.cpu().numpy() - ref) / ref)
+    print(f"  max rel err exact {errs['exact']:.2e} padded {errs['padded']:.2e}")
+    assert errs["exact"] <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_exact_force_solve(lib, prec):
+    print(f"exact force solve {prec}", flush=True)
+    N, L, m = 128, 1.0, STIFF
+    f = inputs.paraboloid(N, L, 1.0)
+    op = ExactOperator(N, L, m)
+    d = 4e-3
+    ref = solve_pk(op, f, d, tol=1e-10)
+    assert ref.converged
+    plan = _plan(lib, N, L, m, prec)
+    ft = torch.tensor(f, device="cuda")
+    p = torch.zeros_like(ft)
+    mask = torch.zeros(N, N, dtype=torch.uint8, device="cuda")
+    tol = 1e-10 if prec == "fp64" else 1e-8
+    res = lib.cb_solve_force(plan, ft, ref.F, p, mask, tol=tol)
+    e_p = np.linalg.norm(p.cpu().numpy() - ref.p) / np.linalg.norm(ref.p)
+    agr = agreement(mask.cpu().numpy().astype(bool), ref.p > 0)
+    print(f"  iters {res['iters']} (oracle {ref.iters}) e_p {e_p:.2e} d {res['d']:.6e} vs {d:.6e} agree {agr}")
+    if prec == "fp64":
+        assert e_p < 1e-8 and agr == 1.0 and res["d"] == pytest.approx(d, rel=1e-8)
+    else:
+        assert e_p < 1e-4 and agr >= 0.999 and res["d"] == pytest.approx(d, rel=1e-5)
+
+
+def test_exact_adhesive_solve(lib):
+    print("exact adhesive", flush=True)
+    N, L, m = 64, 1.0, STIFF
+    f = inputs.paraboloid(N, L, 1.0)
+    d, dg = 3e-3, 3e-5  # five Eq. 12 rounds in the oracle
+    op = ExactOperator(N, L, m)
+    sc = critical_stress(m, dg, L / N)
+    st, rounds, _, conv = adhesive_solve(op, f, d, sc, 1e-12 * L, tol=1e-10)
+    assert conv
+    plan = _plan(lib, N, L, m, "fp64", dgamma=dg)
+    ft = torch.tensor(f, device="cuda")
+    p = torch.zeros_like(ft)
+    mask = torch.zeros(N, N, dtype=torch.uint8, device="cuda")
+    res = lib.cb_solve_indent(plan, ft, d, p, mask, tol=1e-10)
+    assert np.array_equal(mask.cpu().numpy().astype(bool), st.S)
+    e_p = np.linalg.norm(p.cpu().numpy() - st.p) / np.linalg.norm(st.p)
+    print(f"  rounds {res['rounds']} (oracle {rounds}) e_p {e_p:.2e}")
+    assert e_p < 1e-8 and res["rounds"] == rounds and rounds > 1
+
+
+def test_exact_batch_apply_equals_single(lib):
+    print("exact batch apply", flush=True)
+    N = 128
+    mats = [STIFF, SOFT, Material(0.02, 3.0, 0.3, 1.0, 0.3)]
+    plans = [_plan(lib, N, 1.0, m, "fp32") for m in mats]
+    ps = [torch.randn(N, N, dtype=torch.float32, device="cuda") for _ in mats]
+    us = [torch.empty_like(x) for x in ps]
+    lib.cb_apply_K_batch(plans, ps, us)
+    for plan, x, ub in zip(plans, ps, us):
+        u1 = torch.empty_like(x)
+        lib.cb_apply_K(plan, x, u1)
+        torch.cuda.synchronize()
+        assert torch.equal(u1, ub)
+
+
+def test_exact_rejects_thin_top_layer(lib):
+    N = 128
+    with pytest.raises(lib.CoatbemError) as e:
+        lib.cb_plan_create(N, 1.0, 1.0 / (9 * N), 2.0, 0.3, 1.0, 0.3, 0.0, "fp64", kernel_mode="exact")
+    assert e.value.status == lib.CB_E_UNSUPPORTED
