@@ -13,6 +13,12 @@ Also timed on the same set and tolerance: the FP32 path from the solver's
 own cold start (the overlap at an approach estimated from the profile),
 and the plain FP64 solver (cold start, one solve after another).  Every
 path's pressures are checked against an FP64 solve to residual 1e-10.
+The same set is also solved with exact-kernel plans (the exact coefficients
+of uniformly loaded cells as the convolution's table): FP32 batched from
+the cold start, against FP64 exact plans at 1e-10, and the difference the
+exact coefficients make to the padded point-sampled kernel's solution.
+The uneven batched recipe (N from 128 to 1024, half adhesive) and packed
+small-N convolutions are timed after it.
 
 Measured live: cb_apply_K and its three kernels at N = 1024 (FP32 and
 FP64), graph-replayed with HIP events on the stream they run on; the
@@ -221,6 +227,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-solves", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact-kernel leg")
     ap.add_argument("--cpu-iters", type=int, default=400, help="iteration budget of the oracle's solve")
     ap.add_argument("--c4", type=int, default=256, help="problems of the uneven batched recipe leg (0: skip)")
     ap.add_argument("--dump", default=None, help="write per-problem results (JSON) here")
@@ -405,6 +412,40 @@ def main():
                      "1e-10 (oracle parity of the recipe: tests/test_gpu_batch.py)"}
         del pl64, f4, p4, q4
 
+    # ---- the exact non-periodic kernel: the same set, FP32 batched, cold -------
+    exact = None
+    if not args.no_exact:
+        t0 = time.perf_counter()
+        plx = [cb.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, "fp32", tune_cache=TUNE_CACHE,
+                                 kernel_mode="exact") for c in cases]
+        build_s = (time.perf_counter() - t0) / n
+        px = [torch.zeros_like(p) for p in ps32]
+        rx, tx = timed(lambda: cb.cb_solve_batch(plx, fs32, targets, [1] * n, px, tol=TOL), 1, 1)
+        del plx
+        plx64 = [cb.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, "fp64", tune_cache=TUNE_CACHE,
+                                   kernel_mode="exact") for c in cases]
+        pxr = [torch.zeros_like(p) for p in ps64]
+        rxr = cb.cb_solve_batch(plx64, fs64, targets, [1] * n, pxr, tol=TOL_REF)
+        torch.cuda.synchronize()
+        del plx64
+        ex_p = max((torch.linalg.norm(a - b) / torch.linalg.norm(b)).item() for a, b in zip(px, pxr))
+        ex_F = max(abs(a["F"] - b["F"]) / b["F"] for a, b in zip(rx, rxr))
+        ex_agr = min(1.0 - ((a > 0) ^ (b > 0)).sum().item() / max(((a > 0) | (b > 0)).sum().item(), 1)
+                     for a, b in zip(px, pxr))
+        # what the exact coefficients change in the solution: FP64 exact against FP64 padded, both at 1e-10
+        ex_vs_pad = [(torch.linalg.norm(a - b) / torch.linalg.norm(b)).item() for a, b in zip(pxr, pref)]
+        ex_d = [abs(a["d"] - b["d"]) / abs(b["d"]) for a, b in zip(rxr, res_r)]
+        exact = {"value": n / tx, "unit": "solves/s", "mean_iters": it(rx),
+                 "table_build_s_per_plan": build_s,
+                 "accuracy_vs_fp64_exact_1e-10": {"max_rel_L2_p": ex_p, "max_rel_F": ex_F,
+                                                  "min_set_agreement": ex_agr},
+                 "exact_vs_padded_fp64": {"median_rel_L2_p": float(np.median(ex_vs_pad)),
+                                          "max_rel_L2_p": max(ex_vs_pad), "max_rel_d": max(ex_d)},
+                 "how": "the same 32 force solves with CB_KERNEL_EXACT plans (exact cell coefficients as the "
+                        "table of the same convolution kernels), FP32 directions, cold start, one "
+                        "cb_solve_batch; table build on the host, outside the timed region"}
+        del px, pxr
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(cases[0], args.cpu_iters)
@@ -438,6 +479,7 @@ def main():
                        "how": "FP64 plans, cold start, one cb_solve_force after another"},
         "speedup_vs_plain_fp64": value / value_p,
         "batched_recipe": c4,
+        "exact_kernel": exact,
         "apply_K_batch_small_N": small_batch,
         "apply_K": {prec: {k: {"ms": round(v["ms"], 5), "GBps": round(v["GBps"], 1)} for k, v in t.items()}
                     for prec, t in timing.items()},
