@@ -326,7 +326,8 @@ int cb_apply_K_batch(int n, const cb_plan* plans, const void* const* p, void* co
  *   N: power of two in [16, 1024] (larger N: CB_E_INVALID).  precision:
  *   CB_FP64 or CB_FP32, the type of table, p and u.  table: device,
  *   (N+1)^2 values T[a][b] = K^(dk sqrt(a^2+b^2)) / M^2, M = 2N, row-major
- *   (cb_transfer_table's table times 1/M^2, converted to the precision).
+ *   (cb_transfer_table's table times 1/M^2, converted to the precision;
+ *   cb_transfer_table_exact's table the same way gives the exact kernel).
  *   p, u: device N*N; u must not alias p; all three 16-byte aligned.
  *   stream: hipStream_t (NULL: the null stream); asynchronous.  Every call
  *   on one device shares that device's intermediate: calls that overlap

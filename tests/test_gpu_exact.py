@@ -8,7 +8,8 @@ of coefficients agree to 1e-12); at N = 1024 the response to unit pressure
 on one cell, at sampled cells, against the oracle's coefficients computed
 one by one (FP64 1e-10 relative); a loaded block of a homogeneous half-space
 against Love's formula (1e-12); solves FP64 pressure 1e-8 with identical
-contact sets, FP32 1e-4 and >= 0.999.
+contact sets, FP32 1e-4 and >= 0.999; an adhesive sweep step by step as the
+library's padded sweep test.
 """
 import numpy as np
 import pytest
@@ -163,6 +164,39 @@ def test_exact_adhesive_solve(lib):
     e_p = np.linalg.norm(p.cpu().numpy() - st.p) / np.linalg.norm(st.p)
     print(f"  rounds {res['rounds']} (oracle {rounds}) e_p {e_p:.2e}")
     assert e_p < 1e-8 and res["rounds"] == rounds and rounds > 1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_exact_adhesive_sweep(lib, prec):
+    """A loading and unloading sweep on an exact plan against the oracle's
+    sweep on the exact operator, step by step (FP64: identical areas, F and
+    U_el to 1e-8 of their spans, identical final set; FP32: 1% + 2 cells,
+    1e-3)."""
+    from oracle.solvers import sweep
+    print(f"exact sweep {prec}", flush=True)
+    N, L = 64, 1.0
+    m = Material(0.05, 1.0, 0.3, 5.0, 0.3)
+    f = inputs.paraboloid(N, L, 1.0)
+    dg = 3e-4
+    steps = list(np.linspace(0, 0.01, 6)[1:]) + list(np.linspace(0.01, -0.01, 9)[1:])
+    out, st = sweep(ExactOperator(N, L, m), f, steps, critical_stress(m, dg, L / N), 1e-12 * L, dg, tol=1e-10)
+    plan = _plan(lib, N, L, m, prec, dgamma=dg)
+    ft = torch.tensor(f, device="cuda")
+    p = torch.zeros_like(ft)
+    mask = torch.zeros(N, N, dtype=torch.uint8, device="cuda")
+    res = lib.cb_sweep(plan, ft, steps, p, mask, tol=1e-10 if prec == "fp64" else 1e-8)
+    Fspan = max(abs(o["F"]) for o in out)
+    Uspan = max(abs(o["U_el"]) for o in out)
+    for o, r in zip(out, res):
+        print(f"  d={o['d']:+.4e} F {r['F']:+.6e} vs {o['F']:+.6e} A {r['area']:.5f} vs {o['area']:.5f}")
+        if prec == "fp64":
+            assert r["area"] == pytest.approx(o["area"], abs=1e-15)
+            assert abs(r["F"] - o["F"]) <= 1e-8 * Fspan and abs(r["U_el"] - o["U_el"]) <= 1e-8 * Uspan
+        else:
+            assert abs(r["area"] - o["area"]) <= 0.01 * max(o["area"], 1e-12) + 2 * (L / N) ** 2
+            assert abs(r["F"] - o["F"]) <= 1e-3 * Fspan
+    if prec == "fp64":
+        assert np.array_equal(mask.cpu().numpy().astype(bool), st.S)
 
 
 def test_exact_batch_apply_equals_single(lib):
