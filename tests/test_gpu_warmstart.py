@@ -21,12 +21,12 @@ Measured and asserted:
     guess, so the solve takes its cold start: the network's guess measured
     slower there);
   - against the uniform start the guess saves iterations (bar: 0.97 of the
-    uniform mean; measured 16.71 -> 13.96 at N = 256, 14.88 -> 13.75 at
+    uniform mean; measured 16.71 -> 13.33 at N = 256, 14.88 -> 13.62 at
     N = 1024), and so does the library's cold start (asserted no worse than
     the uniform start).
   - Not asserted, reported: the cold start needs fewer iterations than the
-    network's guess (measured 12.0 against 14.0 at N = 256, 10.4 against
-    13.8 at N = 1024).  With the inverse-symbol preconditioner the
+    network's guess (measured 12.0 against 13.3 at N = 256, 10.4 against
+    13.6 at N = 1024).  With the inverse-symbol preconditioner the
     iteration converges so fast that a guess saves only log(e0 cold /
     e0 guess) / log(rate) iterations: perturbed exact solutions need 9.0
     iterations at 1% error and 10.2 at 3% against 11.4 from the cold
