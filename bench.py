@@ -11,7 +11,9 @@ through cb_solve_batch, FFT launch shapes from the shipped tune cache.
 
 Also timed on the same set and tolerance: the FP32 path from the solver's
 own cold start (the overlap at an approach estimated from the profile),
-and the plain FP64 solver (cold start, one solve after another).  Every
+the same path from a uniform pressure (the published method's start), and
+the plain FP64 solver (cold start, one solve after another); the
+network's gain against both starts of the method without it is reported.  Every
 path's pressures are checked against an FP64 solve to residual 1e-10.
 The same set is also solved with exact-kernel plans (the exact coefficients
 of uniformly loaded cells as the convolution's table): FP32 batched from
@@ -322,6 +324,15 @@ def main():
     def step_cold32():
         return cb.cb_solve_batch(plans32, fs32, targets, [1] * n, pc32, tol=TOL)
 
+    pu32 = [torch.zeros_like(p) for p in ps32]
+
+    def step_uniform32():
+        # the published method's start: uniform pressure carrying the load
+        # (two-phase iteration, as the solver takes it from that start)
+        for p, c in zip(pu32, cases):
+            p.fill_(c.target / (c.L * c.L))
+        return cb.cb_solve_batch(plans32, fs32, targets, [1] * n, pu32, tol=TOL, init=1, precond=3)
+
     def timed(fn, steps, warmup):
         for _ in range(warmup):
             fn()
@@ -338,6 +349,9 @@ def main():
     # ---- FP32 batched, cold start ----------------------------------------------
     res_c, t_c = timed(step_cold32, args.steps, args.warmup)
     value_c = n * args.steps / t_c
+    # ---- FP32 batched, uniform start ---------------------------------------------
+    res_u, t_u = timed(step_uniform32, args.steps, args.warmup)
+    value_u = n * args.steps / t_u
     # ---- plain FP64: cold start, one solve after another --------------------------
     def step_plain64():
         return [cb.cb_solve_force(pl, f, c.target, p, tol=TOL) for pl, f, p, c in zip(plans64, fs64, ps64, cases)]
@@ -359,6 +373,7 @@ def main():
         return {"max_rel_L2_p": max(ep), "max_rel_F": max(eF), "min_set_agreement": min(agr)}
 
     acc_l, acc_c, acc_p = accuracy(ps32, res_l), accuracy(pc32, res_c), accuracy(ps64, res_p)
+    acc_u = accuracy(pu32, res_u)
     it = lambda res: float(np.mean([r["iters"] for r in res]))  # noqa: E731
 
     timing, roof = apply_roofline(cb, plans32[0], plans64[0], N)
@@ -475,6 +490,12 @@ def main():
         "mean_iters": it(res_l),
         "warmstart_ms_per_step": float(np.median(ws_ms)),
         "fp32_cold_batched": {"value": value_c, "unit": "solves/s", "mean_iters": it(res_c), "accuracy": acc_c},
+        "fp32_uniform_batched": {"value": value_u, "unit": "solves/s", "mean_iters": it(res_u), "accuracy": acc_u,
+                                 "how": "the same path from a uniform pressure (the published method's start), "
+                                        "two-phase iteration"},
+        "warm_start_gain": {"vs_uniform_start": value / value_u - 1.0, "vs_estimated_cold_start": value / value_c - 1.0,
+                            "note": "the network's guess against the two starts of the method without it: "
+                                    "positive = the learned configuration is faster"},
         "plain_fp64": {"value": value_p, "unit": "solves/s", "mean_iters": it(res_p), "accuracy": acc_p,
                        "how": "FP64 plans, cold start, one cb_solve_force after another"},
         "speedup_vs_plain_fp64": value / value_p,
