@@ -199,3 +199,59 @@ def test_fig5_large_alpha_thin_layer(lib, prec):
     assert max(abs(e) for e in err[2:]) < 0.08
     assert Fmin / abs(Fcr) == pytest.approx(-1.0, abs=0.06)
     assert out[-1]["area"] == 0.0
+
+
+def test_fig5_intermediate_alpha_crosses_over(lib):
+    """Fig. 5 at alpha = 0.5, the paper's intermediate case (Sec. 3.1): where
+    the contact radius is small against the layer (a << h) the pull-off
+    curve follows the thick-layer series (Eq. 22-23), at large contact
+    radii it approaches the thin-layer limit (Eq. 17-18).  Paraboloid,
+    layer on a rigid base, dgamma / (E1 h) = 5e-5 as in the paper, D = h/32,
+    N = 512; approach until the thin-layer contact radius is 4 h (40
+    steps), retraction to -3 |d_J| (240 steps).  On the receding branch:
+      - a < h/2: the force within 5% of Eq. 22 (measured 0.9%), while
+        Eq. 17 misses it by more than 20% (measured 29%);
+      - a >= 3 h: within 25% of Eq. 17 (median; measured 15%), while the
+        thick-layer series is off by more than 100% (measured 630%);
+      - the departure from Eq. 17 shrinks as the contact grows (median
+        54% for h <= a < 2 h, 22% for 2 h <= a < 3 h, 15% beyond)."""
+    print("Fig. 5 paraboloid alpha = 0.5, D = h/32, N = 512", flush=True)
+    h, N = 1.0, 512
+    D = h / 32
+    L = N * D
+    E1, nu = 1.0, 0.3
+    E1s = E1 / (1 - nu * nu)
+    Et = an.e_tilde(E1, nu)
+    dg = 5e-5 * E1 * h
+    R = 0.5 * math.sqrt(E1s * h ** 3 / (2 * dg))
+    a0, a1 = an.series_coefficient(0, nu), an.series_coefficient(1, nu)
+    _, _, dJ = an.jkr_pulloff_displacement_control(R, E1s, dg)
+    _, dmax = an.thin_layer_paraboloid(4.0 * h, R, h, Et, dg)
+    plan = lib.cb_plan_create(N, L, h, E1, nu, 1e5 * E1, nu, dg, "fp32")
+    f = torch.tensor(inputs.paraboloid(N, L, R), device="cuda")
+    p = torch.zeros_like(f)
+    m = torch.zeros(N, N, dtype=torch.uint8, device="cuda")
+    steps = np.concatenate([np.linspace(0, dmax, 41)[1:], np.linspace(dmax, -3.0 * abs(dJ), 241)[1:]])
+    out = lib.cb_sweep(plan, f, steps, p, m, tol=1e-8)
+    assert all(o["status"] == 0 for o in out)
+    bands = {"small": [], "1-2": [], "2-3": [], "large": []}
+    for o in out[40:]:
+        if o["area"] <= 0.0 or o["rounds"] < 2:
+            continue
+        a = math.sqrt(o["area"] / math.pi)
+        F22, _ = an.thick_layer_paraboloid(a, R, h, E1s, dg, a0, a1)
+        F17, _ = an.thin_layer_paraboloid(a, R, h, Et, dg)
+        e22, e17 = abs(o["F"] - F22) / abs(o["F"]), abs(o["F"] - F17) / abs(o["F"])
+        key = "small" if a < 0.5 * h else "1-2" if h <= a < 2 * h else "2-3" if 2 * h <= a < 3 * h else \
+            "large" if a >= 3 * h else None
+        if key:
+            bands[key].append((e22, e17))
+    med = {k: (float(np.median([x[0] for x in v])), float(np.median([x[1] for x in v])))
+           for k, v in bands.items() if v}
+    print("  relative force error against Eq. 22 / Eq. 17 (median per band of a/h): " +
+          ", ".join(f"{k} (n={len(bands[k])}) {v[0]:.3f} / {v[1]:.3f}" for k, v in med.items()), flush=True)
+    assert len(bands["small"]) >= 2 and len(bands["large"]) >= 20
+    assert all(e22 <= 0.05 and e17 >= 0.2 for e22, e17 in bands["small"])
+    assert med["large"][1] <= 0.25 and med["large"][0] >= 1.0
+    assert med["1-2"][1] > med["2-3"][1] > med["large"][1]
+    assert out[-1]["area"] == 0.0
