@@ -57,10 +57,10 @@ TOL_REF = 1e-10     # FP64 reference for the accuracy checks
 # WRITE x 1.0); the summary and commands are in profiles/.  Valid while the
 # FFT sources hash to `src` and the plan uses `variant`.
 K2_TRAFFIC = {"kernel": "k2_cols", "N": 1024, "precision": "fp32", "variant": 3,
-              "src": "f2c5753e1c642de6:aac5cf310e1177e5",
-              "fetch_bytes": 6344.2 * 1024 * 2.0, "write_bytes": 8192.0 * 1024,
+              "src": "c01bbc9a8645ea9b:9aa4b23123ca8568",
+              "fetch_bytes": 6340.3 * 1024 * 2.0, "write_bytes": 8192.0 * 1024,
               # SQ_INSTS_VALU per launch (same probe, same conditions)
-              "valu_wave_insts": 3375694.0}
+              "valu_wave_insts": 3142332.0}
 # wave64 VALU instructions the chip issues per second without packed FP32:
 # 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per instruction on a 16-lane SIMD
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4

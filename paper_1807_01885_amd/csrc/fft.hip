@@ -249,6 +249,9 @@ __device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const
   // FP32 scheme or with the table loaded after the forward passes: the
   // registers are wanted by the forward passes).
   constexpr bool kEagerLoads = sizeof(T) == 4;
+  // ... but not at radix-16 last passes (N = 2048, 4096), where the
+  // prefetched row costs an occupancy step (N = 2048: 27.0 against 24.1 us)
+  constexpr bool kPrefetchTable = kEagerLoads && RL <= 8;
   const int kxl = active ? kx : 0;
   const T* trow = Tq + (size_t)kxl * NC;
   T tq[NBL][RL];
@@ -263,7 +266,7 @@ __device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const
     }
   };
   auto tval = [&](int b, int i) -> T {
-    if constexpr (kEagerLoads) {
+    if constexpr (kPrefetchTable) {
       return tq[b][i];
     } else {
       const int ky = t + b * NT2 + i * (L / RL);
@@ -288,7 +291,7 @@ __device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const
                                                      : C{T(0), T(0)};
       }
     }
-    if constexpr (kEagerLoads) load_tq();
+    if constexpr (kPrefetchTable) load_tq();
     TW::compute(tws, tid, NTH);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
@@ -316,12 +319,29 @@ __device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const
 #pragma unroll
       for (int b = 0; b < NB; b++) {
         const int j = t + b * NT2;
-        butterfly<T, L, M, RL, L / RL, 1>(a[b], j, tw);
+        if constexpr (RL <= 8) {
+          // the last forward pass and its conjugate transpose share the
+          // butterfly's twiddles
+          C w[RL];
+          twiddles<T, M, RL, L / RL>(w, j, tw);
 #pragma unroll
-        for (int i = 0; i < RL; i++) a[b][i] = cscale(a[b][i], tval(b, i));
-        dft<T, RL, -1>(a[b]);
+          for (int i = 1; i < RL; i++) a[b][i] = cmul(a[b][i], w[i]);
+          dft<T, RL, 1>(a[b]);
 #pragma unroll
-        for (int i = 0; i < RL; i++) line[padi<PS>(out_index<RL, 1>(j, i))] = a[b][i];
+          for (int i = 0; i < RL; i++) a[b][i] = cscale(a[b][i], tval(b, i));
+          dft<T, RL, -1>(a[b]);
+#pragma unroll
+          for (int i = 1; i < RL; i++) a[b][i] = cmul(a[b][i], cconj(w[i]));
+        } else {
+          // radix 16: holding fifteen twiddles across the multiply costs an
+          // occupancy step (N = 2048: FP64 K2 48.7 -> 74.7 us); form them twice
+          butterfly<T, L, M, RL, L / RL, 1>(a[b], j, tw);
+#pragma unroll
+          for (int i = 0; i < RL; i++) a[b][i] = cscale(a[b][i], tval(b, i));
+          butterfly_t<T, M, RL, L / RL>(a[b], j, tw);
+        }
+#pragma unroll
+        for (int i = 0; i < RL; i++) line[padi<PS>(j + i * (L / RL))] = a[b][i];
       }
     } else {
       // the tile holding the packed column (block-uniform branch).  With
@@ -333,7 +353,7 @@ __device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const
       // butterfly; FP64 reads it where it multiplies.
       const T* tn = Tq + (size_t)(NC - 1) * NC;
       T tnv[NB][RL];
-      if constexpr (kEagerLoads) {
+      if constexpr (kPrefetchTable) {
 #pragma unroll
         for (int b = 0; b < NB; b++) {
 #pragma unroll
@@ -357,7 +377,7 @@ __device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const
 #pragma unroll
         for (int i = 0; i < RL; i++) {
           const int ky = j + i * (L / RL);
-          if constexpr (kEagerLoads) {
+          if constexpr (kPrefetchTable) {
             const C zr = cconj(line[padi<PS>((L - ky) & (L - 1))]);
             const T t0 = tq[b][i], t1 = tnv[b][i];
             const C pk = cadd(cscale(a[b][i], T(0.5) * (t0 + t1)), cscale(zr, T(0.5) * (t0 - t1)));
@@ -379,34 +399,34 @@ __device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const
 #pragma unroll
       for (int b = 0; b < NB; b++) {
         const int j = t + b * NT2;
-        dft<T, RL, -1>(a[b]);
+        butterfly_t<T, M, RL, L / RL>(a[b], j, tw);
 #pragma unroll
-        for (int i = 0; i < RL; i++) line[padi<PS>(out_index<RL, 1>(j, i))] = a[b][i];
+        for (int i = 0; i < RL; i++) line[padi<PS>(j + i * (L / RL))] = a[b][i];
       }
     }
     __syncthreads();
   }
-  // inverse passes: the first (radix RL, stride 1) is done; the greedy
-  // schedule continues from stride RL
-  constexpr int RIL = last_radix_from(L, E, RL);
-  MidPasses<T, L, M, NT2, -1, PS, RL, L / RIL>::run(line, t, tw);
+  // inverse transform: the conjugate transposes of the forward passes in
+  // reverse order (the last one is done above), so that the stride-1 pass,
+  // which has no twiddles, comes last and writes the natural order
+  MidPassesT<T, L, M, NT2, PS, R0, L / RL>::run(line, t, tw);
   {
-    constexpr int NB = L / (RIL * NT2);
-    C a[NB][RIL];
+    constexpr int NB = L / (R0 * NT2);
+    C a[NB][R0];
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = t + b * NT2;
 #pragma unroll
-      for (int i = 0; i < RIL; i++) a[b][i] = line[padi<PS>(j + i * (L / RIL))];
+      for (int i = 0; i < R0; i++) a[b][i] = line[padi<PS>(out_index<R0, 1>(j, i))];
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
       const int j = t + b * NT2;
-      butterfly<T, L, M, RIL, L / RIL, -1, PAD>(a[b], j, tw);  // padded: only rows n < N are kept
+      butterfly_t<T, M, R0, 1, PAD>(a[b], j, tw);  // padded: only rows n < N are formed
       if (active) {
 #pragma unroll
-        for (int i = 0; i < (PAD ? RIL / 2 : RIL); i++) {
-          const int n = j + i * (L / RIL);  // < N
+        for (int i = 0; i < (PAD ? R0 / 2 : R0); i++) {
+          const int n = j + i * (L / R0);  // < N
           S[(size_t)(n / RB) * (NC * RB) + kx * RB + (n % RB)] = a[b][i];
         }
       }

@@ -189,39 +189,46 @@ __host__ __device__ constexpr int last_radix_from(int L, int E, int Ls0) {
 }
 __host__ __device__ constexpr int last_radix(int L, int E) { return last_radix_from(L, E, 1); }
 
+// The R - 1 twiddles w^i, w = exp(-2 pi i k scale / LT), of butterfly j of
+// a Stockham pass at stride Ls > 1 (k = j mod Ls, scale = LT / (Ls R)),
+// into w[1..R-1].  They come from table lookups of w, w^4 and (R = 16) w^8
+// and products of at most two further factors, so that each is within a
+// few roundings of exact while most lookups (two LDS reads, index
+// arithmetic and a product each) are saved.
+template <typename T, int LT, int R, int Ls>
+__device__ __forceinline__ void twiddles(cx<T>* w, int j, const Tw<T, LT>& tw) {
+  const int k = j & (Ls - 1);
+  constexpr int scale = LT / (Ls * R);
+  if constexpr (R <= 4) {
+#pragma unroll
+    for (int i = 1; i < R; i++) w[i] = tw.get(i * k * scale);
+  } else {
+    const int e = k * scale;
+    w[1] = tw.get(e);
+    w[4] = tw.get(4 * e);
+    w[2] = cmul(w[1], w[1]);
+    w[3] = cmul(w[2], w[1]);
+#pragma unroll
+    for (int i = 5; i < 8; i++) w[i] = cmul(w[4], w[i - 4]);
+    if constexpr (R == 16) {
+      w[8] = tw.get(8 * e);
+      w[12] = cmul(w[8], w[4]);
+#pragma unroll
+      for (int i = 9; i < 12; i++) w[i] = cmul(w[8], w[i - 8]);
+#pragma unroll
+      for (int i = 13; i < 16; i++) w[i] = cmul(w[12], w[i - 12]);
+    }
+  }
+}
+
 // Twiddle then DFT of one butterfly of a Stockham pass (stride Ls, radix R,
-// twiddle-table length LT, line length L; j = butterfly index).  The R - 1
-// twiddles w^i, w = exp(-2 pi i k scale / LT), come from table lookups of
-// w, w^4 and (R = 16) w^8 and products of at most two further factors, so
-// that each is within a few roundings of exact while most lookups (two LDS
-// reads, index arithmetic and a product each) are saved.
+// twiddle-table length LT, line length L; j = butterfly index).
 // HALF_OUT: only the lower half of the butterfly's outputs is formed.
 template <typename T, int L, int LT, int R, int Ls, int DIR, bool HALF_OUT = false>
 __device__ __forceinline__ void butterfly(cx<T>* a, int j, const Tw<T, LT>& tw) {
   if constexpr (Ls > 1) {
-    const int k = j & (Ls - 1);
-    constexpr int scale = LT / (Ls * R);
     cx<T> w[R];
-    if constexpr (R <= 4) {
-#pragma unroll
-      for (int i = 1; i < R; i++) w[i] = tw.get(i * k * scale);
-    } else {
-      const int e = k * scale;
-      w[1] = tw.get(e);
-      w[4] = tw.get(4 * e);
-      w[2] = cmul(w[1], w[1]);
-      w[3] = cmul(w[2], w[1]);
-#pragma unroll
-      for (int i = 5; i < 8; i++) w[i] = cmul(w[4], w[i - 4]);
-      if constexpr (R == 16) {
-        w[8] = tw.get(8 * e);
-        w[12] = cmul(w[8], w[4]);
-#pragma unroll
-        for (int i = 9; i < 12; i++) w[i] = cmul(w[8], w[i - 8]);
-#pragma unroll
-        for (int i = 13; i < 16; i++) w[i] = cmul(w[12], w[i - 12]);
-      }
-    }
+    twiddles<T, LT, R, Ls>(w, j, tw);
 #pragma unroll
     for (int i = 1; i < R; i++) {
       if constexpr (DIR < 0) w[i].y = -w[i].y;
@@ -230,6 +237,24 @@ __device__ __forceinline__ void butterfly(cx<T>* a, int j, const Tw<T, LT>& tw) 
   }
   if constexpr (HALF_OUT) dft_half_out<T, R, DIR>(a);
   else dft<T, R, DIR>(a);
+}
+
+// The conjugate transpose of a forward butterfly: inverse DFT, then the
+// conjugated twiddles of the same butterfly.  Taking the forward passes in
+// reverse order this way gives the inverse transform (each forward pass is
+// a permutation, a diagonal of twiddles and DFTs; its conjugate transpose
+// undoes it up to the factor R): the first pass, which has no twiddles,
+// comes last.
+template <typename T, int LT, int R, int Ls, bool HALF_OUT = false>
+__device__ __forceinline__ void butterfly_t(cx<T>* a, int j, const Tw<T, LT>& tw) {
+  if constexpr (HALF_OUT) dft_half_out<T, R, -1>(a);
+  else dft<T, R, -1>(a);
+  if constexpr (Ls > 1) {
+    cx<T> w[R];
+    twiddles<T, LT, R, Ls>(w, j, tw);
+#pragma unroll
+    for (int i = 1; i < (HALF_OUT ? R / 2 : R); i++) a[i] = cmul(a[i], cconj(w[i]));
+  }
 }
 
 template <int R, int Ls>
@@ -260,6 +285,29 @@ __device__ __forceinline__ void lds_pass(cx<T>* buf, int t, const Tw<T, LT>& tw)
   __syncthreads();
 }
 
+// The conjugate transpose of lds_pass at the same stride and radix: reads
+// the forward pass's output positions, writes its input positions.
+template <typename T, int L, int LT, int R, int Ls, int NT, int PS>
+__device__ __forceinline__ void lds_pass_t(cx<T>* buf, int t, const Tw<T, LT>& tw) {
+  constexpr int NB = L / (R * NT);
+  cx<T> a[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    const int j = t + b * NT;
+#pragma unroll
+    for (int i = 0; i < R; i++) a[b][i] = buf[padi<PS>(out_index<R, Ls>(j, i))];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; b++) {
+    const int j = t + b * NT;
+    butterfly_t<T, LT, R, Ls>(a[b], j, tw);
+#pragma unroll
+    for (int i = 0; i < R; i++) buf[padi<PS>(j + i * (L / R))] = a[b][i];
+  }
+  __syncthreads();
+}
+
 // All passes with stride Ls < LsEnd, LDS -> LDS.
 template <typename T, int L, int LT, int NT, int DIR, int PS, int Ls, int LsEnd>
 struct MidPasses {
@@ -268,6 +316,19 @@ struct MidPasses {
       constexpr int R = pick_radix(L, L / NT, Ls);
       lds_pass<T, L, LT, R, Ls, NT, DIR, PS>(buf, t, tw);
       MidPasses<T, L, LT, NT, DIR, PS, Ls * R, LsEnd>::run(buf, t, tw);
+    }
+  }
+};
+
+// The conjugate transposes of the passes MidPasses<..., Ls, LsEnd> runs, in
+// reverse order (the inverse transform's middle passes).
+template <typename T, int L, int LT, int NT, int PS, int Ls, int LsEnd>
+struct MidPassesT {
+  __device__ __forceinline__ static void run(cx<T>* buf, int t, const Tw<T, LT>& tw) {
+    if constexpr (Ls < LsEnd) {
+      constexpr int R = pick_radix(L, L / NT, Ls);
+      MidPassesT<T, L, LT, NT, PS, Ls * R, LsEnd>::run(buf, t, tw);
+      lds_pass_t<T, L, LT, R, Ls, NT, PS>(buf, t, tw);
     }
   }
 };
