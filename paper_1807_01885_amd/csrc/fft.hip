@@ -165,31 +165,44 @@ __device__ __forceinline__ void rows_fwd_body(int bid, const T* __restrict__ p, 
 
   // split into the half spectrum of the length-M real transform:
   // X[k] = (Z[k] + conj Z[L-k])/2 - i/2 W^k (Z[k] - conj Z[L-k]),
-  // W = exp(-2 pi i / M), k in [0, L]; items in tile order (k major, rr minor)
+  // W = exp(-2 pi i / M), k in [0, L].  One item forms the pair k, L - k,
+  // which shares its two inputs and, as W^L = -1 (W^(L-k) = -conj W^k),
+  // its twiddle; items in tile order (k major, rr minor), k in [0, L/2]
   constexpr int ITEMS = G * NC * RB;
+  constexpr int PAIRS = L / 2 + 1;
+  constexpr int PITEMS = G * PAIRS * RB;
   C* out = S + (size_t)bid * ITEMS;
 #pragma unroll
-  for (int it = 0; it < (ITEMS + NTH - 1) / NTH; it++) {
+  for (int it = 0; it < (PITEMS + NTH - 1) / NTH; it++) {
     const int q = tid + it * NTH;
-    if (q < ITEMS) {
-      const int g = q / (NC * RB);
-      const int qq = q - g * (NC * RB);
+    if (q < PITEMS) {
+      const int g = q / (PAIRS * RB);
+      const int qq = q - g * (PAIRS * RB);
       const int k = qq / RB;
       const int rr = qq - k * RB;
       const C* ln = buf + (g * RB + rr) * LP;
+      C* o = out + g * (NC * RB) + rr;
       if (k == 0) {
         // X[0] and X[L] are real: both travel in slot 0 as X[0] + i X[L]
         // (slot L is left unwritten and K2 runs one column fewer)
         const C z0 = ln[padi<PS>(0)];
-        out[q] = C{z0.x + z0.y, z0.x - z0.y};
-      } else if (k < L) {
+        o[0] = C{z0.x + z0.y, z0.x - z0.y};
+      } else {
         const C zk = ln[padi<PS>(k)];
-        const C zn = cconj(ln[padi<PS>(L - k)]);
-        const C e = cscale(cadd(zk, zn), T(0.5));
-        const C o = cscale(csub(zk, zn), T(0.5));  // times -i below
+        const C zm = ln[padi<PS>(L - k)];
         const C w = tw.get(k);
-        const C wo = cmul(w, mul_mi<1>(o));
-        out[q] = cadd(e, wo);
+        {
+          const C zn = cconj(zm);
+          const C e = cscale(cadd(zk, zn), T(0.5));
+          const C od = cscale(csub(zk, zn), T(0.5));  // times -i below
+          o[k * RB] = cadd(e, cmul(w, mul_mi<1>(od)));
+        }
+        if (k != L / 2) {
+          const C zn = cconj(zk);
+          const C e = cscale(cadd(zm, zn), T(0.5));
+          const C od = cscale(csub(zm, zn), T(0.5));
+          o[(L - k) * RB] = cadd(e, cmul(C{-w.x, w.y}, mul_mi<1>(od)));
+        }
       }
     }
   }
@@ -477,7 +490,6 @@ __device__ __forceinline__ void rows_inv_body(int bid, const cx<T>* __restrict__
   const int tid = threadIdx.x;
   const TW tw{tws, tws + TW::NLO};
   constexpr int ITEMS = G * NC * RB;
-  constexpr int NIT = (ITEMS + NTH - 1) / NTH;
   const C* in = S + (size_t)bid * ITEMS;
   // The operands of the EPI sums (the cells this thread writes in the last
   // pass) are loaded first, so that their latency overlaps the transform.
@@ -500,56 +512,54 @@ __device__ __forceinline__ void rows_inv_body(int bid, const cx<T>* __restrict__
       }
     }
   }
+  // Z[k] = (X[k] + conj X[L-k]) + i W^-k (X[k] - conj X[L-k]) for the pair
+  // (k, L - k), read straight from the half spectrum (slot 0 holds
+  // X[0] + i X[L], both real; slot L is unused); as W^L = -1 the pair shares
+  // its twiddle.  Items in tile order (k major, rr minor), k in [0, L/2];
+  // the loads are unconditional (the last items clamped) so that they are
+  // issued together.
+  constexpr int PAIRS = L / 2 + 1;
+  constexpr int PITEMS = G * PAIRS * RB;
+  constexpr int NIP = (PITEMS + NTH - 1) / NTH;
   {
-    C v[NIT];
+    C xa[NIP], xb[NIP];
 #pragma unroll
-    for (int it = 0; it < NIT; it++) {
+    for (int it = 0; it < NIP; it++) {
       const int q = tid + it * NTH;
-      if (q < ITEMS) v[it] = in[q];
+      const int qc = q < PITEMS ? q : PITEMS - 1;
+      const int g = qc / (PAIRS * RB);
+      const int qq = qc - g * (PAIRS * RB);
+      const int k = qq / RB;
+      const int rr = qq - k * RB;
+      const C* src = in + g * (NC * RB) + rr;
+      xa[it] = src[k * RB];
+      xb[it] = src[(L - k) * RB];
     }
     TW::compute(tws, tid, NTH);
+    __syncthreads();
 #pragma unroll
-    for (int it = 0; it < NIT; it++) {
+    for (int it = 0; it < NIP; it++) {
       const int q = tid + it * NTH;
-      if (q < ITEMS) {
-        const int g = q / (NC * RB);
-        const int qq = q - g * (NC * RB);
+      if (q < PITEMS) {
+        const int g = q / (PAIRS * RB);
+        const int qq = q - g * (PAIRS * RB);
         const int k = qq / RB;
         const int rr = qq - k * RB;
         C* ln = buf + (g * RB + rr) * LP;
-        if (k == 0) {
-          // slot 0 holds X[0] + i X[L] (both real); slot L is unused
-          ln[padi<PS>(0)] = C{v[it].x, T(0)};
-          ln[padi<PS>(L)] = C{v[it].y, T(0)};
-        } else if (k < L) {
-          ln[padi<PS>(k)] = v[it];
+        const C xk = k == 0 ? C{xa[it].x, T(0)} : xa[it];
+        const C xn = k == 0 ? C{xa[it].y, T(0)} : xb[it];
+        const C w = cconj(tw.get(k));
+        {
+          const C sm = cadd(xk, cconj(xn));
+          const C dd = csub(xk, cconj(xn));
+          ln[padi<PS>(k)] = cadd(sm, mul_mi<-1>(cmul(w, dd)));
+        }
+        if (k != 0 && k != L / 2) {
+          const C sm = cadd(xn, cconj(xk));
+          const C dd = csub(xn, cconj(xk));
+          ln[padi<PS>(L - k)] = cadd(sm, mul_mi<-1>(cmul(C{-w.x, w.y}, dd)));
         }
       }
-    }
-  }
-  __syncthreads();
-  // Z[k] = (X[k] + conj X[L-k]) + i W^-k (X[k] - conj X[L-k]), pairs (k, L-k)
-  constexpr int PAIRS = L / 2 + 1;
-#pragma unroll
-  for (int it = 0; it < (ROWS * PAIRS + NTH - 1) / NTH; it++) {
-    const int q = tid + it * NTH;
-    if (q >= ROWS * PAIRS) break;
-    const int lr = q / PAIRS;
-    const int k = q - lr * PAIRS;
-    C* ln = buf + lr * LP;
-    const C xk = ln[padi<PS>(k)];
-    const C xn = ln[padi<PS>(L - k)];
-    {
-      const C s = cadd(xk, cconj(xn));
-      const C dd = csub(xk, cconj(xn));
-      const C w = cconj(tw.get(k));
-      ln[padi<PS>(k)] = cadd(s, mul_mi<-1>(cmul(w, dd)));
-    }
-    if (k != 0 && k != L / 2) {
-      const C s = cadd(xn, cconj(xk));
-      const C dd = csub(xn, cconj(xk));
-      const C w = cconj(tw.get(L - k));
-      ln[padi<PS>(L - k)] = cadd(s, mul_mi<-1>(cmul(w, dd)));
     }
   }
   __syncthreads();
