@@ -57,7 +57,7 @@ TOL_REF = 1e-10     # FP64 reference for the accuracy checks
 # WRITE x 1.0); the summary and commands are in profiles/.  Valid while the
 # FFT sources hash to `src` and the plan uses `variant`.
 K2_TRAFFIC = {"kernel": "k2_cols", "N": 1024, "precision": "fp32", "variant": 3,
-              "src": "c01bbc9a8645ea9b:9aa4b23123ca8568",
+              "src": "7f5c8bb32f464928:9aa4b23123ca8568",
               "fetch_bytes": 6340.3 * 1024 * 2.0, "write_bytes": 8192.0 * 1024,
               # SQ_INSTS_VALU per launch (same probe, same conditions)
               "valu_wave_insts": 3142332.0}

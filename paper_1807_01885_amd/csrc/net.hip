@@ -394,11 +394,17 @@ __global__ void k_features(const double* __restrict__ f, int N, int G, double L,
   }
 }
 
-// partial sums of softplus(z) over the G x G head
-__global__ void __launch_bounds__(256) k_qmean(const float* __restrict__ Z16, int G, double* part) {
+// partial sums of softplus(z) over the G x G head; softplus(z) itself is
+// kept in sp (G x G, compact) for the prolongation
+__global__ void __launch_bounds__(256) k_qmean(const float* __restrict__ Z16, int G, double* part,
+                                               float* __restrict__ sp) {
   __shared__ double sh[256];
   double s = 0.0;
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < G * G; e += RP * 256) s += softplusf(Z16[(size_t)e * C]);
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < G * G; e += RP * 256) {
+    const float q = softplusf(Z16[(size_t)e * C]);
+    sp[e] = q;
+    s += q;
+  }
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
@@ -412,13 +418,14 @@ __global__ void __launch_bounds__(256) k_qmean(const float* __restrict__ Z16, in
 // q = softplus(z) / mean(q), set to zero below cut, then bilinear
 // (cell-centred) interpolation to N >= G, or cell averages for N < G.
 // Unit mean before the cut; the solve rescales to the load.
-__device__ __forceinline__ double qcut(const float* Z16, int G, int yy, int xx, double inv_mean, double cut) {
+// (sp = softplus(z), compact, from k_qmean: one evaluation per head pixel)
+__device__ __forceinline__ double qcut(const float* sp, int G, int yy, int xx, double inv_mean, double cut) {
   yy = yy < 0 ? 0 : (yy >= G ? G - 1 : yy);
   xx = xx < 0 ? 0 : (xx >= G ? G - 1 : xx);
-  const double q = softplusf(Z16[((size_t)yy * G + xx) * C]) * inv_mean;
+  const double q = sp[(size_t)yy * G + xx] * inv_mean;
   return q < cut ? 0.0 : q;
 }
-__global__ void k_prolong(const float* __restrict__ Z16, int G, int N, const double* meanp, double cut,
+__global__ void k_prolong(const float* __restrict__ sp, int G, int N, const double* meanp, double cut,
                           double* __restrict__ p) {
   const int tot = N * N;
   __shared__ double im_s;
@@ -432,13 +439,13 @@ __global__ void k_prolong(const float* __restrict__ Z16, int G, int N, const dou
       const double sy = (y + 0.5) * G / N - 0.5, sx = (x + 0.5) * G / N - 0.5;
       const int y0 = (int)floor(sy), x0 = (int)floor(sx);
       const double wy = sy - y0, wx = sx - x0;
-      v = (1 - wy) * ((1 - wx) * qcut(Z16, G, y0, x0, im, cut) + wx * qcut(Z16, G, y0, x0 + 1, im, cut)) +
-          wy * ((1 - wx) * qcut(Z16, G, y0 + 1, x0, im, cut) + wx * qcut(Z16, G, y0 + 1, x0 + 1, im, cut));
+      v = (1 - wy) * ((1 - wx) * qcut(sp, G, y0, x0, im, cut) + wx * qcut(sp, G, y0, x0 + 1, im, cut)) +
+          wy * ((1 - wx) * qcut(sp, G, y0 + 1, x0, im, cut) + wx * qcut(sp, G, y0 + 1, x0 + 1, im, cut));
     } else {
       const int r = G / N;
       double s = 0.0;
       for (int a = 0; a < r; a++)
-        for (int b = 0; b < r; b++) s += qcut(Z16, G, y * r + a, x * r + b, im, cut);
+        for (int b = 0; b < r; b++) s += qcut(sp, G, y * r + a, x * r + b, im, cut);
       v = s / (r * r);
     }
     p[e] = v;
@@ -466,6 +473,7 @@ struct cb_net_s {
   double* lossh = nullptr;
   double* scratch = nullptr;
   float* feat = nullptr;
+  float* sp = nullptr;            // batch x H x W fp32: softplus of the head's channel 0
   std::vector<void*> allocs;
 };
 
@@ -538,6 +546,7 @@ extern "C" int cb_net_create(cb_net* out, int batch, int H, int W, void* stream)
   A((void**)&N->lossv, batch * 8);
   A((void**)&N->scratch, (size_t)2 * batch * RP * 8);
   A((void**)&N->feat, px * C * 4);
+  A((void**)&N->sp, px * 4);
   if (rc == CB_OK && hipHostMalloc((void**)&N->lossh, batch * 8, 0) != hipSuccess) rc = cb_fail(CB_E_NOMEM, "pinned");
   if (rc == CB_OK && (hipMemset(N->m1, 0, NPARAM * 4) != hipSuccess || hipMemset(N->m2, 0, NPARAM * 4) != hipSuccess ||
                       hipMemset(N->prm, 0, NPARAM * 4) != hipSuccess))
@@ -751,8 +760,9 @@ extern "C" int cb_net_warmstart_batch(cb_net N, int n, const cb_plan* plans, con
       continue;
     }
     double* mean = N->scratch + (size_t)(N->batch + i) * RP;
-    hipLaunchKernelGGL(k_qmean, dim3(RP), dim3(256), 0, N->stream, N->head + i * hwc, N->H, mean);
-    hipLaunchKernelGGL(k_prolong, egrid((long long)P->N * P->N), dim3(256), 0, N->stream, N->head + i * hwc, N->H,
+    float* sp = N->sp + (size_t)i * N->H * N->W;
+    hipLaunchKernelGGL(k_qmean, dim3(RP), dim3(256), 0, N->stream, N->head + i * hwc, N->H, mean, sp);
+    hipLaunchKernelGGL(k_prolong, egrid((long long)P->N * P->N), dim3(256), 0, N->stream, (const float*)sp, N->H,
                        P->N, (const double*)mean, cut, p_out[i]);
   }
   CB_HIP(hipGetLastError());
