@@ -1,13 +1,15 @@
-"""Write tests/golden/c2_sweep_h0.1_E10.json: the FP64 oracle's quasi-static
-adhesive sweep (Sec. 2 last paragraph, Eq. 12) of the N = 512 paraboloid
-workload with h = 0.1, E1/E2 = 10 (80 approach steps, 120 retraction
-steps to -2 |d_c|; the recipe of paper_1807_01885_amd/inputs.py).
+"""Write tests/golden/c2_sweep_h<h>_E<E1>.json: the FP64 oracle's
+quasi-static adhesive sweep (Sec. 2 last paragraph, Eq. 12) of one N = 512
+paraboloid workload of config 2 (80 approach steps, 120 retraction steps
+to -2 |d_c|; the recipe of paper_1807_01885_amd/inputs.py), by index into
+inputs.adhesive_sweep_c2() (h in {0.02, 0.1, 0.5} x E1/E2 in {0.1, 10}):
+index 3 is h = 0.1, E1/E2 = 10.
 
 Per step: d, F = D^2 sum p, area D^2 |S|, U_el = 1/2 D^2 sum p u, the
 detach/attach rounds and a hash of the contact set (sha256 of its packed
 bits, 16 hex digits).  Calls only oracle/ and the seeded input recipe,
-which holds no arithmetic of the method.  Offline (tens of minutes):
-    python tests/golden/make_c2_sweep.py
+which holds no arithmetic of the method.  Offline (tens of minutes each):
+    python tests/golden/make_c2_sweep.py [index ...]      (default: 3)
 """
 import hashlib
 import json
@@ -25,17 +27,20 @@ from oracle.solvers import AdhesiveState, adhesive_step  # noqa: E402
 from oracle.transfer import Material, critical_stress  # noqa: E402
 from paper_1807_01885_amd import inputs  # noqa: E402
 
-INDEX = 3
 TOL = 1e-10
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c2_sweep_h0.1_E10.json")
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def out_path(c):
+    return os.path.join(HERE, f"c2_sweep_h{c.h:g}_E{c.E1:g}.json")
 
 
 def mask_hash(S):
     return hashlib.sha256(np.packbits(S.astype(bool)).tobytes()).hexdigest()[:16]
 
 
-def main():
-    c = inputs.adhesive_sweep_c2()[INDEX]
+def write(index):
+    c = inputs.adhesive_sweep_c2()[index]
     steps = c.meta["d_steps"]
     mat = Material(c.h, c.E1, c.nu1, c.E2, c.nu2)
     op = Operator(c.N, c.L, mat)
@@ -53,12 +58,18 @@ def main():
         print(f"step {k:3d} d={d:+.4e} F={rec[-1]['F']:+.6e} area={rec[-1]['area']:.6f} rounds={rounds} "
               f"{time.time() - t0:.0f}s", flush=True)
     out = dict(source="oracle.solvers.adhesive_step (FP64), Sec. 2 last paragraph, Eq. 12",
-               recipe="paper_1807_01885_amd.inputs.adhesive_sweep_c2()[3]", N=c.N, L=c.L, h=c.h, E1=c.E1,
+               recipe=f"paper_1807_01885_amd.inputs.adhesive_sweep_c2()[{index}]", N=c.N, L=c.L, h=c.h, E1=c.E1,
                nu1=c.nu1, E2=c.E2, nu2=c.nu2, dgamma=c.dgamma, sigma_c=sc, attach_tol=atol, tol=TOL,
                mask_hash="sha256 of numpy.packbits(contact set, row-major), first 16 hex digits", steps=rec)
-    with open(OUT, "w") as fh:
+    path = out_path(c)
+    with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
-    print("wrote", OUT)
+    print("wrote", path)
+
+
+def main():
+    for index in [int(a) for a in sys.argv[1:]] or [3]:
+        write(index)
 
 
 if __name__ == "__main__":
