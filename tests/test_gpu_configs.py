@@ -181,22 +181,24 @@ def test_n4096_force_solve_contact_conditions(lib):
     assert rel < 1e-6 and pen < 1e-6
 
 
+@pytest.mark.parametrize("index", [0, 2, 3, 4, 5])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_c2_sweep_against_oracle_golden(lib, prec):
-    """Config 2, sweep h = 0.1, E1/E2 = 10 (N = 512, 200 steps), step by step
-    against the FP64 oracle's sweep stored in tests/golden/ (written by
-    tests/golden/make_c2_sweep.py, which calls only the oracle): FP64
-    identical contact set (hash) and area at every step, F and U_el within
-    1e-8 of their spans; FP32 area within 1% + 2 cells, F and U_el within
-    1e-3 of their spans."""
+def test_c2_sweep_against_oracle_golden(lib, prec, index):
+    """Config 2 (N = 512, 200 steps; h in {0.02, 0.1, 0.5} x E1/E2 in
+    {0.1, 10}), each sweep whose oracle run is stored in tests/golden/
+    (written by tests/golden/make_c2_sweep.py, which calls only the oracle),
+    step by step against it: FP64 identical contact set (hash) and area at
+    every step, F and U_el within 1e-8 of their spans; FP32 area within
+    1% + 2 cells, F and U_el within 1e-3 of their spans."""
     import hashlib
     import json
     import os
-    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c2_sweep_h0.1_E10.json")))
-    c = inputs.adhesive_sweep_c2()[3]
+    c = inputs.adhesive_sweep_c2()[index]
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", f"c2_sweep_h{c.h:g}_E{c.E1:g}.json")))
     steps = c.meta["d_steps"]
     assert len(steps) == len(gold["steps"]) and c.N == gold["N"] and c.dgamma == gold["dgamma"]
-    print(f"C2 sweep against the oracle's golden, {prec}", flush=True)
+    assert c.h == gold["h"] and c.E1 == gold["E1"]
+    print(f"C2 sweep h = {c.h:g}, E1/E2 = {c.E1:g} against the oracle's golden, {prec}", flush=True)
     plan = lib.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, c.dgamma, prec)
     ft = torch.tensor(c.f, dtype=torch.float64, device="cuda")
     p = torch.zeros_like(ft)
