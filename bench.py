@@ -57,10 +57,10 @@ TOL_REF = 1e-10     # FP64 reference for the accuracy checks
 # WRITE x 1.0); the summary and commands are in profiles/.  Valid while the
 # FFT sources hash to `src` and the plan uses `variant`.
 K2_TRAFFIC = {"kernel": "k2_cols", "N": 1024, "precision": "fp32", "variant": 3,
-              "src": "7f5c8bb32f464928:9aa4b23123ca8568",
-              "fetch_bytes": 6340.3 * 1024 * 2.0, "write_bytes": 8192.0 * 1024,
+              "src": "85027b7a9235f86c:3ed6ec38f5a5fd4e",
+              "fetch_bytes": 6334.2 * 1024 * 2.0, "write_bytes": 8192.0 * 1024,
               # SQ_INSTS_VALU per launch (same probe, same conditions)
-              "valu_wave_insts": 3142332.0}
+              "valu_wave_insts": 3019452.0}
 # wave64 VALU instructions the chip issues per second without packed FP32:
 # 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per instruction on a 16-lane SIMD
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4

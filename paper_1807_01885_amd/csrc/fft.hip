@@ -316,7 +316,13 @@ __device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const
     }
     __syncthreads();
   }
-  MidPasses<T, L, M, NT2, 1, PS, R0, L / RL>::run(line, t, tw);
+  // FP32 with a radix <= 8 last pass: each middle pass leaves its twiddles
+  // in registers for its conjugate transpose (at most 32 complex values per
+  // thread)
+  constexpr int NMID = count_passes(L, E, R0, L / RL);
+  constexpr bool kHoldTw = kPrefetchTable && NMID > 0 && NMID * E <= 32;
+  C wh[kHoldTw ? NMID * E : 1];
+  MidPasses<T, L, M, NT2, 1, PS, R0, L / RL, kHoldTw>::run(line, t, tw, wh);
   // last forward pass (stride L/RL) -> multiply -> first inverse pass, in registers
   {
     constexpr int NB = L / (RL * NT2);
@@ -422,7 +428,7 @@ __device__ __forceinline__ void cols_body(int tile, cx<T>* __restrict__ S, const
   // inverse transform: the conjugate transposes of the forward passes in
   // reverse order (the last one is done above), so that the stride-1 pass,
   // which has no twiddles, comes last and writes the natural order
-  MidPassesT<T, L, M, NT2, PS, R0, L / RL>::run(line, t, tw);
+  MidPassesT<T, L, M, NT2, PS, R0, L / RL, kHoldTw>::run(line, t, tw, wh);
   {
     constexpr int NB = L / (R0 * NT2);
     C a[NB][R0];

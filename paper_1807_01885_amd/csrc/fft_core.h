@@ -264,8 +264,10 @@ __device__ __forceinline__ int out_index(int j, int i) {
 }
 
 // One Stockham pass LDS -> LDS for the line at `buf` (NT threads, t).
-template <typename T, int L, int LT, int R, int Ls, int NT, int DIR, int PS>
-__device__ __forceinline__ void lds_pass(cx<T>* buf, int t, const Tw<T, LT>& tw) {
+// HOLD: the butterflies' twiddles are also left in wh[b * R + i] (one row
+// of L / NT per pass) for the pass's conjugate transpose.
+template <typename T, int L, int LT, int R, int Ls, int NT, int DIR, int PS, bool HOLD = false>
+__device__ __forceinline__ void lds_pass(cx<T>* buf, int t, const Tw<T, LT>& tw, cx<T>* wh = nullptr) {
   constexpr int NB = L / (R * NT);
   cx<T> a[NB][R];
 #pragma unroll
@@ -278,7 +280,18 @@ __device__ __forceinline__ void lds_pass(cx<T>* buf, int t, const Tw<T, LT>& tw)
 #pragma unroll
   for (int b = 0; b < NB; b++) {
     const int j = t + b * NT;
-    butterfly<T, L, LT, R, Ls, DIR>(a[b], j, tw);
+    if constexpr (HOLD && Ls > 1) {
+      cx<T> w[R];
+      twiddles<T, LT, R, Ls>(w, j, tw);
+#pragma unroll
+      for (int i = 1; i < R; i++) {
+        wh[b * R + i] = w[i];
+        a[b][i] = cmul(a[b][i], DIR < 0 ? cconj(w[i]) : w[i]);
+      }
+      dft<T, R, DIR>(a[b]);
+    } else {
+      butterfly<T, L, LT, R, Ls, DIR>(a[b], j, tw);
+    }
 #pragma unroll
     for (int i = 0; i < R; i++) buf[padi<PS>(out_index<R, Ls>(j, i))] = a[b][i];
   }
@@ -286,9 +299,10 @@ __device__ __forceinline__ void lds_pass(cx<T>* buf, int t, const Tw<T, LT>& tw)
 }
 
 // The conjugate transpose of lds_pass at the same stride and radix: reads
-// the forward pass's output positions, writes its input positions.
-template <typename T, int L, int LT, int R, int Ls, int NT, int PS>
-__device__ __forceinline__ void lds_pass_t(cx<T>* buf, int t, const Tw<T, LT>& tw) {
+// the forward pass's output positions, writes its input positions.  HOLD:
+// the twiddles are the ones the forward pass (DIR = 1) left in wh.
+template <typename T, int L, int LT, int R, int Ls, int NT, int PS, bool HOLD = false>
+__device__ __forceinline__ void lds_pass_t(cx<T>* buf, int t, const Tw<T, LT>& tw, const cx<T>* wh = nullptr) {
   constexpr int NB = L / (R * NT);
   cx<T> a[NB][R];
 #pragma unroll
@@ -301,34 +315,50 @@ __device__ __forceinline__ void lds_pass_t(cx<T>* buf, int t, const Tw<T, LT>& t
 #pragma unroll
   for (int b = 0; b < NB; b++) {
     const int j = t + b * NT;
-    butterfly_t<T, LT, R, Ls>(a[b], j, tw);
+    if constexpr (HOLD && Ls > 1) {
+      dft<T, R, -1>(a[b]);
+#pragma unroll
+      for (int i = 1; i < R; i++) a[b][i] = cmul(a[b][i], cconj(wh[b * R + i]));
+    } else {
+      butterfly_t<T, LT, R, Ls>(a[b], j, tw);
+    }
 #pragma unroll
     for (int i = 0; i < R; i++) buf[padi<PS>(j + i * (L / R))] = a[b][i];
   }
   __syncthreads();
 }
 
-// All passes with stride Ls < LsEnd, LDS -> LDS.
-template <typename T, int L, int LT, int NT, int DIR, int PS, int Ls, int LsEnd>
+// Number of passes with stride Ls0 <= Ls < LsEnd of a length-L line with E
+// elements per thread.
+__host__ __device__ constexpr int count_passes(int L, int E, int Ls0, int LsEnd) {
+  int n = 0;
+  for (int Ls = Ls0; Ls < LsEnd; Ls *= pick_radix(L, E, Ls)) n++;
+  return n;
+}
+
+// All passes with stride Ls < LsEnd, LDS -> LDS.  HOLD: pass p leaves its
+// twiddles in wh + p * (L / NT) (see lds_pass).
+template <typename T, int L, int LT, int NT, int DIR, int PS, int Ls, int LsEnd, bool HOLD = false>
 struct MidPasses {
-  __device__ __forceinline__ static void run(cx<T>* buf, int t, const Tw<T, LT>& tw) {
+  __device__ __forceinline__ static void run(cx<T>* buf, int t, const Tw<T, LT>& tw, cx<T>* wh = nullptr) {
     if constexpr (Ls < LsEnd) {
       constexpr int R = pick_radix(L, L / NT, Ls);
-      lds_pass<T, L, LT, R, Ls, NT, DIR, PS>(buf, t, tw);
-      MidPasses<T, L, LT, NT, DIR, PS, Ls * R, LsEnd>::run(buf, t, tw);
+      lds_pass<T, L, LT, R, Ls, NT, DIR, PS, HOLD>(buf, t, tw, wh);
+      MidPasses<T, L, LT, NT, DIR, PS, Ls * R, LsEnd, HOLD>::run(buf, t, tw, HOLD ? wh + L / NT : wh);
     }
   }
 };
 
 // The conjugate transposes of the passes MidPasses<..., Ls, LsEnd> runs, in
-// reverse order (the inverse transform's middle passes).
-template <typename T, int L, int LT, int NT, int PS, int Ls, int LsEnd>
+// reverse order (the inverse transform's middle passes); HOLD: with the
+// twiddles MidPasses<..., 1, ..., HOLD> left in wh.
+template <typename T, int L, int LT, int NT, int PS, int Ls, int LsEnd, bool HOLD = false>
 struct MidPassesT {
-  __device__ __forceinline__ static void run(cx<T>* buf, int t, const Tw<T, LT>& tw) {
+  __device__ __forceinline__ static void run(cx<T>* buf, int t, const Tw<T, LT>& tw, const cx<T>* wh = nullptr) {
     if constexpr (Ls < LsEnd) {
       constexpr int R = pick_radix(L, L / NT, Ls);
-      MidPassesT<T, L, LT, NT, PS, Ls * R, LsEnd>::run(buf, t, tw);
-      lds_pass_t<T, L, LT, R, Ls, NT, PS>(buf, t, tw);
+      MidPassesT<T, L, LT, NT, PS, Ls * R, LsEnd, HOLD>::run(buf, t, tw, HOLD ? wh + L / NT : wh);
+      lds_pass_t<T, L, LT, R, Ls, NT, PS, HOLD>(buf, t, tw, wh);
     }
   }
 };
