@@ -255,3 +255,53 @@ def test_fig5_intermediate_alpha_crosses_over(lib):
     assert med["large"][1] <= 0.25 and med["large"][0] >= 1.0
     assert med["1-2"][1] > med["2-3"][1] > med["large"][1]
     assert out[-1]["area"] == 0.0
+
+
+def test_fig5_pulloff_force_moves_between_the_limits(lib):
+    """Fig. 5 across alpha (Eq. 26): the most tensile force of the
+    displacement-controlled cycle moves from JKR's -3/2 pi R dgamma (thick
+    layer, alpha -> 0) to Eq. 19's -2 pi R dgamma (thin layer, alpha ->
+    infinity) as alpha grows.  The paper plots five alphas; the labels of
+    0.1, 0.2, 0.5 and 15 are legible, the fifth is read as 2, and 1 and 5
+    are added.  Paraboloid, layer on a rigid base (E2 = 1e5 E1),
+    dgamma / (E1 h) = 5e-5; cells h/64 (alpha 0.2), h/32 (0.5), h/16 (1, 2),
+    h/8 (5, 15); approach in 40 steps to the thin-layer approach of contact
+    radius 4 h (6 h at alpha 5, twice |d_crit| of Eq. 19 at alpha 15),
+    retraction in 240 steps past the last contact.  With q = F_min / (-2 pi
+    R dgamma) (JKR 0.75, Eq. 19 1): q does not fall as alpha grows (0.01
+    allowed for the grid), q(0.2) lies nearer JKR's value and q(15) within
+    5% of Eq. 19's (measured 0.793, 0.821, 0.908, 0.938, 0.968, 0.976)."""
+    h = 1.0
+    E1, nu = 1.0, 0.3
+    E1s = E1 / (1 - nu * nu)
+    Et = an.e_tilde(E1, nu)
+    dg = 5e-5 * E1 * h
+    qs = []
+    for alpha, cph, N, amax in [(0.2, 64, 512, None), (0.5, 32, 512, 4.0), (1.0, 16, 512, 4.0),
+                                (2.0, 16, 512, 4.0), (5.0, 8, 512, 6.0), (15.0, 8, 256, None)]:
+        D = h / cph
+        L = N * D
+        R = alpha * math.sqrt(E1s * h ** 3 / (2 * dg))
+        _, _, dJ = an.jkr_pulloff_displacement_control(R, E1s, dg)
+        dcr, _, _ = an.thin_layer_paraboloid_critical(R, h, Et, dg)
+        if alpha < 0.5:
+            dmax, dend = 2.0 * abs(dJ), -3.0 * abs(dJ)
+        elif amax is None:
+            dmax, dend = 2.0 * abs(dcr), -3.0 * abs(dcr)
+        else:
+            _, dmax = an.thin_layer_paraboloid(amax * h, R, h, Et, dg)
+            dend = -3.0 * max(abs(dJ), abs(dcr))
+        print(f"alpha {alpha:g}: D = h/{cph}, N = {N}", flush=True)
+        plan = lib.cb_plan_create(N, L, h, E1, nu, 1e5 * E1, nu, dg, "fp32")
+        f = torch.tensor(inputs.paraboloid(N, L, R), device="cuda")
+        p = torch.zeros_like(f)
+        m = torch.zeros(N, N, dtype=torch.uint8, device="cuda")
+        steps = np.concatenate([np.linspace(0, dmax, 41)[1:], np.linspace(dmax, dend, 241)[1:]])
+        out = lib.cb_sweep(plan, f, steps, p, m, tol=1e-8)
+        lib.cb_plan_destroy(plan)
+        assert all(o["status"] == 0 for o in out) and out[-1]["area"] == 0.0
+        qs.append(min(o["F"] for o in out) / (-2.0 * math.pi * R * dg))
+    print("  q = F_min / (-2 pi R dgamma) for alpha 0.2, 0.5, 1, 2, 5, 15: " + ", ".join(f"{q:.4f}" for q in qs),
+          flush=True)
+    assert all(b >= a - 0.01 for a, b in zip(qs, qs[1:]))
+    assert 0.70 <= qs[0] < 0.875 and abs(qs[-1] - 1.0) <= 0.05
