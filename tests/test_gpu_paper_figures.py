@@ -261,9 +261,8 @@ def test_fig5_pulloff_force_moves_between_the_limits(lib):
     """Fig. 5 across alpha (Eq. 26): the most tensile force of the
     displacement-controlled cycle moves from JKR's -3/2 pi R dgamma (thick
     layer, alpha -> 0) to Eq. 19's -2 pi R dgamma (thin layer, alpha ->
-    infinity) as alpha grows.  The paper plots five alphas; the labels of
-    0.1, 0.2, 0.5 and 15 are legible, the fifth is read as 2, and 1 and 5
-    are added.  Paraboloid, layer on a rigid base (E2 = 1e5 E1),
+    infinity) as alpha grows.  The paper plots five alphas and names 0.1,
+    0.2, 0.5 and 15; the fifth is taken as 2, and 1 and 5 are added.  Paraboloid, layer on a rigid base (E2 = 1e5 E1),
     dgamma / (E1 h) = 5e-5; cells h/64 (alpha 0.2), h/32 (0.5), h/16 (1, 2),
     h/8 (5, 15); approach in 40 steps to the thin-layer approach of contact
     radius 4 h (6 h at alpha 5, twice |d_crit| of Eq. 19 at alpha 15),
