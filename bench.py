@@ -27,6 +27,8 @@ FP64), graph-replayed with HIP events on the stream they run on; the
 roofline object uses the dominant kernel's algorithmic bytes per launch
 over its mean duration, and its HBM traffic from the committed
 FETCH_SIZE / WRITE_SIZE counter runs while the kernel source is unchanged.
+The same convolution with the fixed launch shape 1 (no tune cache) is
+timed beside it (apply_K_untuned).
 The CPU baseline times the FP64 oracle's own solve of the first problem
 on the host (its constrained CG from its uniform start, to the same
 residual), end to end.
@@ -148,6 +150,25 @@ def apply_roofline(cb, plan32, plan64, N):
             "bytes_per_launch": t32k[dom]["bytes"], "mean_launch_ms": t32k[dom]["ms"],
             "fft_variant": variant, "valu_issue": issue}
     return timing, roof
+
+
+def untuned_apply_timing(cb, case):
+    """cb_apply_K of the first problem's plans with the fixed launch shape 1
+    (no tune cache), beside the tuned figures of apply_K."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(0)
+    pr = rng.standard_normal((case.N, case.N))
+    out = {"fft_variant": 1}
+    for prec, s in (("fp32", 4), ("fp64", 8)):
+        plan = cb.cb_plan_create(case.N, case.L, case.h, case.E1, case.nu1, case.E2, case.nu2, 0.0, prec,
+                                 fft_variant=1)
+        p = torch.tensor(pr, dtype=torch.float32 if prec == "fp32" else torch.float64, device="cuda")
+        u = torch.empty_like(p)
+        ms = time_apply(cb, plan, p, u)["apply"]
+        cb.cb_plan_destroy(plan)
+        out[prec] = {"ms": round(ms, 5), "GBps": round(alg_bytes(case.N, s)["apply"] / (ms * 1e-3) / 1e9, 1)}
+    return out
 
 
 def batch_apply_timing(cb, inputs, n=64, N=128, replays=20):
@@ -377,6 +398,7 @@ def main():
     it = lambda res: float(np.mean([r["iters"] for r in res]))  # noqa: E731
 
     timing, roof = apply_roofline(cb, plans32[0], plans64[0], N)
+    untuned = untuned_apply_timing(cb, cases[0])
     small_batch = batch_apply_timing(cb, inputs)
 
     if args.dump:
@@ -504,6 +526,7 @@ def main():
         "apply_K_batch_small_N": small_batch,
         "apply_K": {prec: {k: {"ms": round(v["ms"], 5), "GBps": round(v["GBps"], 1)} for k, v in t.items()}
                     for prec, t in timing.items()},
+        "apply_K_untuned": untuned,
     }
     print(json.dumps(line))
 
