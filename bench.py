@@ -231,16 +231,37 @@ def cpu_baseline(case, budget_iters):
     r = solve_pk(op, case.f, case.target, mode="force", tol=TOL, max_iter=budget_iters)
     dt = time.perf_counter() - t0
     per_iter = dt / max(r.iters, 1)
+    # the oracle's convolution alone, with all workers and with one
+    apply_ms = {}
+    for w in (workers, 1):
+        o = op if w == workers else oop.Operator(case.N, case.L, Material(case.h, case.E1, case.nu1, case.E2,
+                                                                           case.nu2), workers=1)
+        ta = time.perf_counter()
+        for _ in range(3):
+            o.apply(case.f)
+        apply_ms[f"workers_{w}"] = round(1e3 * (time.perf_counter() - ta) / 3, 1)
+    host = {"cpu": cpu_model(), "oracle_apply_ms": apply_ms}
     if r.converged:
-        return {"value": 1.0 / dt, "unit": "solves/s", "cores": workers, "kind": "oracle",
+        return {"value": 1.0 / dt, "unit": "solves/s", "cores": workers, "kind": "oracle", **host,
                 "sample": (f"FP64 oracle (numpy/scipy.fft, {workers} workers), one complete solve of the first "
                            f"problem of the N=1024 set to residual {TOL:g}: {r.iters} iterations of its own "
                            f"constrained CG in {dt:.1f} s ({per_iter*1e3:.1f} ms/iteration)")}
-    return {"value": 1.0 / dt, "unit": "solves/s", "cores": workers, "kind": "oracle",
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": workers, "kind": "oracle", **host,
             "sample": (f"FP64 oracle (numpy/scipy.fft, {workers} workers), first problem of the N=1024 set: its own "
                        f"constrained CG (published activation rule, uniform start) had not converged after "
                        f"{r.iters} iterations ({dt:.1f} s, residual {r.resid:.1e}, {per_iter*1e3:.1f} ms/iteration); "
                        f"value = 1 / that time, an upper bound of its solve rate")}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
