@@ -318,13 +318,35 @@ __global__ void k_weights_bf16(const float* __restrict__ prm, u16* __restrict__ 
 // each; the consumer folds the RP partials in a fixed order.
 constexpr int RP = 64;
 
-// partial minima of f over N*N
-__global__ void __launch_bounds__(256) k_fmin(const double* __restrict__ f, int n, double* part) {
+struct Scalars {
+  float s[8];
+};
+
+// The problems of one warm-start launch, by value: problem q of a launch is
+// blockIdx.y; its slot in the net's buffers and partials is base + q.
+constexpr int WS_MAX = 32;
+struct WsProblem {
+  const double* f;   // N x N profile
+  double* p;         // N x N initial pressure (output)
+  float* x;          // G x G x C features (output)
+  int N;
+  int guess;         // 0: the problem gets zeros (the solve takes its cold start)
+  double L;
+  Scalars sc;
+};
+struct WsBatch {
+  WsProblem q[WS_MAX];
+};
+
+// partial minima of f over N*N (RP blocks per problem)
+__global__ void __launch_bounds__(256) k_fmin(WsBatch B, int base, double* scratch) {
   __shared__ double sh[256];
+  const WsProblem& P = B.q[blockIdx.y];
+  double* part = scratch + (size_t)(base + blockIdx.y) * RP;
   // 16-byte loads, four independent minima per thread (n even: N x N, N >= 8)
   double m0 = INFINITY, m1 = INFINITY, m2 = INFINITY, m3 = INFINITY;
-  const double2* f2 = reinterpret_cast<const double2*>(f);
-  const int n2 = n >> 1, stride = RP * 256;
+  const double2* f2 = reinterpret_cast<const double2*>(P.f);
+  const int n2 = (P.N * P.N) >> 1, stride = RP * 256;
   int e = blockIdx.x * 256 + threadIdx.x;
   for (; e + stride < n2; e += 2 * stride) {
     const double2 a = f2[e], b = f2[e + stride];
@@ -358,18 +380,19 @@ __device__ __forceinline__ double fold_sum(const double* part) {
   return s;
 }
 
-struct Scalars {
-  float s[8];
-};
-
 // x[y][x][c] on the G x G net grid from the N x N profile: cell averages
 // (N >= G) or nearest cells (N < G) of the gap g0 = f - min f, as three
 // clipped channels g0/(s L) for s in {0.005, 0.02, 0.08}, then the
 // problem scalars broadcast, remaining channels zero.
-__global__ void k_features(const double* __restrict__ f, int N, int G, double L, const double* fminp, Scalars sc,
-                           float* __restrict__ x) {
-  const int tot = G * G;
-  const double f0 = fold_min(fminp);
+__global__ void k_features(WsBatch B, int base, int G, const double* scratch) {
+  const WsProblem& P = B.q[blockIdx.y];
+  const int N = P.N, tot = G * G;
+  const double L = P.L;
+  const double* __restrict__ f = P.f;
+  __shared__ double f0_s;
+  if (threadIdx.x == 0) f0_s = fold_min(scratch + (size_t)(base + blockIdx.y) * RP);
+  __syncthreads();
+  const double f0 = f0_s;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
     const int y = e / G, xx = e % G;
     double g0;
@@ -383,21 +406,27 @@ __global__ void k_features(const double* __restrict__ f, int N, int G, double L,
       const int r = G / N;
       g0 = f[(size_t)(y / r) * N + xx / r] - f0;
     }
-    float* o = x + (size_t)e * C;
+    float* o = P.x + (size_t)e * C;
     o[0] = (float)fmin(g0 / (0.005 * L), 1.0);
     o[1] = (float)fmin(g0 / (0.02 * L), 1.0);
     o[2] = (float)fmin(g0 / (0.08 * L), 1.0);
 #pragma unroll
-    for (int c = 0; c < 8; c++) o[3 + c] = sc.s[c];
+    for (int c = 0; c < 8; c++) o[3 + c] = P.sc.s[c];
 #pragma unroll
     for (int c = 11; c < C; c++) o[c] = 0.f;
   }
 }
 
-// partial sums of softplus(z) over the G x G head; softplus(z) itself is
-// kept in sp (G x G, compact) for the prolongation
-__global__ void __launch_bounds__(256) k_qmean(const float* __restrict__ Z16, int G, double* part,
-                                               float* __restrict__ sp) {
+// partial sums of softplus(z) over the G x G head of each problem that
+// gets a guess; softplus(z) itself is kept in sp (G x G, compact) for the
+// prolongation
+__global__ void __launch_bounds__(256) k_qmean(WsBatch B, int base, const float* __restrict__ head, int G,
+                                               double* scratch_mean, float* __restrict__ sp_all) {
+  if (!B.q[blockIdx.y].guess) return;
+  const int i = base + blockIdx.y;
+  const float* Z16 = head + (size_t)i * G * G * C;
+  float* sp = sp_all + (size_t)i * G * G;
+  double* part = scratch_mean + (size_t)i * RP;
   __shared__ double sh[256];
   double s = 0.0;
   for (int e = blockIdx.x * 256 + threadIdx.x; e < G * G; e += RP * 256) {
@@ -417,7 +446,8 @@ __global__ void __launch_bounds__(256) k_qmean(const float* __restrict__ Z16, in
 // p[N x N] from the head output z (channel 0 of a G x G x 16 FP32 tensor):
 // q = softplus(z) / mean(q), set to zero below cut, then bilinear
 // (cell-centred) interpolation to N >= G, or cell averages for N < G.
-// Unit mean before the cut; the solve rescales to the load.
+// Unit mean before the cut; the solve rescales to the load.  A problem
+// without a guess gets zeros.
 // (sp = softplus(z), compact, from k_qmean: one evaluation per head pixel)
 __device__ __forceinline__ double qcut(const float* sp, int G, int yy, int xx, double inv_mean, double cut) {
   yy = yy < 0 ? 0 : (yy >= G ? G - 1 : yy);
@@ -425,11 +455,19 @@ __device__ __forceinline__ double qcut(const float* sp, int G, int yy, int xx, d
   const double q = sp[(size_t)yy * G + xx] * inv_mean;
   return q < cut ? 0.0 : q;
 }
-__global__ void k_prolong(const float* __restrict__ sp, int G, int N, const double* meanp, double cut,
-                          double* __restrict__ p) {
-  const int tot = N * N;
+__global__ void k_prolong(WsBatch B, int base, const float* __restrict__ sp_all, int G,
+                          const double* scratch_mean, double cut) {
+  const WsProblem& P = B.q[blockIdx.y];
+  const int N = P.N, tot = N * N;
+  double* __restrict__ p = P.p;
+  if (!P.guess) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) p[e] = 0.0;
+    return;
+  }
+  const int i = base + blockIdx.y;
+  const float* sp = sp_all + (size_t)i * G * G;
   __shared__ double im_s;
-  if (threadIdx.x == 0) im_s = ((double)G * G) / fold_sum(meanp);
+  if (threadIdx.x == 0) im_s = ((double)G * G) / fold_sum(scratch_mean + (size_t)i * RP);
   __syncthreads();
   const double im = im_s;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
@@ -702,37 +740,44 @@ extern "C" int cb_net_adam_step(cb_net N, float lr) {
   return CB_OK;
 }
 
-__global__ void k_fill0(double* __restrict__ p, long long n) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-    p[i] = 0.0;
-}
-
-// features of one problem into x, its min f kept in scratch[slot]
-static int features_into(cb_net N, const double* f, int Nf, double L, double h, double E1, double nu1, double E2,
-                         double nu2, double F, float* x, int slot) {
+// One problem of a warm-start launch: argument checks and the scalars of
+// its features (f: N x N profile, x: its G x G x C feature block).
+static int ws_problem(cb_net N, const double* f, int Nf, double L, double h, double E1, double nu1, double E2,
+                      double nu2, double F, float* x, WsProblem* q) {
   if (!N || !f || !x) return cb_fail(CB_E_INVALID, "null argument");
   if (!cb::aligned16(f)) return cb_fail(CB_E_INVALID, "f must be 16-byte aligned");
   if (N->H != N->W) return cb_fail(CB_E_INVALID, "square net grid required");
   const int G = N->H;
   if (Nf < 8 || (Nf % G != 0 && G % Nf != 0)) return cb_fail(CB_E_INVALID, "N must divide or be a multiple of the net grid");
   const double E2s = E2 / (1.0 - nu2 * nu2);
-  Scalars sc{};
-  sc.s[0] = (float)(std::log10(std::max(h, 1e-12) / L) / 3.0);
-  sc.s[1] = (float)(std::log10(E1 / E2) / 2.0);
-  sc.s[2] = (float)(2.0 * nu1);
-  sc.s[3] = (float)(2.0 * nu2);
-  sc.s[4] = (float)(std::log10(std::max(F, 1e-300) / (E2s * L * L)) / 4.0);
-  sc.s[5] = 1.f;
-  hipLaunchKernelGGL(k_fmin, dim3(RP), dim3(256), 0, N->stream, f, Nf * Nf, N->scratch + (size_t)slot * RP);
-  hipLaunchKernelGGL(k_features, egrid((long long)G * G), dim3(256), 0, N->stream, f, Nf, G, L,
-                     (const double*)(N->scratch + (size_t)slot * RP), sc, x);
-  CB_HIP(hipGetLastError());
+  *q = WsProblem{};
+  q->f = f;
+  q->x = x;
+  q->N = Nf;
+  q->L = L;
+  q->sc.s[0] = (float)(std::log10(std::max(h, 1e-12) / L) / 3.0);
+  q->sc.s[1] = (float)(std::log10(E1 / E2) / 2.0);
+  q->sc.s[2] = (float)(2.0 * nu1);
+  q->sc.s[3] = (float)(2.0 * nu2);
+  q->sc.s[4] = (float)(std::log10(std::max(F, 1e-300) / (E2s * L * L)) / 4.0);
+  q->sc.s[5] = 1.f;
   return CB_OK;
+}
+
+// features of the nq problems of B (slots base ..): min f, then the features
+static void ws_features(cb_net N, const WsBatch& B, int base, int nq) {
+  hipLaunchKernelGGL(k_fmin, dim3(RP, nq), dim3(256), 0, N->stream, B, base, N->scratch);
+  hipLaunchKernelGGL(k_features, dim3(egrid((long long)N->H * N->H).x, nq), dim3(256), 0, N->stream, B, base, N->H,
+                     (const double*)N->scratch);
 }
 
 extern "C" int cb_net_features(cb_net N, const double* f, int Nf, double L, double h, double E1, double nu1, double E2,
                                double nu2, double F, float* x) {
-  return features_into(N, f, Nf, L, h, E1, nu1, E2, nu2, F, x, 0);
+  WsBatch B{};
+  if (int rc = ws_problem(N, f, Nf, L, h, E1, nu1, E2, nu2, F, x, &B.q[0])) return rc;
+  ws_features(N, B, 0, 1);
+  CB_HIP(hipGetLastError());
+  return CB_OK;
 }
 
 extern "C" int cb_net_warmstart_batch(cb_net N, int n, const cb_plan* plans, const double* const* f,
@@ -741,29 +786,32 @@ extern "C" int cb_net_warmstart_batch(cb_net N, int n, const cb_plan* plans, con
   if (n < 1 || n > N->batch) return cb_fail(CB_E_INVALID, "batch size out of range");
   if (!(cut >= 0.0)) return cb_fail(CB_E_INVALID, "cut must be >= 0");
   const size_t hwc = (size_t)N->H * N->W * C;
+  // problems in launches of up to WS_MAX (problem index in the batch = base + q)
+  std::vector<WsBatch> groups((n + WS_MAX - 1) / WS_MAX);
+  int maxN = 0;
   for (int i = 0; i < n; i++) {
     const cb_plan P = plans[i];
     if (!P || !f[i] || !p_out[i]) return cb_fail(CB_E_INVALID, "null plan or array in the batch");
-    if (int rc = features_into(N, f[i], P->N, P->L, P->h, P->E1, P->nu1, P->E2, P->nu2, F_host[i], N->feat + i * hwc,
-                               i))
+    WsProblem& q = groups[i / WS_MAX].q[i % WS_MAX];
+    if (int rc = ws_problem(N, f[i], P->N, P->L, P->h, P->E1, P->nu1, P->E2, P->nu2, F_host[i], N->feat + i * hwc, &q))
       return rc;
+    q.p = p_out[i];
+    // stiff thin coating: no guess (zeros; the solve then takes its cold
+    // start): the network's guess measured slower than a cold start there.
+    // Layered stacks and periodic plans lie outside its training data.
+    q.guess = !(P->precond_auto == 1 || P->layered || P->kernel_mode != CB_KERNEL_PADDED);
+    maxN = std::max(maxN, P->N);
   }
+  for (size_t g = 0; g < groups.size(); g++)
+    ws_features(N, groups[g], (int)g * WS_MAX, std::min(WS_MAX, n - (int)g * WS_MAX));
   if (int rc = cb_net_forward(N, n, N->feat, nullptr)) return rc;
-  for (int i = 0; i < n; i++) {
-    const cb_plan P = plans[i];
-    if (P->precond_auto == 1 || P->layered || P->kernel_mode != CB_KERNEL_PADDED) {
-      // stiff thin coating: no guess (zeros; the solve then takes its cold
-      // start): the network's guess measured slower than a cold start there.
-      // Layered stacks and periodic plans lie outside its training data.
-      hipLaunchKernelGGL(k_fill0, egrid((long long)P->N * P->N), dim3(256), 0, N->stream, p_out[i],
-                         (long long)P->N * P->N);
-      continue;
-    }
-    double* mean = N->scratch + (size_t)(N->batch + i) * RP;
-    float* sp = N->sp + (size_t)i * N->H * N->W;
-    hipLaunchKernelGGL(k_qmean, dim3(RP), dim3(256), 0, N->stream, N->head + i * hwc, N->H, mean, sp);
-    hipLaunchKernelGGL(k_prolong, egrid((long long)P->N * P->N), dim3(256), 0, N->stream, (const float*)sp, N->H,
-                       P->N, (const double*)mean, cut, p_out[i]);
+  double* mean = N->scratch + (size_t)N->batch * RP;
+  for (size_t g = 0; g < groups.size(); g++) {
+    const int base = (int)g * WS_MAX, nq = std::min(WS_MAX, n - base);
+    hipLaunchKernelGGL(k_qmean, dim3(RP, nq), dim3(256), 0, N->stream, groups[g], base, (const float*)N->head, N->H,
+                       mean, N->sp);
+    hipLaunchKernelGGL(k_prolong, dim3(egrid((long long)maxN * maxN).x, nq), dim3(256), 0, N->stream, groups[g], base,
+                       (const float*)N->sp, N->H, (const double*)mean, cut);
   }
   CB_HIP(hipGetLastError());
   CB_HIP(hipStreamSynchronize(N->stream));
