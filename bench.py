@@ -283,6 +283,8 @@ def main():
     ap.add_argument("--profile-solves", action="store_true",
                     help="only the FP32 solves of the set, cold then from the learned guess, one after another "
                          "on one host thread (for rocprofv3 --kernel-trace --stats)")
+    ap.add_argument("--profile-warmstart", action="store_true",
+                    help="only the batched warm start of the set, eight times (for rocprofv3 --kernel-trace --stats)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -329,6 +331,20 @@ def main():
             print(f"solve {len(its)}/{n}: iterations cold {cold} warm {warm}", flush=True)
         print(json.dumps({"profile_solves": "done", "mean_iters_cold": float(np.mean([a for a, _ in its])),
                           "mean_iters_warm": float(np.mean([b for _, b in its]))}))
+        return
+    if args.profile_warmstart:
+        plans = [cb.cb_plan_create(c.N, c.L, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, "fp32", tune_cache=TUNE_CACHE)
+                 for c in cases]
+        fs = [torch.tensor(c.f, dtype=torch.float64, device="cuda") for c in cases]
+        ps = [torch.zeros_like(f) for f in fs]
+        ws = WarmStart(batch=n)
+        ms = []
+        for _ in range(8):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ws.batch(plans, fs, [c.target for c in cases], ps)
+            ms.append(1e3 * (time.perf_counter() - t0))
+        print(json.dumps({"profile_warmstart": "done", "problems": n, "host_ms_per_call": ms}))
         return
     if args.roofline_only:
         c = cases[0]
