@@ -273,3 +273,37 @@ def test_warmstart_batch_equals_single(lib):
         assert torch.equal(a, b)
     with pytest.raises(lib.CoatbemError):
         lib.cb_net_warmstart_batch(net1, plans, fs, Fs, outs, cut=0.1)   # n > batch
+
+
+def test_warmstart_batch_more_than_one_launch(lib):
+    """The warm start takes its problems in launches of up to 32: a batch of
+    35 (two launches, sizes 64 to 256 on a 64 x 64 net grid, every fifth a
+    stiff thin coating, which gets zeros) equals one call per problem bit
+    for bit."""
+    params = _params(9)
+    L = 1.0
+    specs = []
+    for i in range(35):
+        N = (64, 128, 256)[i % 3]
+        stiff = i % 5 == 0
+        specs.append((N, 0.02 if stiff else 0.1 + 0.01 * i, 40.0 if stiff else 0.5, 1e-3 * (1 + i % 4), stiff))
+    net1 = _net(lib, params, 1, 64, 64)
+    netb = _net(lib, params, len(specs), 64, 64)
+    plans, fs, Fs, single = [], [], [], []
+    for i, (N, h, E1, F, stiff) in enumerate(specs):
+        plan = lib.cb_plan_create(N, L, h, E1, 0.3, 1.0, 0.3, 0.0, "fp32")
+        prof = inputs.paraboloid(N, L, 1.0 + 0.1 * i) if i % 2 else inputs.cone(N, L, 0.05 + 0.002 * i)
+        f = torch.tensor(prof, dtype=torch.float64, device="cuda")
+        p = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        lib.cb_net_warmstart(net1, plan, f, F, p, cut=0.1)
+        plans.append(plan), fs.append(f), Fs.append(F), single.append(p)
+    outs = [torch.full_like(p, -1.0) for p in single]
+    lib.cb_net_warmstart_batch(netb, plans, fs, Fs, outs, cut=0.1)
+    for (N, h, E1, F, stiff), a, b in zip(specs, outs, single):
+        assert torch.equal(a, b)
+        if stiff:
+            assert not torch.any(a != 0.0)
+        else:
+            assert float(a.sum()) > 0.0
+    for pl in plans:
+        lib.cb_plan_destroy(pl)
