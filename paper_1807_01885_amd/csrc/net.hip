@@ -64,22 +64,34 @@ k_conv(const u16* __restrict__ X, const u16* __restrict__ Wt, const float* __res
 #pragma unroll
   for (int tap = 0; tap < 9; tap++)
     b[tap] = *reinterpret_cast<const s4*>(Wt + (tap * C + i) * C + 4 * kg);
+  // the epilogue's operands (bias, skip) are loaded with the others
+  const int co = i;
+  const float bb = bias ? bias[co] : 0.f;
+  // (unconditional: without a skip the input, of the same shape, is read
+  // and its value dropped, so that no branch ends in a wait)
+  const u16* sks = skip ? skip : X;
+  float sk[4];
+#pragma unroll
+  for (int j = 0; j < 4; j++) sk[j] = bf2f(sks[(size_t)(tile * 16 + 4 * kg + j) * C + co]);
   f4 acc = {0.f, 0.f, 0.f, 0.f};
   const int q = tile * 16 + i;
+  // the nine taps' loads are unconditional (a tap outside the image reads
+  // the pixel itself and is zeroed after the load), so that they go out
+  // together instead of one round trip per tap behind a branch
+  s4 a[9];
 #pragma unroll
   for (int tap = 0; tap < 9; tap++) {
     const int qs = shifted(q, tap, H, W);
-    s4 a = {0, 0, 0, 0};
-    if (qs >= 0) a = *reinterpret_cast<const s4*>(X + (size_t)qs * C + 4 * kg);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[tap], acc, 0, 0, 0);
+    a[tap] = *reinterpret_cast<const s4*>(X + (size_t)(qs >= 0 ? qs : q) * C + 4 * kg);
+    if (qs < 0) a[tap] = s4{0, 0, 0, 0};
   }
-  const int co = i;
-  const float bb = bias ? bias[co] : 0.f;
+#pragma unroll
+  for (int tap = 0; tap < 9; tap++) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[tap], b[tap], acc, 0, 0, 0);
 #pragma unroll
   for (int j = 0; j < 4; j++) {
     const int qo = tile * 16 + 4 * kg + j;
     float v = acc[j] + bb;
-    if (skip) v += bf2f(skip[(size_t)qo * C + co]);
+    if (skip) v += sk[j];
     if (RELU) v = v > 0.f ? v : 0.f;
     if (Yb) Yb[(size_t)qo * C + co] = f2bf(v);
     if (Yf) Yf[(size_t)qo * C + co] = v;
