@@ -330,3 +330,35 @@ def test_adhesive_status_matches_residual(lib, prec):
         else:
             assert rc in (lib.CB_OK, lib.CB_E_NOCONV)
             assert (rc == lib.CB_OK) == (res["resid"] <= tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_degenerate_loads(lib, prec):
+    """The solutions the method fixes without iterating: zero force, and
+    approaches at or below the profile's lowest point (touching or apart).
+    Each gives p = 0 everywhere, zero force and area, status OK, whatever
+    the state left in p and the mask; the smallest grid (N = 16) then
+    solves a loaded indent to the oracle's pressure."""
+    c = inputs.paraboloid_c1()
+    plan = lib.cb_plan_create(16, 4.0, c.h, c.E1, c.nu1, c.E2, c.nu2, 0.0, prec)
+    f = inputs.paraboloid(16, 4.0, 1.0)
+    ft = torch.tensor(f, dtype=torch.float64, device="cuda")
+    p = torch.full((16, 16), 3.0, dtype=torch.float64, device="cuda")
+    mask = torch.ones(16, 16, dtype=torch.uint8, device="cuda")
+    for kind, target in [("force", 0.0), ("indent", float(f.min())), ("indent", float(f.min()) - 1e-3)]:
+        p.fill_(3.0)
+        mask.fill_(1)
+        r = (lib.cb_solve_force if kind == "force" else lib.cb_solve_indent)(plan, ft, target, p, mask, tol=1e-10)
+        assert r["status"] == 0 and r["F"] == 0.0 and r["area"] == 0.0, (kind, target, r)
+        assert not torch.any(p != 0.0) and not torch.any(mask != 0)
+    # a loaded indent on the smallest grid against the oracle
+    d = 0.1
+    r = lib.cb_solve_indent(plan, ft, d, p, mask, tol=1e-10 if prec == "fp64" else 1e-8)
+    op = Operator(16, 4.0, Material(c.h, c.E1, c.nu1, c.E2, c.nu2))
+    ref = solve_pk(op, f, d, mode="disp", tol=1e-10)
+    pg = p.cpu().numpy()
+    err = np.linalg.norm(pg - ref.p) / np.linalg.norm(ref.p)
+    print(f"  N=16 indent d={d}: rel L2 p {err:.2e}, set agreement {agreement(pg > 0, ref.p > 0):.4f}", flush=True)
+    assert r["status"] == 0
+    assert err <= (1e-8 if prec == "fp64" else 1e-4)
+    assert agreement(pg > 0, ref.p > 0) >= (1.0 if prec == "fp64" else 0.999)
